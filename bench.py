@@ -1,0 +1,178 @@
+#!/usr/bin/env python3
+"""Throughput of the ESP reciprocal-space path (energy + forces + virial).
+
+One step = one esp_forces call (cell sort, spreading, forward FFT, scaling and
+reduction, potential, inverse FFT, gather, finalisation) for all N particles
+of the workload, inputs already resident in device memory.
+
+Workload (default): bulk-water-shaped system, 10,000 rigid 3-site triplets in
+a cubic 6.7 nm cell (N = 30,000), tolerance 1e-5, seeded synthetic input.
+The headline value is the FP32 path; the plain FP64 path (analytic
+parameters) is timed beside it on the same input.
+
+Prints ONE JSON line.  See DESIGN.md for the byte model behind "roofline".
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per launch (per particle / per grid point) of each stage;
+# r = bytes of a real, N particles, G = M1 M2 M3 grid points, S = complex
+# half-spectrum entries (M1/2+1) M2 M3.
+def stage_bytes(stage, N, G, S, r):
+    rec = 16 if r == 4 else 32                     # sorted particle record
+    c = 2 * r
+    return {
+        "bin": N * (4 * r + rec + 8),               # xyz, q in; record, key, rank out
+        "scan": 0,
+        "scatter": N * (rec + 8 + rec + 4),         # record, key, rank in; record, perm out
+        "spread": N * rec + G * r,                  # sorted records in, grid out
+        "fft_xy": G * r + S * c,                    # real grid in, half spectrum out
+        "fft_z": 2 * S * c,                         # spectrum in and out
+        "fft_xy_inv": S * c + G * r,
+        "gather": N * (rec + 4 + 3 * r) + G * r,    # records, perm in; forces out; phi in
+        "finalize": 0,
+    }[stage]
+
+
+def run_plan(plan, xyz, q, steps, warmup, torch):
+    f, out7 = plan.forces(xyz, q)
+    for _ in range(warmup):
+        plan.forces(xyz, q, f=f, out7=out7)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.forces(xyz, q, f=f, out7=out7)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    plan.check()
+    return dt, f, out7
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--tol", type=float, default=1e-5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU decomposition is described in DESIGN.md but not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from oracle import esp_grid
+    from paper_2601_00161_amd import synth
+    from paper_2601_00161_amd.esp import Plan
+
+    dev = torch.device("cuda:0")
+    h, r, q = synth.config2(args.seed)
+    N = len(q)
+    r32, q32 = r.astype(np.float32), q.astype(np.float32)
+
+    # ---- FP32 headline path ---------------------------------------------------
+    p32 = Plan(h, N, args.tol, precision="fp32")
+    x32, c32 = torch.from_numpy(r32).to(dev), torch.from_numpy(q32).to(dev)
+    # pre-pass: every stage timed once per step to find the dominant kernel
+    p32.profile(["bin", "scan", "scatter", "spread", "fft_xy", "fft_z", "fft_xy_inv", "gather", "finalize"], 64)
+    for _ in range(32):
+        p32.forces(x32, c32)
+    stages = p32.profile_read()
+    dominant = max(stages, key=lambda s: stages[s][0] / stages[s][1])
+    # timed region, with events around the dominant kernel only
+    p32.profile([dominant], args.steps + args.warmup + 2)
+    dt32, f32, o32 = run_plan(p32, x32, c32, args.steps, args.warmup, torch)
+    dom_ms, dom_n = p32.profile_read()[dominant]
+    p32.profile([], 0)
+
+    # ---- plain FP64 path ----------------------------------------------------------
+    p64 = Plan(h, N, args.tol, precision="fp64")
+    x64, c64 = torch.from_numpy(r32.astype(np.float64)).to(dev), torch.from_numpy(q32.astype(np.float64)).to(dev)
+    dt64, f64, o64 = run_plan(p64, x64, c64, args.steps, args.warmup, torch)
+
+    # ---- parity of both against the oracle at identical parameters -----------------
+    def parity(plan, f, o):
+        prm = plan.params
+        ref = esp_grid.esp_grid(h, r32.astype(np.float64), q32.astype(np.float64),
+                                esp_grid.GridParams(prm["c_split"], prm["c_spread"], prm["P"],
+                                                    tuple(prm["M"]), prm["rc"]))
+        f = f.cpu().numpy().astype(np.float64)
+        o = o.cpu().numpy()
+        W = ref.virial
+        w6 = np.array([W[0, 0], W[1, 1], W[2, 2], W[0, 1], W[0, 2], W[1, 2]])
+        return {"energy": float(abs(o[0] - ref.energy) / abs(ref.energy)),
+                "virial": float(np.linalg.norm(o[1:] - w6) / np.linalg.norm(w6)),
+                "forces_rms": float(np.sqrt(np.sum((f - ref.forces) ** 2) / np.sum(ref.forces ** 2)))}
+
+    par32 = parity(p32, f32, o32)
+    par64 = parity(p64, f64, o64)
+
+    # ---- CPU baseline: the oracle's gridded ESP (FP64) on the host ----------------
+    cpu = None
+    if not args.no_cpu:
+        prm = p64.params
+        gp = esp_grid.GridParams(prm["c_split"], prm["c_spread"], prm["P"], tuple(prm["M"]), prm["rc"])
+        reps, t0 = 0, time.perf_counter()
+        while reps < 1 or time.perf_counter() - t0 < 10.0:
+            esp_grid.esp_grid(h, r32.astype(np.float64), q32.astype(np.float64), gp)
+            reps += 1
+        tc = (time.perf_counter() - t0) / reps
+        cpu = {"value": N / tc / 1e6, "unit": "M particle-steps/s", "cores": 1, "kind": "oracle",
+               "sample": f"{reps} full steps of the oracle's gridded FP64 ESP (numpy, single thread) on the "
+                         f"same N={N} workload at the FP64 plan's parameters; "
+                         f"host has {len(os.sched_getaffinity(0))} cores available"}
+
+    prm = p32.params
+    G = prm["M"][0] * prm["M"][1] * prm["M"][2]
+    S = (prm["M"][0] // 2 + 1) * prm["M"][1] * prm["M"][2]
+    avg_s = dom_ms / dom_n / 1e3
+    bytes_dom = stage_bytes(dominant, N, G, S, 4)
+    achieved = bytes_dom / avg_s / 1e9
+    value = N * args.steps / dt32 / 1e6
+    v64 = N * args.steps / dt64 / 1e6
+    line = {
+        "metric": "M particle-steps/s (E+F+virial) at 1e-5 rel err: FP32+learned vs plain FP64",
+        "value": round(value, 3),
+        "unit": "M particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt32 / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "bulk-water-shaped, 10,000 rigid 3-site triplets, cubic 6.7 nm, N=30000, tol 1e-5",
+                   "seed": args.seed, "params": "analytic", "c": prm["c_split"], "P": prm["P"],
+                   "M": prm["M"], "rc": prm["rc"], "tile": prm["tile"]},
+        "fp64_baseline": {"value": round(v64, 3), "ms_per_step": dt64 / args.steps * 1e3,
+                          "params": "analytic", "M": p64.params["M"], "P": p64.params["P"]},
+        "speedup_vs_fp64": value / v64,
+        "parity_vs_oracle": {"fp32": par32, "fp64": par64},
+        "stage_ms_fp32": {k: v[0] / v[1] for k, v in stages.items()},
+        "roofline": {"kernel": dominant, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": bytes_dom, "avg_launch_us": avg_s * 1e6},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,219 @@
+/*
+ * esp.h -- C ABI of the MI355X (gfx950) reciprocal-space ESP library.
+ *
+ * Ewald summation with prolates (ESP) for NPT: the long-range (Fourier-space)
+ * energy, the full 6-component virial tensor and the forces of a periodic
+ * system of point charges in a general (triclinic) cell.
+ *
+ * What is computed (citations are to Liang, Lu & Jiang, "Fast Ewald Summation
+ * with Prolates for Charged Systems in the NPT Ensemble", arXiv 2601.00161):
+ *
+ *   E  = U_F + U_self (+ U_cb + U_bb when sum q != 0)     eq. UF, eq. selfen, eq. Corr
+ *   W  = V * (P_F + P_cb + P_bb)                           eq. diag, eq. PFfinal, eq. Corr
+ *   F  = F_F, the Fourier-space force by analytic
+ *        differentiation of the gridded energy             App. C, eq. UFAnal / eq. AD
+ *
+ * through the particle-mesh steps of Sec. 4.1 (Algorithm 1): PSWF spreading
+ * onto a uniform grid along the cell vectors, one forward 3D FFT, diagonal
+ * scaling by W_hat^-2 times the splitting kernel, and a Fourier-space
+ * reduction; forces add one inverse FFT and a gather with the window gradient.
+ * The real-space part (U_N, P_N, F_N of eq. UN / eq. PinsN) is NOT computed
+ * here; the caller adds it.
+ *
+ * Conventions
+ *   Units: any consistent length unit (the defaults assume nm); charges in e;
+ *     the Coulomb constant is esp_opts.coulomb_k (1 by default).
+ *   Cell: h[3*i + j] = component i of cell vector j (cell vectors are the
+ *     columns of h, Sec. 2.2); det h must be positive.
+ *   Positions: xyz[3*p + d], any real values (wrapped into the cell).
+ *   out7 = { E, W_xx, W_yy, W_zz, W_xy, W_xz, W_yz }, W = V * P in energy
+ *     units, so tr W = E for the converged Coulomb energy (eq. PSRela).
+ *   Forces: f[3*p + d], overwritten (not accumulated).
+ *
+ * Memory and ordering
+ *   xyz, q, f and out7 are DEVICE pointers owned by the caller.  Every call
+ *   is enqueued on the plan's stream and is asynchronous; results are valid
+ *   after the stream is synchronised.  The plan owns all scratch memory,
+ *   which it allocates in esp_plan only; the per-step calls allocate nothing.
+ *   A plan is used by one host thread at a time; calls on one plan must not
+ *   overlap.
+ *
+ * Errors
+ *   Negative status = error, nothing was enqueued; positive = warning, the
+ *   result is valid.  esp_last_error() describes the most recent problem.
+ *   Non-finite positions or charges are detected on the device: the affected
+ *   particles are treated as uncharged, and the next call to esp_check()
+ *   (which synchronises) reports ESP_ENONFINITE.
+ */
+#ifndef ESP_MI355X_H
+#define ESP_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct esp_plan_s esp_plan_t;
+typedef struct esp_batch_s esp_batch_t;
+
+typedef enum {
+  ESP_OK = 0,
+  ESP_WARN_REPLAN = 1,    /* esp_set_box: the new box is >10% off the grid rule */
+  ESP_WARN_FALLBACK = 2,  /* esp_plan: learned parameters rejected, analytic used */
+  ESP_EINVAL = -1,        /* bad argument (null pointer, bad size or option) */
+  ESP_EBOX = -2,          /* det h <= 0 or not finite */
+  ESP_ECUTOFF = -3,       /* rc >= half the smallest perpendicular cell width */
+  ESP_ENOMEM = -4,        /* device allocation failed */
+  ESP_EDEVICE = -5,       /* HIP runtime error */
+  ESP_ENONFINITE = -6     /* non-finite input seen by the device */
+} esp_status;
+
+enum { ESP_FP32 = 0, ESP_FP64 = 1 };
+enum { ESP_ANALYTIC = 0, ESP_EXPLICIT = 1, ESP_LEARNED = 2 };
+enum { ESP_ISO = 0, ESP_SEMI = 1, ESP_ANISO = 2, ESP_FLEX = 3 };
+
+/* Options.  Fill with esp_opts_default() and override fields.
+ *
+ * tol semantics (target relative error of the requested outputs):
+ *   analytic parameters use Delta = tol for ISO/SEMI/ANISO coupling and
+ *   Delta = tol/5 for FLEX (off-diagonal virial components are harder,
+ *   Sec. 5.1), then c from psi_0^c(1)/psi_0^c(0) = Delta, P = ceil(-log10
+ *   Delta) + 1, and M_d = next 2,3,5-smooth integer >= sigma |h_d| c /(pi rc)
+ *   with sigma = grid_sigma.
+ * With params = ESP_EXPLICIT the fields c_split, c_spread, P, M are used
+ * as given (each must be set).  With ESP_LEARNED the parameters come from the
+ * proposer registered with esp_set_proposer (analytic fallback otherwise). */
+typedef struct {
+  int precision;       /* ESP_FP32 (default) or ESP_FP64 */
+  int params;          /* ESP_ANALYTIC (default), ESP_EXPLICIT, ESP_LEARNED */
+  int coupling;        /* ESP_ISO .. ESP_FLEX: which virial components must meet tol */
+  double rc;           /* cutoff radius of the split; default 0.9 */
+  double c_split;      /* explicit: PSWF bandwidth of the splitting kernel */
+  double c_spread;     /* explicit: PSWF bandwidth of the window */
+  int P;               /* explicit: window support in grid points per dimension */
+  int M[3];            /* explicit: grid subintervals along each cell vector */
+  double grid_sigma;   /* analytic grid oversampling; default 1.07 */
+  double coulomb_k;    /* Coulomb constant multiplying E, W, F; default 1 */
+  int tile;            /* spreading tile edge in grid cells; 0 = automatic */
+  void *stream;        /* hipStream_t for every call on the plan; NULL = default */
+  double window_tol;   /* max error of the window polynomials relative to psi(0);
+                          0 = automatic: max(Delta/100, 2e-8) for FP32, Delta/1000
+                          for FP64 */
+} esp_opts;
+
+/* Parameters a plan resolved to (returned by esp_get_params). */
+typedef struct {
+  int precision;
+  int64_t n;
+  double tol, delta, rc, c_split, c_spread;
+  int P, M[3];
+  int tile[3], ntiles;
+  int window_degree;   /* degree of the per-subinterval window polynomials */
+  int kernel_degree;   /* Chebyshev degree of the psi / psi' kernel fits */
+  double lambda0_split, C0_split, psi0_split;
+  double volume;
+  int params_source;   /* ESP_ANALYTIC / ESP_EXPLICIT / ESP_LEARNED actually used */
+} esp_params;
+
+void esp_opts_default(esp_opts *o);
+
+/* Create a plan for n particles in cell h at tolerance tol (Sec. 5.1 rules,
+ * or explicit / learned parameters).  Allocates every device buffer.
+ *   h: host, 9 doubles.   n >= 1.   tol in [1e-12, 1e-1).   o may be NULL.
+ * Errors: ESP_EINVAL, ESP_EBOX, ESP_ECUTOFF, ESP_ENOMEM, ESP_EDEVICE. */
+esp_status esp_plan(const double h[9], int64_t n, double tol, const esp_opts *o,
+                    esp_plan_t **out);
+
+/* New cell for the following calls (an NPT step).  No re-allocation: the
+ * splitting and grid parameters stay fixed while the box fluctuates
+ * (Sec. 3.3, Sec. 5.1).  Returns ESP_WARN_REPLAN if the grid rule is now
+ * violated by more than 10 %; ESP_EBOX / ESP_ECUTOFF on an invalid cell. */
+esp_status esp_set_box(esp_plan_t *p, const double h[9]);
+
+/* Energy and virial only: spreading, one forward FFT, scaling and reduction
+ * (Algorithm 1; no inverse FFT).  FP32 plans take float pointers; FP64
+ * plans use the _f64 variants.  xyz: 3n, q: n, out7: 7 doubles (device). */
+esp_status esp_energy_virial(esp_plan_t *p, const float *xyz, const float *q, double *out7);
+esp_status esp_energy_virial_f64(esp_plan_t *p, const double *xyz, const double *q, double *out7);
+
+/* Energy, virial and forces (App. C, analytic differentiation).
+ * f: 3n (device), overwritten.  out7 may be NULL. */
+esp_status esp_forces(esp_plan_t *p, const float *xyz, const float *q, float *f, double *out7);
+esp_status esp_forces_f64(esp_plan_t *p, const double *xyz, const double *q, double *f,
+                          double *out7);
+
+/* Synchronise the plan's stream and report device-side errors
+ * (ESP_ENONFINITE) seen since the last check; clears the flag. */
+esp_status esp_check(esp_plan_t *p);
+
+esp_status esp_get_params(const esp_plan_t *p, esp_params *out);
+const char *esp_last_error(const esp_plan_t *p);
+void esp_destroy(esp_plan_t *p);
+
+/* ---- stage hooks (for testing each step of the path in isolation) ------
+ * esp_stage_spread: cell sort + spreading only; copies the real grid
+ *   (M1*M2*M3 reals, index (g3*M2 + g2)*M1 + g1, i.e. g1 fastest) to
+ *   grid_out (device) and leaves the plan's grid cleared.
+ * esp_stage_fft: forward real-to-complex 3D FFT of grid_in (device, layout
+ *   as above, unnormalised, sign exp(-2 pi i m.g/M)) into spec_out (device,
+ *   (M1/2+1)*M2*M3 complex numbers as interleaved re,im; index
+ *   (m3*M2 + m2)*(M1/2+1) + m1).
+ * esp_stage_potential: the full force path up to the potential grid phi
+ *   (unnormalised inverse FFT of F_hat rho_hat / (V W_hat^2)), copied to
+ *   phi_out (device, real grid layout).
+ * esp_stage_sort: cell sort only; copies the permutation (int32, sorted
+ *   position -> particle index, n entries) and the tile offsets (int32,
+ *   ntiles + 1 entries) to perm_out / offsets_out (device).
+ * Precision of the real/complex buffers follows the plan. */
+esp_status esp_stage_sort(esp_plan_t *p, const void *xyz, const void *q, int32_t *perm_out,
+                          int32_t *offsets_out);
+esp_status esp_stage_spread(esp_plan_t *p, const void *xyz, const void *q, void *grid_out);
+esp_status esp_stage_fft(esp_plan_t *p, const void *grid_in, void *spec_out);
+esp_status esp_stage_potential(esp_plan_t *p, const void *xyz, const void *q, void *phi_out);
+
+/* Stream used by every subsequent call on the plan (hipStream_t; NULL =
+ * the default stream). */
+esp_status esp_set_stream(esp_plan_t *p, void *stream);
+
+/* ---- host-only helpers (no device needed) -------------------------------
+ * esp_resolve_params: the parameters esp_plan would choose for (h, n, tol,
+ *   o), with the same validation and error codes, without touching the
+ *   device.
+ * esp_pswf_eval: psi_0^c (unit L2 norm, psi(0) > 0) and its derivative at
+ *   m points x (any real x; beyond |x| = 1 the eigen-equation continuation),
+ *   plus int_0^x psi for |x| <= 1 (NaN outside); the constants
+ *   {psi(0), C0 = int_0^1 psi, lambda0} are written to consts3 if non-NULL.
+ *   All pointers are host pointers.  Useful for the caller's real-space
+ *   kernel N^c(r) = (1 - int_0^{r/rc} psi / C0) / r (Sec. 3.1).
+ * esp_c_from_delta: the bandwidth c with psi_0^c(1) / psi_0^c(0) = delta. */
+esp_status esp_resolve_params(const double h[9], int64_t n, double tol, const esp_opts *o,
+                              esp_params *out);
+esp_status esp_pswf_eval(double c, int64_t m, const double *x, double *psi, double *dpsi,
+                         double *ipsi, double *consts3);
+double esp_c_from_delta(double delta);
+
+/* ---- per-stage timing ----------------------------------------------------
+ * Stages, in launch order: 0 bin, 1 scan, 2 scatter (the cell sort), 3 spread,
+ * 4 fft_xy, 5 fft_z (z transform + scaling/reduction [+ G and inverse z]),
+ * 6 fft_xy_inv, 7 gather, 8 finalize.
+ * esp_profile_enable: record a HIP event pair on the plan's stream around each
+ *   launch of the stages in stage_mask (bit s = stage s), for up to
+ *   max_launches launches per stage; mask 0 turns profiling off.  Synchronises.
+ * esp_profile_read: synchronise and return, per stage (ESP_NUM_STAGES
+ *   entries, host arrays), the accumulated milliseconds and launch counts
+ *   since profiling was enabled. */
+#define ESP_NUM_STAGES 9
+esp_status esp_profile_enable(esp_plan_t *p, unsigned stage_mask, int max_launches);
+esp_status esp_profile_read(esp_plan_t *p, double *total_ms, int64_t *launches);
+const char *esp_stage_name(int stage);
+
+/* Library version string. */
+const char *esp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ESP_MI355X_H */

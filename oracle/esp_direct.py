@@ -55,16 +55,19 @@ class SplitResult:
 def real_space(h, r, q, c, rc, forces=True):
     """U_N (eq. UN), W_N (eq. PinsN, sign +) and F_N (eq. Fc) over pairs within rc."""
     q = np.asarray(q, np.float64)
-    i, j, d = lattice.pairs_within(h, r, rc)
-    dist = np.linalg.norm(d, axis=1)
-    qq = q[i] * q[j]
-    U = 0.5 * float(np.sum(qq * splitting.near_kernel(dist, c, rc)))
-    fw = qq * splitting.near_force_weight(dist, c, rc) / dist ** 3
-    W = 0.5 * np.einsum("p,pa,pb->ab", fw, d, d)
-    F = None
-    if forces:
-        F = np.zeros((r.shape[0], 3))
-        np.add.at(F, i, fw[:, None] * d)
+    N = q.shape[0]
+    U = 0.0
+    W = np.zeros((3, 3))
+    F = np.zeros((N, 3)) if forces else None
+    for i, j, d in lattice.pair_chunks(h, r, rc):
+        dist = np.linalg.norm(d, axis=1)
+        qq = q[i] * q[j]
+        U += 0.5 * float(np.sum(qq * splitting.near_kernel(dist, c, rc)))
+        fw = qq * splitting.near_force_weight(dist, c, rc) / dist ** 3
+        W += 0.5 * np.einsum("p,pa,pb->ab", fw, d, d)
+        if forces:
+            for a in range(3):
+                F[:, a] += np.bincount(i, weights=fw * d[:, a], minlength=N)
     return U, W, F
 
 

@@ -61,17 +61,19 @@ def ewald(h, r, q, rcut=None, forces=True):
     kcut = 2.0 * beta * ETA
 
     # ---- real space: primed sum over pairs and images --------------------
-    i, j, d = lattice.pairs_within(h, r, rcut)
-    dist = np.linalg.norm(d, axis=1)
-    qq = q[i] * q[j]
-    e_pair = qq * erfc(beta * dist) / dist
-    # -r dU/dr for the pair potential erfc(beta r)/r
-    g = qq * (erfc(beta * dist) / dist + 2.0 * beta / np.sqrt(np.pi) * np.exp(-(beta * dist) ** 2))
-    U_real = 0.5 * float(np.sum(e_pair))
-    W_real = 0.5 * np.einsum("p,pa,pb->ab", g / dist ** 2, d, d)
+    U_real = 0.0
+    W_real = np.zeros((3, 3))
     F = np.zeros((N, 3))
-    if forces:
-        np.add.at(F, i, (g / dist ** 2)[:, None] * d)
+    for i, j, d in lattice.pair_chunks(h, r, rcut):
+        dist = np.linalg.norm(d, axis=1)
+        qq = q[i] * q[j]
+        U_real += 0.5 * float(np.sum(qq * erfc(beta * dist) / dist))
+        # -r dU/dr for the pair potential erfc(beta r)/r
+        g = qq * (erfc(beta * dist) / dist + 2.0 * beta / np.sqrt(np.pi) * np.exp(-(beta * dist) ** 2))
+        W_real += 0.5 * np.einsum("p,pa,pb->ab", g / dist ** 2, d, d)
+        if forces:
+            for a in range(3):
+                F[:, a] += np.bincount(i, weights=g / dist ** 2 * d[:, a], minlength=N)
 
     # ---- Fourier space -----------------------------------------------------
     mmax = lattice.mode_box(h, kcut)

@@ -102,15 +102,16 @@ def back_transform(h, r, X, mmax):
     return T
 
 
-def pairs_within(h, r, rcut, chunk=4096):
-    """All periodic pairs (i, j, n) with 0 < |r_i - r_j - h n| <= rcut.
+def pair_chunks(h, r, rcut, chunk=2048, rows=None):
+    """Periodic pairs (i, j, n) with 0 < |r_i - r_j - h n| <= rcut, in chunks of i.
 
     Positions are wrapped into the cell, the images that can reach the cell
     are replicated explicitly, and SciPy's k-d tree returns the pairs.  Every
     ordered pair appears once per image, so sums over the result carry the
-    factor 1/2 of the primed double sums of the paper.
+    factor 1/2 of the primed double sums of the paper.  ``rows`` restricts i
+    to a subset of particles.
 
-    Returns (i, j, d) with d = r_i - (r_j + h n) of shape (npairs, 3).
+    Yields (i, j, d) with d = r_i - (r_j + h n) of shape (npairs, 3).
     """
     h = np.asarray(h, np.float64)
     s = reduced(h, r)
@@ -121,14 +122,18 @@ def pairs_within(h, r, rcut, chunk=4096):
     shifts = np.array(list(itertools.product(*[range(-n, n + 1) for n in nimg])), dtype=np.float64)
     ext = (r0[None, :, :] + (shifts @ h.T)[:, None, :]).reshape(-1, 3)
     tree = cKDTree(ext)
-    I, J, D = [], [], []
-    for i0 in range(0, N, chunk):
-        sub = cKDTree(r0[i0:i0 + chunk])
+    idx = np.arange(N) if rows is None else np.asarray(rows, dtype=np.int64)
+    for c0 in range(0, idx.size, chunk):
+        sel = idx[c0:c0 + chunk]
+        sub = cKDTree(r0[sel])
         res = sub.sparse_distance_matrix(tree, rcut, output_type="ndarray")
         keep = res["v"] > 0.0
-        ii = res["i"][keep].astype(np.int64) + i0
+        ii = sel[res["i"][keep].astype(np.int64)]
         jj = res["j"][keep].astype(np.int64)
-        I.append(ii)
-        J.append(jj % N)
-        D.append(r0[ii] - ext[jj])
+        yield ii, jj % N, r0[ii] - ext[jj]
+
+
+def pairs_within(h, r, rcut, chunk=2048):
+    """All pairs of ``pair_chunks`` concatenated (small systems only)."""
+    I, J, D = zip(*pair_chunks(h, r, rcut, chunk))
     return np.concatenate(I), np.concatenate(J), np.concatenate(D)

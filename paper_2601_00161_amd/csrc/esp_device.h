@@ -1,0 +1,136 @@
+// Device-side data layout shared by the kernels and the host plan.
+//
+// Precision policy: R = float is the production path (spreading, FFT and
+// gather in FP32, FP32 Kahan-compensated per-thread mode sums, FP64 block
+// partials and final sums); R = double is the plain FP64 path built from the
+// same kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace espx {
+
+constexpr int kMaxP = 12;          // largest window support per dimension
+constexpr int kMaxWinDeg = 20;     // largest degree of the window polynomials
+constexpr int kMaxKerDeg = 48;     // largest Chebyshev degree of the kernel fits
+constexpr int kMaxRadix = 5;
+constexpr int kMaxStages = 16;
+constexpr int kNumSums = 7;        // energy + 6 virial components
+constexpr int kSpreadChunk = 64;   // particles staged per spreading round
+
+template <typename R>
+struct Cplx {
+  R x, y;
+};
+
+// Sorted particle record.  FP32: reduced coordinates as 32-bit fixed point
+// (s = S / 2^32), so binning and stencil placement are exact integer
+// operations; FP64: reduced coordinates in [0, 1).
+template <typename R>
+struct Record;
+template <>
+struct alignas(16) Record<float> {
+  uint32_t S[3];
+  float q;
+};
+template <>
+struct alignas(32) Record<double> {
+  double s[3];
+  double q;
+};
+
+struct FftLen {
+  int n;                 // transform length
+  int nstage;
+  int rad[kMaxStages];   // radices, applied in order
+  int tw;                // offset of exp(-2 pi i k / n), k < n, in the twiddle table
+};
+
+template <typename R>
+struct DevPlan {
+  // sizes
+  int64_t n;
+  int M1, M2, M3, H;               // grid; H = M1 / 2 + 1 half-spectrum columns
+  int P, nw, nker;                 // window support, window degree, kernel degree
+  int T1, T2, T3, nt1, nt2, nt3, ntiles;
+  int cz;                          // columns per block in the z-pass
+  int nbin;                        // blocks of the binning kernel
+  int nzblk;                       // blocks of the z-pass
+  // cell (updated by esp_set_box)
+  float hinv_hi[9], hinv_lo[9];    // h^-1 as float-float (FP32 path), row major
+  double hinv[9];                  // h^-1 (FP64 path), row major
+  R B[9];                          // 2 pi h^-T, row major: k = B m
+  R G[9];                          // -h^-T diag(M): force = q G grad_u
+  R kcut2;                         // (c_split / rc)^2
+  R ysc;                           // (rc / c_split)^2: y = |k|^2 ysc = x^2
+  R A;                             // 2 pi lam0 / C0 of the splitting PSWF
+  R inv_vol;                       // 1 / V
+  R coulomb_k;
+  // tables (device)
+  const R* win;                    // P x (nw + 1) monomial coefficients in tau
+  const R* kerf;                   // Chebyshev coefficients of psi(sqrt(y)), z = 2y - 1
+  const R* kerg;                   // Chebyshev coefficients of x psi'(x), x = sqrt(y)
+  const R* iw1;                    // 1 / w_hat(2 pi m / M1)^2, DFT index order
+  const R* iw2;
+  const R* iw3;
+  const Cplx<R>* tw;               // twiddles for the three lengths
+  FftLen f1, f2, f3;
+  // buffers
+  int* counts;                     // ntiles
+  int* offsets;                    // ntiles + 1
+  int* keys;                       // n
+  int* ranks;                      // n
+  int* perm;                       // n: sorted position -> particle
+  Record<R>* tmp;                  // n: records in input order
+  Record<R>* sorted;               // n
+  R* rho;                          // M1 M2 M3 real grid (kept zero between calls)
+  Cplx<R>* spec;                   // H M2 M3 half spectrum
+  R* phi;                          // M1 M2 M3 potential grid
+  double* zpart;                   // nzblk x 7 partial sums
+  double* qpart;                   // nbin x 2 partial sums (sum q, sum q^2)
+  int* flags;                      // [0]: non-finite input seen
+};
+
+// Launchers (defined in esp_kernels.hip, instantiated for float and double).
+template <typename R>
+hipError_t launch_bin(const DevPlan<R>& d, const R* xyz, const R* q, hipStream_t s);
+template <typename R>
+hipError_t launch_scan(const DevPlan<R>& d, hipStream_t s);
+template <typename R>
+hipError_t launch_scatter(const DevPlan<R>& d, hipStream_t s);
+template <typename R>
+hipError_t launch_spread(const DevPlan<R>& d, hipStream_t s);
+template <typename R>
+hipError_t launch_fft_xy(const DevPlan<R>& d, const R* grid, Cplx<R>* spec, bool clear_input,
+                         hipStream_t s);
+enum ZMode { Z_FFT_ONLY = 0, Z_ENERGY = 1, Z_POTENTIAL = 2 };
+template <typename R>
+hipError_t launch_fft_z(const DevPlan<R>& d, ZMode mode, hipStream_t s);
+template <typename R>
+hipError_t launch_fft_xy_inv(const DevPlan<R>& d, hipStream_t s);
+template <typename R>
+hipError_t launch_gather(const DevPlan<R>& d, R* f, hipStream_t s);
+struct FinalConsts {
+  double inv2V;        // 1 / (2 V)
+  double self_coef;    // psi(0) / (2 C0 rc)
+  double bg_coef;      // 2 pi Ic / V  (U_corr = -bg_coef Q^2)
+  double coulomb_k;
+};
+template <typename R>
+hipError_t launch_finalize(const DevPlan<R>& d, FinalConsts c, double* out7, hipStream_t s);
+template <typename R>
+hipError_t launch_fill(R* p, size_t count, hipStream_t s);
+
+// LDS bytes the kernels need for a plan (the host checks them against the
+// device limit before any launch).
+template <typename R>
+size_t lds_fft_xy(const DevPlan<R>& d);
+template <typename R>
+size_t lds_fft_z(const DevPlan<R>& d);
+template <typename R>
+size_t lds_spread(const DevPlan<R>& d);
+int fft_threads(int lines_x_len);
+
+}  // namespace espx
