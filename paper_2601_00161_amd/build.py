@@ -18,6 +18,8 @@ LIB = os.path.join(HERE, "libesp_mi355x.so")
 
 ARCH = "gfx950"
 SOURCES = ["esp_kernels.hip", "esp_mlp.hip", "esp_plan.cpp", "esp_batch.cpp", "pswf.cpp"]
+# compiled once per window support P, to instantiate the P-specialised kernels in parallel
+PER_P = ("esp_stencil.hip", range(2, 13))
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",
     # no packed-FP32 instructions in device code
@@ -50,6 +52,10 @@ def build(verbose: bool = False) -> str:
         obj = os.path.join(OBJ, os.path.splitext(s)[0] + ".o")
         lang = ["-x", "hip"] if s.endswith(".hip") else []
         jobs.append([hipcc, *FLAGS, *lang, "-c", os.path.join(CSRC, s), "-o", obj])
+    src, ps = PER_P
+    for P in ps:
+        obj = os.path.join(OBJ, f"{os.path.splitext(src)[0]}_p{P}.o")
+        jobs.append([hipcc, *FLAGS, f"-DESP_P={P}", "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj])
     with ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
         list(ex.map(_run, jobs))
     objs = [j[-1] for j in jobs]

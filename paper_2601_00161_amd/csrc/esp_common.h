@@ -1,0 +1,317 @@
+// Device helpers shared by the kernel translation units: complex arithmetic,
+// the LDS Stockham FFT, block reductions, reduced coordinates and stencil
+// placement, and the final FP64 sums.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "esp_device.h"
+
+namespace espx {
+
+// ------------------------------------------------------------------ complex
+template <typename R>
+__device__ __forceinline__ Cplx<R> cadd(Cplx<R> a, Cplx<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename R>
+__device__ __forceinline__ Cplx<R> csub(Cplx<R> a, Cplx<R> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename R>
+__device__ __forceinline__ Cplx<R> cmul(Cplx<R> a, Cplx<R> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename R>
+__device__ __forceinline__ Cplx<R> cscale(Cplx<R> a, R s) { return {a.x * s, a.y * s}; }
+// a + sgn * i * b
+template <typename R>
+__device__ __forceinline__ Cplx<R> cadd_i(Cplx<R> a, Cplx<R> b, R sgn) {
+  return {a.x - sgn * b.y, a.y + sgn * b.x};
+}
+
+// ------------------------------------------------------------- butterflies
+// sgn = -1: forward DFT (exp(-2 pi i jk/R)); sgn = +1: inverse (unnormalised).
+template <typename R, int RAD>
+struct Dft;
+
+template <typename R>
+struct Dft<R, 2> {
+  __device__ static void run(Cplx<R>* v, R) {
+    Cplx<R> a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  }
+};
+
+template <typename R>
+struct Dft<R, 3> {
+  __device__ static void run(Cplx<R>* v, R sgn) {
+    const R s60 = R(0.86602540378443864676);
+    Cplx<R> t1 = cadd(v[1], v[2]);
+    Cplx<R> t2 = csub(v[0], cscale(t1, R(0.5)));
+    Cplx<R> t3 = cscale(csub(v[1], v[2]), s60);
+    v[0] = cadd(v[0], t1);
+    v[1] = cadd_i(t2, t3, sgn);
+    v[2] = cadd_i(t2, t3, -sgn);
+  }
+};
+
+template <typename R>
+struct Dft<R, 4> {
+  __device__ static void run(Cplx<R>* v, R sgn) {
+    Cplx<R> a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+    Cplx<R> b0 = cadd(v[1], v[3]), b1 = csub(v[1], v[3]);
+    v[0] = cadd(a0, b0);
+    v[2] = csub(a0, b0);
+    v[1] = cadd_i(a1, b1, sgn);
+    v[3] = cadd_i(a1, b1, -sgn);
+  }
+};
+
+template <typename R>
+struct Dft<R, 5> {
+  __device__ static void run(Cplx<R>* v, R sgn) {
+    const R c1 = R(0.30901699437494742410), c2 = R(-0.80901699437494742410);
+    const R s1 = R(0.95105651629515357212), s2 = R(0.58778525229247312917);
+    Cplx<R> t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+    Cplx<R> t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
+    Cplx<R> a1 = {v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y};
+    Cplx<R> a2 = {v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y};
+    Cplx<R> b1 = {s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y};
+    Cplx<R> b2 = {s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y};
+    v[0] = cadd(v[0], cadd(t1, t2));
+    v[1] = cadd_i(a1, b1, sgn);
+    v[4] = cadd_i(a1, b1, -sgn);
+    v[2] = cadd_i(a2, b2, sgn);
+    v[3] = cadd_i(a2, b2, -sgn);
+  }
+};
+
+// One Stockham stage of nlines independent length-n transforms held in LDS:
+// element e of line l lives at base[l * lstride + e * estride].
+template <typename R, int RAD>
+__device__ void fft_stage(const Cplx<R>* __restrict__ in, Cplx<R>* __restrict__ out, int n, int Ns,
+                          int nlines, int lstride, int estride, const Cplx<R>* __restrict__ tw,
+                          R sgn) {
+  const int nb = n / RAD;
+  const int total = nlines * nb;
+  const int tunit = n / (Ns * RAD);
+  for (int id = threadIdx.x; id < total; id += blockDim.x) {
+    const int line = id / nb;
+    const int i = id - line * nb;
+    const int j = i % Ns;
+    const Cplx<R>* src = in + line * lstride;
+    Cplx<R>* dst = out + line * lstride;
+    Cplx<R> v[RAD];
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) v[r] = src[(i + r * nb) * estride];
+    if (Ns > 1) {
+#pragma unroll
+      for (int r = 1; r < RAD; ++r) {
+        Cplx<R> w = tw[tunit * j * r];      // j r < Ns RAD, so the index is < n
+        w.y = sgn < 0 ? w.y : -w.y;
+        v[r] = cmul(v[r], w);
+      }
+    }
+    Dft<R, RAD>::run(v, sgn);
+    const int ob = (i / Ns) * Ns * RAD + j;
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) dst[(ob + r * Ns) * estride] = v[r];
+  }
+  __syncthreads();
+}
+
+// All stages; ping-pongs between a and b and returns the buffer holding the result.
+template <typename R>
+__device__ Cplx<R>* fft_lines(Cplx<R>* a, Cplx<R>* b, const FftLen& f, int nlines, int lstride,
+                              int estride, const Cplx<R>* tw, bool inverse) {
+  const R sgn = inverse ? R(1) : R(-1);
+  int Ns = 1;
+  Cplx<R>* in = a;
+  Cplx<R>* out = b;
+  for (int s = 0; s < f.nstage; ++s) {
+    switch (f.rad[s]) {
+      case 2: fft_stage<R, 2>(in, out, f.n, Ns, nlines, lstride, estride, tw, sgn); break;
+      case 3: fft_stage<R, 3>(in, out, f.n, Ns, nlines, lstride, estride, tw, sgn); break;
+      case 4: fft_stage<R, 4>(in, out, f.n, Ns, nlines, lstride, estride, tw, sgn); break;
+      default: fft_stage<R, 5>(in, out, f.n, Ns, nlines, lstride, estride, tw, sgn); break;
+    }
+    Ns *= f.rad[s];
+    Cplx<R>* t = in;
+    in = out;
+    out = t;
+  }
+  return in;
+}
+
+// ------------------------------------------------------------- reductions
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Block-wide sums of NV doubles (fixed order, deterministic).  red: LDS of
+// at least NV * (blockDim / 64) doubles.  Result valid in thread 0.
+template <int NV>
+__device__ void block_sum(double* v, double* red) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) red[k * 16 + wid] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double s = 0;
+      for (int w = 0; w < nw; ++w) s += red[k * 16 + w];
+      v[k] = s;
+    }
+  }
+}
+
+// ----------------------------------------------------------- coordinates
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+  s = a + b;
+  float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// s_d = (h^-1 r)_d in float-float arithmetic, wrapped to [0, 1) and returned as
+// 32-bit fixed point floor(frac(s_d) 2^32).
+__device__ __forceinline__ uint32_t fixed_reduced(const float* hi, const float* lo, float x, float y,
+                                                  float z) {
+  const float r[3] = {x, y, z};
+  float sh = 0.f, sl = 0.f;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    float p = hi[j] * r[j];
+    float pe = fmaf(hi[j], r[j], -p);          // exact product error
+    float t, e;
+    two_sum(sh, p, t, e);
+    sh = t;
+    sl += e + pe + lo[j] * r[j];
+  }
+  float fh, e2;
+  two_sum(sh, -floorf(sh), fh, e2);            // fractional part, error kept in e2
+  sl += e2;
+  const float scale = 4294967296.0f;           // 2^32
+  float xh = fh * scale;                       // exact (power of two)
+  float ih = floorf(xh);
+  float rem = xh - ih;                         // exact
+  float t = rem + sl * scale;
+  long long S = static_cast<long long>(ih) + static_cast<long long>(floorf(t));
+  return static_cast<uint32_t>(S & 0xffffffffLL);
+}
+
+// Stencil base g0 = ceil(u - P/2) (wrapped into [0, M)) and the local offset
+// tau = u - g0 - (P-1)/2 in (-1/2, 1/2] of the first stencil point, from the
+// fixed-point reduced coordinate S (u = M S / 2^32).
+__device__ __forceinline__ void stencil_fixed(uint32_t S, int M, int P, int& gm, float& tau) {
+  const long long U = static_cast<long long>(static_cast<unsigned long long>(M) * S);
+  const long long a = U - (static_cast<long long>(P) << 31);
+  const long long g0 = (a + 0xffffffffLL) >> 32;                    // ceil(a / 2^32)
+  const long long tf = U - (g0 << 32) - (static_cast<long long>(P - 1) << 31);
+  tau = static_cast<float>(tf) * 2.3283064365386963e-10f;           // 2^-32
+  int g = static_cast<int>(g0);
+  gm = g < 0 ? g + M : g;
+}
+
+__device__ __forceinline__ void stencil_f64(double s, int M, int P, int& gm, double& tau) {
+  const double u = s * M;
+  const double g0 = ceil(u - 0.5 * P);
+  tau = u - g0 - 0.5 * (P - 1);
+  int g = static_cast<int>(g0);
+  gm = g < 0 ? g + M : (g >= M ? g - M : g);
+}
+
+template <typename R>
+struct Coord;
+
+template <>
+struct Coord<float> {
+  __device__ static void make(const DevPlan<float>& d, float x, float y, float z, float q,
+                              Record<float>& rec) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) rec.S[k] = fixed_reduced(d.hinv_hi + 3 * k, d.hinv_lo + 3 * k, x, y, z);
+    rec.q = q;
+  }
+  __device__ static void stencil(const Record<float>& rec, int dim, int M, int P, int& gm, float& tau) {
+    const uint32_t S = dim == 0 ? rec.S[0] : (dim == 1 ? rec.S[1] : rec.S[2]);
+    stencil_fixed(S, M, P, gm, tau);
+  }
+};
+
+template <>
+struct Coord<double> {
+  __device__ static void make(const DevPlan<double>& d, double x, double y, double z, double q,
+                              Record<double>& rec) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      double s = d.hinv[3 * k] * x + d.hinv[3 * k + 1] * y + d.hinv[3 * k + 2] * z;
+      s -= floor(s);
+      rec.s[k] = s < 1.0 ? s : 0.0;
+    }
+    rec.q = q;
+  }
+  __device__ static void stencil(const Record<double>& rec, int dim, int M, int P, int& gm, double& tau) {
+    const double sd = dim == 0 ? rec.s[0] : (dim == 1 ? rec.s[1] : rec.s[2]);
+    stencil_f64(sd, M, P, gm, tau);
+  }
+};
+
+template <typename R>
+__device__ __forceinline__ bool finite_r(R v) { return isfinite(v); }
+
+template <typename R>
+__device__ __forceinline__ void atomic_add_global(R* p, R v) {
+  unsafeAtomicAdd(p, v);
+}
+
+// Final FP64 sums: the z-pass block partials (eq. diag / eq. PFfinal summed
+// over modes), the self-energy (eq. selfen) and, for a net charge, the
+// neutralising-background terms (eq. Corr).  Run by one workgroup of a kernel
+// launched after the z-pass, in a fixed order.
+template <typename R>
+__device__ void finalize_sums(const DevPlan<R>& d, const FinalConsts& fc, double* __restrict__ out,
+                              double* red) {
+  double v[kNumSums];
+#pragma unroll
+  for (int k = 0; k < kNumSums; ++k) v[k] = 0.0;
+  for (int b = threadIdx.x; b < d.nzblk; b += blockDim.x)
+#pragma unroll
+    for (int k = 0; k < kNumSums; ++k) v[k] += d.zpart[static_cast<size_t>(b) * kNumSums + k];
+  block_sum<kNumSums>(v, red);
+  __syncthreads();
+  double qv[2] = {0.0, 0.0};
+  for (int b = threadIdx.x; b < d.nbin; b += blockDim.x) {
+    qv[0] += d.qpart[2 * b];
+    qv[1] += d.qpart[2 * b + 1];
+  }
+  block_sum<2>(qv, red + kNumSums * 16 - 32);
+  if (threadIdx.x == 0) {
+    const double Q = qv[0], Q2 = qv[1];
+    const double Uself = -fc.self_coef * Q2;
+    const double Ucorr = -fc.bg_coef * Q * Q;
+    const double k = fc.coulomb_k;
+    out[0] = k * (v[0] * fc.inv2V + Uself + Ucorr);
+    out[1] = k * (v[1] * fc.inv2V + Ucorr);
+    out[2] = k * (v[2] * fc.inv2V + Ucorr);
+    out[3] = k * (v[3] * fc.inv2V + Ucorr);
+    out[4] = k * v[4] * fc.inv2V;
+    out[5] = k * v[5] * fc.inv2V;
+    out[6] = k * v[6] * fc.inv2V;
+  }
+}
+
+
+// Spreading and gather launchers for one window support P (one translation
+// unit per P, see esp_stencil.hip).
+template <typename R, int P>
+hipError_t spread_launch(const DevPlan<R>& d, hipStream_t s);
+template <typename R, int P>
+hipError_t gather_launch(const DevPlan<R>& d, R* f, FinalConsts c, double* out7, hipStream_t s);
+
+}  // namespace espx

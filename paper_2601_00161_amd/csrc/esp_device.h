@@ -13,7 +13,7 @@
 namespace espx {
 
 constexpr int kMaxP = 12;          // largest window support per dimension
-constexpr int kMaxWinDeg = 20;     // largest degree of the window polynomials
+constexpr int kMaxWinDeg = 16;     // largest degree of the window polynomials (classes 8, 12, 16)
 constexpr int kMaxKerDeg = 48;     // largest Chebyshev degree of the kernel fits
 constexpr int kMaxRadix = 5;
 constexpr int kMaxStages = 16;
@@ -53,7 +53,7 @@ struct DevPlan {
   // sizes
   int64_t n;
   int M1, M2, M3, H;               // grid; H = M1 / 2 + 1 half-spectrum columns
-  int P, nw, nker;                 // window support, window degree, kernel degree
+  int P, nw, nker;                 // window support, padded window degree (8/12/16), kernel degree
   int T1, T2, T3, nt1, nt2, nt3, ntiles;
   int cz;                          // columns per block in the z-pass
   int nbin;                        // blocks of the binning kernel
@@ -69,7 +69,7 @@ struct DevPlan {
   R inv_vol;                       // 1 / V
   R coulomb_k;
   // tables (device)
-  const R* win;                    // P x (nw + 1) monomial coefficients in tau
+  const R* win;                    // (nw + 1) x P monomial coefficients in tau, coefficient-major
   const R* kerf;                   // Chebyshev coefficients of psi(sqrt(y)), z = 2y - 1
   const R* kerg;                   // Chebyshev coefficients of x psi'(x), x = sqrt(y)
   const R* iw1;                    // 1 / w_hat(2 pi m / M1)^2, DFT index order
@@ -88,30 +88,15 @@ struct DevPlan {
   R* rho;                          // M1 M2 M3 real grid (kept zero between calls)
   Cplx<R>* spec;                   // H M2 M3 half spectrum
   R* phi;                          // M1 M2 M3 potential grid
-  double* zpart;                   // nzblk x 7 partial sums
+  double* zpart;                   // nzblk x 7 partial mode sums of the z-pass
   double* qpart;                   // nbin x 2 partial sums (sum q, sum q^2)
-  int* flags;                      // [0]: non-finite input seen
+  int* flags;                      // bit 0: non-finite input; bit 1: inconsistent tile counts
+  int bin_lds;                     // tile histogram of the binning pass fits in LDS
 };
 
 // Launchers (defined in esp_kernels.hip, instantiated for float and double).
 template <typename R>
 hipError_t launch_bin(const DevPlan<R>& d, const R* xyz, const R* q, hipStream_t s);
-template <typename R>
-hipError_t launch_scan(const DevPlan<R>& d, hipStream_t s);
-template <typename R>
-hipError_t launch_scatter(const DevPlan<R>& d, hipStream_t s);
-template <typename R>
-hipError_t launch_spread(const DevPlan<R>& d, hipStream_t s);
-template <typename R>
-hipError_t launch_fft_xy(const DevPlan<R>& d, const R* grid, Cplx<R>* spec, bool clear_input,
-                         hipStream_t s);
-enum ZMode { Z_FFT_ONLY = 0, Z_ENERGY = 1, Z_POTENTIAL = 2 };
-template <typename R>
-hipError_t launch_fft_z(const DevPlan<R>& d, ZMode mode, hipStream_t s);
-template <typename R>
-hipError_t launch_fft_xy_inv(const DevPlan<R>& d, hipStream_t s);
-template <typename R>
-hipError_t launch_gather(const DevPlan<R>& d, R* f, hipStream_t s);
 struct FinalConsts {
   double inv2V;        // 1 / (2 V)
   double self_coef;    // psi(0) / (2 C0 rc)
@@ -119,9 +104,26 @@ struct FinalConsts {
   double coulomb_k;
 };
 template <typename R>
+hipError_t launch_scatter(const DevPlan<R>& d, hipStream_t s);
+// Final sums into out7 (one workgroup) after a z-pass in energy mode.
+template <typename R>
 hipError_t launch_finalize(const DevPlan<R>& d, FinalConsts c, double* out7, hipStream_t s);
 template <typename R>
-hipError_t launch_fill(R* p, size_t count, hipStream_t s);
+hipError_t launch_spread(const DevPlan<R>& d, hipStream_t s);
+template <typename R>
+hipError_t launch_fft_xy(const DevPlan<R>& d, const R* grid, Cplx<R>* spec, bool clear_input,
+                         hipStream_t s);
+enum ZMode { Z_FFT_ONLY = 0, Z_ENERGY = 1, Z_POTENTIAL = 2 };
+// z-pass; unless mode is Z_FFT_ONLY it writes nzblk x 7 partial mode sums.
+template <typename R>
+hipError_t launch_fft_z(const DevPlan<R>& d, ZMode mode, hipStream_t s);
+template <typename R>
+hipError_t launch_fft_xy_inv(const DevPlan<R>& d, hipStream_t s);
+// Gather; when out7 is non-null its block 0 also writes the final sums.
+template <typename R>
+hipError_t launch_gather(const DevPlan<R>& d, R* f, FinalConsts c, double* out7, hipStream_t s);
+template <typename T>
+hipError_t launch_fill(T* p, size_t count, hipStream_t s);
 
 // LDS bytes the kernels need for a plan (the host checks them against the
 // device limit before any launch).

@@ -124,11 +124,15 @@ void choose_tiles(Resolved& r, int tile) {
       if (nt >= 256) break;
     }
   }
-  r.ntiles = 1;
-  for (int d = 0; d < 3; ++d) {
-    r.T[d] = std::min(T, r.M[d]);
-    r.nt[d] = (r.M[d] + r.T[d] - 1) / r.T[d];
-    r.ntiles *= r.nt[d];
+  // the scatter pass keeps all tile offsets in LDS: at most 32768 tiles
+  for (;; ++T) {
+    r.ntiles = 1;
+    for (int d = 0; d < 3; ++d) {
+      r.T[d] = std::min(T, r.M[d]);
+      r.nt[d] = (r.M[d] + r.T[d] - 1) / r.T[d];
+      r.ntiles *= r.nt[d];
+    }
+    if (r.ntiles <= 32768) break;
   }
 }
 
@@ -253,10 +257,8 @@ void factor(int n, FftLen& f) {
 
 }  // namespace
 
-enum StageId { ST_BIN, ST_SCAN, ST_SCATTER, ST_SPREAD, ST_FFT_XY, ST_FFT_Z, ST_FFT_XY_INV, ST_GATHER,
-               ST_FINALIZE, ST_COUNT };
-const char* kStageNames[ST_COUNT] = {"bin", "scan", "scatter", "spread", "fft_xy", "fft_z",
-                                     "fft_xy_inv", "gather", "finalize"};
+enum StageId { ST_BIN, ST_SCATTER, ST_SPREAD, ST_FFT_XY, ST_FFT_Z, ST_FFT_XY_INV, ST_GATHER, ST_COUNT };
+const char* kStageNames[ST_COUNT] = {"bin", "scatter", "spread", "fft_xy", "fft_z", "fft_xy_inv", "gather"};
 
 // Optional per-stage timing with HIP events recorded on the plan's stream.
 struct Profiler {
@@ -278,7 +280,7 @@ struct esp_plan_s {
   Resolved r;
   Profiler prof;
   std::unique_ptr<Pswf> split, spread;
-  int nw = 0, nker = 0;
+  int nw = 0, nw_fitted = 0, nker = 0;
   double A = 0, self_coef = 0, Ic = 0;
   hipStream_t stream = nullptr;
   std::vector<void*> allocs;
@@ -332,18 +334,26 @@ void set_box_fields(esp_plan_t* p, DevPlan<R>& d) {
   d.inv_vol = static_cast<R>(1.0 / r.V);
 }
 
-int fit_window(esp_plan_t* p, double eps, std::vector<double>& coef) {
+// Per-subinterval window polynomials (Sec. 4.3): polynomial p approximates
+// W(tau + (P-1)/2 - p) = psi((tau + (P-1)/2 - p) / omega), tau in [-1/2, 1/2],
+// omega = P/2, by Chebyshev interpolation converted to monomials in tau.  The
+// smallest degree meeting eps (values) and 4 eps (derivatives), relative to
+// psi(0), is chosen, then padded with zeros to the kernel class 8, 12 or 16.
+// Table layout: coef[j * P + p] multiplies tau^j in polynomial p.
+int fit_window(esp_plan_t* p, double eps, std::vector<double>& coef, int* fitted) {
   const Pswf& ps = *p->spread;
   const int P = p->r.P;
   const double omega = 0.5 * P;
-  for (int deg = 3; deg <= kMaxWinDeg; ++deg) {
-    coef.assign(static_cast<size_t>(P) * (deg + 1), 0.0);
+  std::vector<std::vector<double>> best;
+  int deg = 3;
+  for (; deg <= kMaxWinDeg; ++deg) {
+    best.assign(P, {});
     double maxerr = 0, maxderr = 0;
     for (int q = 0; q < P; ++q) {
       const double shift = 0.5 * (P - 1) - q;
       auto f = [&](double tau) { return ps.psi((tau + shift) / omega); };
-      std::vector<double> c = fit_monomial(f, -0.5, 0.5, deg);
-      for (int j = 0; j <= deg; ++j) coef[q * (deg + 1) + j] = c[j];
+      best[q] = fit_monomial(f, -0.5, 0.5, deg);
+      const std::vector<double>& c = best[q];
       for (int s = 0; s <= 64; ++s) {
         const double tau = -0.5 + s / 64.0;
         double v = 0, dv = 0;
@@ -355,9 +365,15 @@ int fit_window(esp_plan_t* p, double eps, std::vector<double>& coef) {
         maxderr = std::max(maxderr, std::fabs(dv - ps.dpsi((tau + shift) / omega) / omega));
       }
     }
-    if (maxerr <= eps * ps.psi0() && maxderr <= 4 * eps * ps.psi0()) return deg;
+    if (maxerr <= eps * ps.psi0() && maxderr <= 4 * eps * ps.psi0()) break;
   }
-  return kMaxWinDeg;
+  deg = std::min(deg, kMaxWinDeg);
+  *fitted = deg;
+  const int cls = deg <= 8 ? 8 : (deg <= 12 ? 12 : 16);
+  coef.assign(static_cast<size_t>(cls + 1) * P, 0.0);
+  for (int q = 0; q < P; ++q)
+    for (int j = 0; j <= deg; ++j) coef[static_cast<size_t>(j) * P + q] = best[q][j];
+  return cls;
 }
 
 int fit_kernel(esp_plan_t* p, std::vector<double>& cf, std::vector<double>& cg) {
@@ -418,7 +434,9 @@ esp_status build_device(esp_plan_t* p) {
   std::vector<double> win;
   double eps = r.precision == ESP_FP32 ? std::max(1e-2 * r.delta, 2e-8) : 1e-3 * r.delta;
   if (r.window_tol > 0) eps = r.window_tol;
-  p->nw = fit_window(p, std::min(eps, 1e-4), win);
+  int fitted = 0;
+  p->nw = fit_window(p, std::min(eps, 1e-4), win, &fitted);
+  p->nw_fitted = fitted;
   std::vector<double> cf, cg;
   p->nker = fit_kernel(p, cf, cg);
   d.nw = p->nw;
@@ -498,6 +516,7 @@ esp_status build_device(esp_plan_t* p) {
       (st = dalloc(p, &d.zpart, static_cast<size_t>(d.nzblk) * kNumSums)) ||
       (st = dalloc(p, &d.qpart, static_cast<size_t>(d.nbin) * 2)) || (st = dalloc(p, &d.flags, 4)))
     return st;
+  d.bin_lds = r.ntiles <= 8192 ? 1 : 0;
   e = hipMemset(d.counts, 0, r.ntiles * sizeof(int));
   if (e == hipSuccess) e = hipMemset(d.rho, 0, G * sizeof(R));
   if (e == hipSuccess) e = hipMemset(d.flags, 0, 4 * sizeof(int));
@@ -529,11 +548,11 @@ hipError_t stage(esp_plan_t* p, int st, F&& launch) {
   return e;
 }
 
+// Cell sort.  Leaves the tile counts set; the spreading pass clears them.
 template <typename R>
 hipError_t run_sort(esp_plan_t* p, const R* xyz, const R* q) {
   DevPlan<R>& d = dev<R>(p);
   hipError_t e = stage(p, ST_BIN, [&] { return launch_bin(d, xyz, q, p->stream); });
-  if (e == hipSuccess) e = stage(p, ST_SCAN, [&] { return launch_scan(d, p->stream); });
   if (e == hipSuccess) e = stage(p, ST_SCATTER, [&] { return launch_scatter(d, p->stream); });
   return e;
 }
@@ -557,7 +576,7 @@ esp_status energy_virial(esp_plan_t* p, const R* xyz, const R* q, double* out7) 
   if (st != ESP_OK) return st;
   hipError_t e = stage(p, ST_FFT_XY, [&] { return launch_fft_xy(d, d.rho, d.spec, true, p->stream); });
   if (e == hipSuccess) e = stage(p, ST_FFT_Z, [&] { return launch_fft_z(d, Z_ENERGY, p->stream); });
-  if (e == hipSuccess) e = stage(p, ST_FINALIZE, [&] { return launch_finalize(d, final_consts(p), out7, p->stream); });
+  if (e == hipSuccess) e = launch_finalize(d, final_consts(p), out7, p->stream);
   return e == hipSuccess ? ESP_OK : hip_fail(p, e, "kernel launch");
 }
 
@@ -581,9 +600,7 @@ esp_status forces(esp_plan_t* p, const R* xyz, const R* q, R* f, double* out7) {
   esp_status st = potential(p, xyz, q);
   if (st != ESP_OK) return st;
   DevPlan<R>& d = dev<R>(p);
-  hipError_t e = stage(p, ST_GATHER, [&] { return launch_gather(d, f, p->stream); });
-  if (e == hipSuccess && out7)
-    e = stage(p, ST_FINALIZE, [&] { return launch_finalize(d, final_consts(p), out7, p->stream); });
+  hipError_t e = stage(p, ST_GATHER, [&] { return launch_gather(d, f, final_consts(p), out7, p->stream); });
   return e == hipSuccess ? ESP_OK : hip_fail(p, e, "kernel launch");
 }
 
@@ -749,6 +766,10 @@ esp_status esp_check(esp_plan_t* p) {
   if (e != hipSuccess) return hip_fail(p, e, "flag read");
   if (h) {
     (void)hipMemset(flags, 0, sizeof(int));
+    if (h & 2) {
+      p->err = "inconsistent tile counts in the cell sort (results of the affected calls are invalid)";
+      return ESP_EDEVICE;
+    }
     p->err = "non-finite position or charge (treated as an uncharged particle)";
     return ESP_ENONFINITE;
   }
@@ -772,7 +793,7 @@ esp_status esp_get_params(const esp_plan_t* p, esp_params* out) {
     out->tile[d] = r.T[d];
   }
   out->ntiles = r.ntiles;
-  out->window_degree = p->nw;
+  out->window_degree = p->nw_fitted;
   out->kernel_degree = p->nker;
   out->lambda0_split = p->split->lambda0();
   out->C0_split = p->split->C0();
@@ -796,15 +817,20 @@ esp_status esp_stage_sort(esp_plan_t* p, const void* xyz, const void* q, int32_t
   hipError_t e;
   const int* perm;
   const int* off;
+  int* counts;
   if (p->r.precision == ESP_FP32) {
     e = run_sort(p, static_cast<const float*>(xyz), static_cast<const float*>(q));
     perm = p->d32.perm;
     off = p->d32.offsets;
+    counts = p->d32.counts;
   } else {
     e = run_sort(p, static_cast<const double*>(xyz), static_cast<const double*>(q));
     perm = p->d64.perm;
     off = p->d64.offsets;
+    counts = p->d64.counts;
   }
+  // no spreading pass follows: clear the tile counts here
+  if (e == hipSuccess) e = launch_fill(counts, p->r.ntiles, p->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(perm_out, perm, p->r.n * sizeof(int), hipMemcpyDeviceToDevice, p->stream);
   if (e == hipSuccess)

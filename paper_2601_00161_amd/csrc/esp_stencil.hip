@@ -1,0 +1,279 @@
+// PSWF spreading (paper Sec. 4.1 Step 1, Sec. 4.2-4.3) and the gather of the
+// analytic-differentiation force (App. C), for one window support P.
+//
+// This file is compiled once per P (-DESP_P=2..12) so that the per-P
+// instantiations build in parallel.  Every kernel is also specialised on the
+// padded degree NW of the window polynomials (8, 12 or 16) so that the Horner
+// loops unroll completely and the coefficient reads are issued up front.
+#include <hip/hip_runtime.h>
+
+#include "esp_common.h"
+
+#ifndef ESP_P
+#error "compile with -DESP_P=<window support>"
+#endif
+
+namespace espx {
+
+// Values of the P window polynomials at tau.  Coefficient-major table:
+// win[j * P + p] multiplies tau^j in polynomial p (the window on the stencil
+// point g0 + p, whose offset from the particle is tau + (P - 1)/2 - p).
+template <typename R, int P, int NW>
+__device__ __forceinline__ void eval_window(const R* __restrict__ win, R tau, R* w) {
+#pragma unroll
+  for (int p = 0; p < P; ++p) w[p] = win[NW * P + p];
+#pragma unroll
+  for (int j = NW - 1; j >= 0; --j)
+#pragma unroll
+    for (int p = 0; p < P; ++p) w[p] = w[p] * tau + win[j * P + p];
+}
+
+// Values and tau-derivatives (= derivatives in grid units).
+template <typename R, int P, int NW>
+__device__ __forceinline__ void eval_window_d(const R* __restrict__ win, R tau, R* w, R* dw) {
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    w[p] = win[NW * P + p];
+    dw[p] = R(0);
+  }
+#pragma unroll
+  for (int j = NW - 1; j >= 0; --j)
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      dw[p] = dw[p] * tau + w[p];
+      w[p] = w[p] * tau + win[j * P + p];
+    }
+}
+
+// ----------------------------------------------------------------- spread
+// One workgroup per tile of T1 x T2 x T3 grid cells.  Its particles (those
+// whose stencil base lies in the tile, contiguous after the cell sort) are
+// spread into an LDS copy of the tile plus its (P - 1)-wide upper halo, which
+// is then added to the periodic grid.  The LDS tile accumulates in FP64 for
+// both precisions: products are formed in R, and ds_add_f64 is the fast LDS
+// atomic on gfx950 (ds_add_f32 is not).
+template <typename R, int P, int NW>
+__global__ void __launch_bounds__(256) k_spread(DevPlan<R> d) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tile = blockIdx.x;
+  const int t1 = tile % d.nt1, t2 = (tile / d.nt1) % d.nt2, t3 = tile / (d.nt1 * d.nt2);
+  const int o1 = t1 * d.T1, o2 = t2 * d.T2, o3 = t3 * d.T3;
+  const int E1 = min(d.T1, d.M1 - o1) + P - 1;
+  const int E2 = min(d.T2, d.M2 - o2) + P - 1;
+  const int E3 = min(d.T3, d.M3 - o3) + P - 1;
+  const int ncell = E1 * E2 * E3;
+  const int maxcell = (d.T1 + P - 1) * (d.T2 + P - 1) * (d.T3 + P - 1);
+  double* grid = reinterpret_cast<double*>(smem);
+  R* wts = reinterpret_cast<R*>(grid + maxcell);     // kSpreadChunk x 3 x P
+  R* win = wts + kSpreadChunk * 3 * P;               // (NW + 1) x P
+  int* base = reinterpret_cast<int*>(win + (NW + 1) * P);   // kSpreadChunk x 3
+  const int start = d.offsets[tile], end = d.offsets[tile + 1];
+  if (threadIdx.x == 0) d.counts[tile] = 0;        // ready for the next binning pass
+  if (start == end) return;
+  for (int k = threadIdx.x; k < ncell; k += blockDim.x) grid[k] = 0.0;
+  for (int k = threadIdx.x; k < (NW + 1) * P; k += blockDim.x) win[k] = d.win[k];
+  __syncthreads();
+  for (int c0 = start; c0 < end; c0 += kSpreadChunk) {
+    const int nc = min(kSpreadChunk, end - c0);
+    // weights: one task per (particle, dimension); q folded into x
+    for (int t = threadIdx.x; t < nc * 3; t += blockDim.x) {
+      const int j = t / 3, dim = t - 3 * j;
+      const Record<R> rec = d.sorted[c0 + j];
+      int gm;
+      R tau;
+      const int Md = dim == 0 ? d.M1 : (dim == 1 ? d.M2 : d.M3);
+      const int od = dim == 0 ? o1 : (dim == 1 ? o2 : o3);
+      Coord<R>::stencil(rec, dim, Md, P, gm, tau);
+      R w[P];
+      eval_window<R, P, NW>(win, tau, w);
+      const R sc = dim == 0 ? rec.q : R(1);
+#pragma unroll
+      for (int p = 0; p < P; ++p) wts[(j * 3 + dim) * P + p] = w[p] * sc;
+      base[j * 3 + dim] = gm - od;
+    }
+    __syncthreads();
+    // accumulation: one task per (particle, z offset), the P x P block of that plane
+    for (int t = threadIdx.x; t < nc * P; t += blockDim.x) {
+      const int j = t / P, cz = t - j * P;
+      const R* wj = wts + j * 3 * P;
+      R wx[P], wy[P];
+#pragma unroll
+      for (int a = 0; a < P; ++a) {
+        wx[a] = wj[a];
+        wy[a] = wj[P + a];
+      }
+      const R wz = wj[2 * P + cz];
+      double* plane = grid + ((base[j * 3 + 2] + cz) * E2 + base[j * 3 + 1]) * E1 + base[j * 3];
+#pragma unroll
+      for (int by = 0; by < P; ++by) {
+        const R v = wy[by] * wz;
+#pragma unroll
+        for (int a = 0; a < P; ++a) atomicAdd(plane + by * E1 + a, static_cast<double>(v * wx[a]));
+      }
+    }
+    __syncthreads();
+  }
+  // write-back: each thread owns one (x, y) column of the tile and walks z
+  const int E12 = E1 * E2;
+  const size_t planesz = static_cast<size_t>(d.M1) * d.M2;
+  for (int k0 = threadIdx.x; k0 < E12; k0 += blockDim.x) {
+    const int y = k0 / E1, x = k0 - y * E1;
+    int gx = o1 + x, gy = o2 + y;
+    gx -= gx >= d.M1 ? d.M1 : 0;
+    gy -= gy >= d.M2 ? d.M2 : 0;
+    R* col = d.rho + static_cast<size_t>(gy) * d.M1 + gx;
+    for (int z = 0; z < E3; ++z) {
+      const R val = static_cast<R>(grid[z * E12 + k0]);
+      int gz = o3 + z;
+      gz -= gz >= d.M3 ? d.M3 : 0;
+      if (val != R(0)) atomic_add_global(col + gz * planesz, val);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ gather
+// L = 2^k >= P lanes per particle.  Lanes 0..2 evaluate the P window values
+// and derivatives of one dimension each and stage them in LDS; lane c < P
+// then sums z-plane c of the stencil against phi; the L partial gradients are
+// reduced with cross-lane shuffles.  F = q G grad_u, G = -h^-T diag(M).
+template <int P>
+struct GatherLanes {
+  static constexpr int L = P <= 2 ? 4 : (P <= 4 ? 4 : (P <= 8 ? 8 : 16));
+};
+
+template <typename R, int P, int NW>
+__global__ void __launch_bounds__(256) k_gather(DevPlan<R> d, R* __restrict__ f, FinalConsts fc,
+                                                double* __restrict__ out7) {
+  constexpr int L = GatherLanes<P>::L;
+  constexpr int G = 256 / L;                          // particles per block
+  if (out7 && blockIdx.x == 0) {
+    __shared__ double red[kNumSums * 16];
+    finalize_sums(d, fc, out7, red);
+  }
+  extern __shared__ __align__(16) unsigned char smem[];
+  R* win = reinterpret_cast<R*>(smem);                // (NW + 1) x P
+  R* wt = win + (NW + 1) * P;                         // G x 6 x P: w1 d1 w2 d2 w3 d3
+  for (int k = threadIdx.x; k < (NW + 1) * P; k += blockDim.x) win[k] = d.win[k];
+  __syncthreads();
+  const int grp = threadIdx.x / L, lane = threadIdx.x - grp * L;
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * G + grp;
+  const bool valid = i < d.n;
+  const Record<R> rec = d.sorted[valid ? i : 0];
+  int g1, g2, g3;
+  R t1, t2, t3;
+  Coord<R>::stencil(rec, 0, d.M1, P, g1, t1);
+  Coord<R>::stencil(rec, 1, d.M2, P, g2, t2);
+  Coord<R>::stencil(rec, 2, d.M3, P, g3, t3);
+  R* my = wt + grp * 6 * P;
+  if (lane < 3) {
+    const R tau = lane == 0 ? t1 : (lane == 1 ? t2 : t3);
+    R w[P], dw[P];
+    eval_window_d<R, P, NW>(win, tau, w, dw);
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      my[2 * lane * P + p] = w[p];
+      my[(2 * lane + 1) * P + p] = dw[p];
+    }
+  }
+  __syncthreads();
+  R gx = R(0), gy = R(0), gz = R(0);
+  if (lane < P) {
+    int xi[P];
+#pragma unroll
+    for (int a = 0; a < P; ++a) {
+      const int x = g1 + a;
+      xi[a] = x >= d.M1 ? x - d.M1 : x;
+    }
+    R w1[P], d1[P];
+#pragma unroll
+    for (int a = 0; a < P; ++a) {
+      w1[a] = my[a];
+      d1[a] = my[P + a];
+    }
+    int z = g3 + lane;
+    z -= z >= d.M3 ? d.M3 : 0;
+    R sxz = R(0), syz = R(0), s0z = R(0);
+#pragma unroll
+    for (int b = 0; b < P; ++b) {
+      int y = g2 + b;
+      y -= y >= d.M2 ? d.M2 : 0;
+      const R* row = d.phi + (static_cast<size_t>(z) * d.M2 + y) * d.M1;
+      R sx = R(0), s0 = R(0);
+#pragma unroll
+      for (int a = 0; a < P; ++a) {
+        const R v = row[xi[a]];
+        sx += v * d1[a];
+        s0 += v * w1[a];
+      }
+      const R w2 = my[2 * P + b], d2 = my[3 * P + b];
+      sxz += sx * w2;
+      s0z += s0 * w2;
+      syz += s0 * d2;
+    }
+    gx = sxz * my[4 * P + lane];
+    gy = syz * my[4 * P + lane];
+    gz = s0z * my[5 * P + lane];
+  }
+#pragma unroll
+  for (int off = L / 2; off > 0; off >>= 1) {
+    gx += __shfl_xor(gx, off, 64);
+    gy += __shfl_xor(gy, off, 64);
+    gz += __shfl_xor(gz, off, 64);
+  }
+  if (lane == 0 && valid) {
+    const R qk = rec.q * d.coulomb_k;
+    const int64_t j = d.perm[i];
+    f[3 * j + 0] = qk * (d.G[0] * gx + d.G[1] * gy + d.G[2] * gz);
+    f[3 * j + 1] = qk * (d.G[3] * gx + d.G[4] * gy + d.G[5] * gz);
+    f[3 * j + 2] = qk * (d.G[6] * gx + d.G[7] * gy + d.G[8] * gz);
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+template <typename R, int P, int NW>
+static hipError_t spread_nw(const DevPlan<R>& d, hipStream_t s) {
+  const size_t lds = lds_spread(d);
+  if (lds > 65536)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spread<R, P, NW>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+  hipLaunchKernelGGL((k_spread<R, P, NW>), dim3(d.ntiles), dim3(256), lds, s, d);
+  return hipGetLastError();
+}
+
+template <typename R, int P, int NW>
+static hipError_t gather_nw(const DevPlan<R>& d, R* f, FinalConsts c, double* out7, hipStream_t s) {
+  constexpr int G = 256 / GatherLanes<P>::L;
+  const int nb = static_cast<int>((d.n + G - 1) / G);
+  const size_t lds = ((NW + 1) * P + G * 6 * P) * sizeof(R);
+  hipLaunchKernelGGL((k_gather<R, P, NW>), dim3(nb), dim3(256), lds, s, d, f, c, out7);
+  return hipGetLastError();
+}
+
+template <typename R, int P>
+hipError_t spread_launch(const DevPlan<R>& d, hipStream_t s) {
+  switch (d.nw) {
+    case 8: return spread_nw<R, P, 8>(d, s);
+    case 12: return spread_nw<R, P, 12>(d, s);
+    case 16: return spread_nw<R, P, 16>(d, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename R, int P>
+hipError_t gather_launch(const DevPlan<R>& d, R* f, FinalConsts c, double* out7, hipStream_t s) {
+  switch (d.nw) {
+    case 8: return gather_nw<R, P, 8>(d, f, c, out7, s);
+    case 12: return gather_nw<R, P, 12>(d, f, c, out7, s);
+    case 16: return gather_nw<R, P, 16>(d, f, c, out7, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template hipError_t spread_launch<float, ESP_P>(const DevPlan<float>&, hipStream_t);
+template hipError_t spread_launch<double, ESP_P>(const DevPlan<double>&, hipStream_t);
+template hipError_t gather_launch<float, ESP_P>(const DevPlan<float>&, float*, FinalConsts, double*,
+                                                hipStream_t);
+template hipError_t gather_launch<double, ESP_P>(const DevPlan<double>&, double*, FinalConsts, double*,
+                                                 hipStream_t);
+
+}  // namespace espx

@@ -85,7 +85,7 @@ SIGNATURES = [
     ("esp_stage_name", ctypes.c_char_p, [ctypes.c_int]),
     ("esp_version", ctypes.c_char_p, []),
 ]
-NUM_STAGES = 9
+NUM_STAGES = 7
 
 _lib_handle = None
 
