@@ -153,17 +153,22 @@ def config3(seed=0):
 
 
 def membrane(n_dipoles: int = 125_000, n_water: int = 250_000, L=(25.0, 25.0, 20.0),
-             config: int = 4, seed: int = 0):
-    """Two Gaussian sheets of +-0.5 dipole pairs in a water slab."""
+             config: int = 4, seed: int = 0, sheet_offset: float = 2.0, sheet_sigma: float = 0.5,
+             water_gap: float = 3.0):
+    """Two Gaussian sheets of +-0.5 dipole pairs (centres at the mid-plane +-
+    sheet_offset) and water triplets whose centres are at least water_gap
+    from the mid-plane."""
     rng = rng_for(config, seed)
     Lx, Ly, Lz = L
+    if not water_gap < Lz / 2.0:
+        raise ValueError("water_gap must be below half the slab height")
     h = np.diag([Lx, Ly, Lz])
     zc = Lz / 2.0
     half = n_dipoles // 2
     sheets = []
     for sign, n in ((+1, half), (-1, n_dipoles - half)):
         xy = rng.random((n, 2)) * [Lx, Ly]
-        z = rng.normal(zc + sign * 2.0, 0.5, size=n)
+        z = rng.normal(zc + sign * sheet_offset, sheet_sigma, size=n)
         head = np.column_stack([xy, z + sign * 0.05])     # outward-pointing dipole
         tail = np.column_stack([xy, z - sign * 0.05])
         sheets.append((head, tail))
@@ -172,8 +177,8 @@ def membrane(n_dipoles: int = 125_000, n_water: int = 250_000, L=(25.0, 25.0, 20
                           for hd, tl in sheets])
     centres = np.empty((0, 3))
     while centres.shape[0] < n_water:
-        cand = rng.random((2 * n_water, 3)) * [Lx, Ly, Lz]
-        cand = cand[np.abs(cand[:, 2] - zc) >= 3.0]
+        cand = rng.random((2 * n_water + 16, 3)) * [Lx, Ly, Lz]
+        cand = cand[np.abs(cand[:, 2] - zc) >= water_gap]
         centres = np.concatenate([centres, cand])
     centres = centres[:n_water]
     pos_w, q_w = place_triplets(rng, centres)
