@@ -7,8 +7,12 @@ of the workload, inputs already resident in device memory.
 
 Workload (default): bulk-water-shaped system, 10,000 rigid 3-site triplets in
 a cubic 6.7 nm cell (N = 30,000), tolerance 1e-5, seeded synthetic input.
-The headline value is the FP32 path; the plain FP64 path (analytic
-parameters) is timed beside it on the same input.
+The headline value is the FP32 path with learned parameters (the
+registered proposer; the analytic rule if it declines); the FP32 path with
+the analytic rule and the plain FP64 path (analytic parameters) are timed
+beside it on the same input.  The CPU leg runs the oracle: the baseline
+timing, parity at identical parameters, and the error of every GPU result
+against an exact reference.
 
 Prints ONE JSON line.  See DESIGN.md for the byte model behind "roofline".
 """
@@ -58,6 +62,111 @@ def run_plan(plan, xyz, q, steps, warmup, torch):
     return dt, f, out7
 
 
+KERNEL_SOURCES = {
+    "spread": ("esp_stencil.hip", "esp_common.h", "esp_device.h"),
+    "gather": ("esp_stencil.hip", "esp_common.h", "esp_device.h"),
+    "bin": ("esp_kernels.hip", "esp_common.h", "esp_device.h"),
+    "scatter": ("esp_kernels.hip", "esp_common.h", "esp_device.h"),
+    "fft_xy": ("esp_kernels.hip", "esp_common.h", "esp_device.h"),
+    "fft_z": ("esp_kernels.hip", "esp_common.h", "esp_device.h"),
+    "fft_xy_inv": ("esp_kernels.hip", "esp_common.h", "esp_device.h"),
+}
+
+
+def sources_sha(kernel):
+    import hashlib
+    hsh = hashlib.sha256()
+    for name in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_2601_00161_amd", "csrc", name), "rb") as f:
+            hsh.update(f.read())
+    return hsh.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload_key):
+    """HBM bytes per launch from the committed counter summary, or None when
+    there is none for this kernel and workload or the kernel's sources have
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_water30k.md")
+    if not os.path.exists(path):
+        return None
+    want = sources_sha(kernel)
+    for line in open(path):
+        if line.startswith("TRAFFIC "):
+            kv = dict(item.split("=", 1) for item in line.split()[1:])
+            if kv.get("kernel") == kernel and kv.get("workload") == workload_key and kv.get("sources") == want:
+                return float(kv["bytes_per_launch"])
+    return None
+
+
+def oracle_leg(h, r32, q32, plans, headline):
+    """CPU side (the oracle, FP64): baseline timing, parity of each GPU plan at
+    identical parameters, and the headline's error against an exact reference
+    (the oracle's ESP at Delta = 1e-11, P = 12, whose CPU tests pin it to
+    classical Ewald) with the oracle's real-space part added."""
+    from oracle import esp_direct, esp_grid
+    from oracle.pswf import c_from_tol
+    r64, q64 = r32.astype(np.float64), q32.astype(np.float64)
+    N = len(q64)
+
+    def gp(prm):
+        return esp_grid.GridParams(prm["c_split"], prm["c_spread"], prm["P"], tuple(prm["M"]), prm["rc"])
+
+    def w6(W):
+        return np.array([W[0, 0], W[1, 1], W[2, 2], W[0, 1], W[0, 2], W[1, 2]])
+
+    out = {"parity_vs_oracle": {}}
+    refs = {}
+    for name, (plan, f, o) in plans.items():
+        prm = plan.params
+        key = (prm["c_split"], prm["P"], tuple(prm["M"]))
+        if key not in refs:
+            refs[key] = esp_grid.esp_grid(h, r64, q64, gp(prm))
+        ref = refs[key]
+        fo, oo = f.cpu().numpy().astype(np.float64), o.cpu().numpy()
+        out["parity_vs_oracle"][name] = {
+            "energy": float(abs(oo[0] - ref.energy) / abs(ref.energy)),
+            "virial": float(np.linalg.norm(oo[1:] - w6(ref.virial)) / np.linalg.norm(w6(ref.virial))),
+            "forces_rms": float(np.sqrt(np.sum((fo - ref.forces) ** 2) / np.sum(ref.forces ** 2)))}
+
+    # CPU baseline: the oracle's gridded ESP at the FP64 plan's parameters
+    p64 = plans["fp64_analytic"][0].params
+    reps, t0 = 0, time.perf_counter()
+    while reps < 1 or time.perf_counter() - t0 < 10.0:
+        esp_grid.esp_grid(h, r64, q64, gp(p64))
+        reps += 1
+    tc = (time.perf_counter() - t0) / reps
+    out["cpu_baseline"] = {
+        "value": N / tc / 1e6, "unit": "M particle-steps/s", "cores": 1, "kind": "oracle",
+        "sample": f"{reps} full steps of the oracle's gridded FP64 ESP (numpy, single thread) on the same "
+                  f"N={N} workload at the FP64 plan's parameters; host has {len(os.sched_getaffinity(0))} cores"}
+
+    # exact reference of the total Coulomb energy, virial and forces
+    c_ref = c_from_tol(1e-11)
+    M_ref = int(np.ceil(1.07 * max(np.linalg.norm(h, axis=0)) * c_ref / (np.pi * 0.9)))
+    M_ref += M_ref % 2
+    ex_F = esp_grid.esp_grid(h, r64, q64, esp_grid.GridParams(c_ref, c_ref, 12, (M_ref,) * 3, 0.9))
+    U_N, W_N, F_N = esp_direct.real_space(h, r64, q64, c_ref, 0.9)
+    E_ex, W_ex, F_ex = ex_F.energy + U_N, ex_F.virial + W_N, ex_F.forces + F_N
+    acc = {}
+    for name, (plan, f, o) in plans.items():
+        prm = plan.params
+        u_n, w_n, f_n = esp_direct.real_space(h, r64, q64, prm["c_split"], prm["rc"])
+        oo = o.cpu().numpy()
+        W = np.array([[oo[1], oo[4], oo[5]], [oo[4], oo[2], oo[6]], [oo[5], oo[6], oo[3]]]) + w_n
+        F = f.cpu().numpy().astype(np.float64) + f_n
+        dg = [(W[a, a] - W_ex[a, a]) for a in range(3)]
+        od = [(W[a, b] - W_ex[a, b]) for a, b in ((0, 1), (0, 2), (1, 2))]
+        acc[name] = {
+            "energy": float(abs(oo[0] + u_n - E_ex) / abs(E_ex)),
+            "pressure_diag": float(np.linalg.norm(dg) / np.linalg.norm(np.diag(W_ex))),
+            "pressure_offdiag": float(np.linalg.norm(od) / np.linalg.norm([W_ex[0, 1], W_ex[0, 2], W_ex[1, 2]])),
+            "forces_rms": float(np.sqrt(np.sum((F - F_ex) ** 2) / np.sum(F_ex ** 2)))}
+    out["accuracy_vs_exact"] = acc
+    out["accuracy_reference"] = (f"total Coulomb (real + reciprocal) from the oracle's ESP at Delta=1e-11, P=12, "
+                                 f"M={M_ref}^3; each GPU result gets the oracle's real-space part at its own c")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -65,8 +174,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--tol", type=float, default=1e-5)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--tile", type=int, default=0, help="spreading tile edge (0 = plan default)")
+    ap.add_argument("--params", default="learned", choices=["learned", "analytic"],
+                    help="parameter source of the FP32 headline plan")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="first run 5 plain device copies of MIB MiB (float32), the known-size "
+                         "kernel that calibrates the FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -75,18 +189,27 @@ def main():
 
     import torch
 
-    from oracle import esp_grid
     from paper_2601_00161_amd import synth
-    from paper_2601_00161_amd.esp import Plan
+    from paper_2601_00161_amd.esp import PARAMS, Plan
 
     dev = torch.device("cuda:0")
+    if args.copy_calib > 0:
+        n = args.copy_calib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"copy calibration: 5 copies of {args.copy_calib} MiB", file=sys.stderr, flush=True)
+        del a, b
     h, r, q = synth.config2(args.seed)
     N = len(q)
     r32, q32 = r.astype(np.float32), q.astype(np.float32)
-
-    # ---- FP32 headline path ---------------------------------------------------
-    p32 = Plan(h, N, args.tol, precision="fp32", tile=args.tile)
     x32, c32 = torch.from_numpy(r32).to(dev), torch.from_numpy(q32).to(dev)
+    x64, c64 = torch.from_numpy(r32.astype(np.float64)).to(dev), torch.from_numpy(q32.astype(np.float64)).to(dev)
+
+    # ---- FP32 headline path (learned parameters) --------------------------------
+    p32 = Plan(h, N, args.tol, precision="fp32", params=args.params, tile=args.tile)
     for _ in range(10):                      # first launches load code objects
         p32.forces(x32, c32)
     torch.cuda.synchronize()
@@ -102,42 +225,20 @@ def main():
     dom_ms, dom_n = p32.profile_read()[dominant]
     p32.profile([], 0)
 
-    # ---- plain FP64 path ----------------------------------------------------------
+    # ---- FP32 with the analytic rule (the proposer's gain) ---------------------
+    pa = Plan(h, N, args.tol, precision="fp32", tile=args.tile)
+    dta, fa, oa = run_plan(pa, x32, c32, args.steps, args.warmup, torch)
+
+    # ---- plain FP64 path, analytic parameters -------------------------------------
     p64 = Plan(h, N, args.tol, precision="fp64", tile=args.tile)
-    x64, c64 = torch.from_numpy(r32.astype(np.float64)).to(dev), torch.from_numpy(q32.astype(np.float64)).to(dev)
     dt64, f64, o64 = run_plan(p64, x64, c64, args.steps, args.warmup, torch)
 
-    # ---- parity of both against the oracle at identical parameters -----------------
-    def parity(plan, f, o):
-        prm = plan.params
-        ref = esp_grid.esp_grid(h, r32.astype(np.float64), q32.astype(np.float64),
-                                esp_grid.GridParams(prm["c_split"], prm["c_spread"], prm["P"],
-                                                    tuple(prm["M"]), prm["rc"]))
-        f = f.cpu().numpy().astype(np.float64)
-        o = o.cpu().numpy()
-        W = ref.virial
-        w6 = np.array([W[0, 0], W[1, 1], W[2, 2], W[0, 1], W[0, 2], W[1, 2]])
-        return {"energy": float(abs(o[0] - ref.energy) / abs(ref.energy)),
-                "virial": float(np.linalg.norm(o[1:] - w6) / np.linalg.norm(w6)),
-                "forces_rms": float(np.sqrt(np.sum((f - ref.forces) ** 2) / np.sum(ref.forces ** 2)))}
-
-    par32 = parity(p32, f32, o32)
-    par64 = parity(p64, f64, o64)
-
-    # ---- CPU baseline: the oracle's gridded ESP (FP64) on the host ----------------
     cpu = None
+    extra = {}
     if not args.no_cpu:
-        prm = p64.params
-        gp = esp_grid.GridParams(prm["c_split"], prm["c_spread"], prm["P"], tuple(prm["M"]), prm["rc"])
-        reps, t0 = 0, time.perf_counter()
-        while reps < 1 or time.perf_counter() - t0 < 10.0:
-            esp_grid.esp_grid(h, r32.astype(np.float64), q32.astype(np.float64), gp)
-            reps += 1
-        tc = (time.perf_counter() - t0) / reps
-        cpu = {"value": N / tc / 1e6, "unit": "M particle-steps/s", "cores": 1, "kind": "oracle",
-               "sample": f"{reps} full steps of the oracle's gridded FP64 ESP (numpy, single thread) on the "
-                         f"same N={N} workload at the FP64 plan's parameters; "
-                         f"host has {len(os.sched_getaffinity(0))} cores available"}
+        extra = oracle_leg(h, r32, q32, {"fp32_headline": (p32, f32, o32), "fp32_analytic": (pa, fa, oa),
+                                         "fp64_analytic": (p64, f64, o64)}, "fp32_headline")
+        cpu = extra.pop("cpu_baseline")
 
     prm = p32.params
     G = prm["M"][0] * prm["M"][1] * prm["M"][2]
@@ -145,8 +246,17 @@ def main():
     avg_s = dom_ms / dom_n / 1e3
     bytes_dom = stage_bytes(dominant, N, G, S, 4)
     achieved = bytes_dom / avg_s / 1e9
+    workload_key = f"water30k_tol{args.tol:g}_P{prm['P']}_M{prm['M'][0]}x{prm['M'][1]}x{prm['M'][2]}"
+    traffic = measured_traffic(dominant, workload_key)
     value = N * args.steps / dt32 / 1e6
     v64 = N * args.steps / dt64 / 1e6
+    va = N * args.steps / dta / 1e6
+    src = {v: k for k, v in PARAMS.items()}[prm["params_source"]]
+
+    def brief(p):
+        return {"source": {v: k for k, v in PARAMS.items()}[p.params["params_source"]],
+                "delta": p.params["delta"], "c": p.params["c_split"], "P": p.params["P"], "M": p.params["M"]}
+
     line = {
         "metric": "M particle-steps/s (E+F+virial) at 1e-5 rel err: FP32+learned vs plain FP64",
         "value": round(value, 3),
@@ -161,16 +271,18 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "bulk-water-shaped, 10,000 rigid 3-site triplets, cubic 6.7 nm, N=30000, tol 1e-5",
-                   "seed": args.seed, "params": "analytic", "c": prm["c_split"], "P": prm["P"],
-                   "M": prm["M"], "rc": prm["rc"], "tile": prm["tile"]},
-        "fp64_baseline": {"value": round(v64, 3), "ms_per_step": dt64 / args.steps * 1e3,
-                          "params": "analytic", "M": p64.params["M"], "P": p64.params["P"]},
+                   "seed": args.seed, "params": src, "delta": prm["delta"], "c": prm["c_split"], "P": prm["P"],
+                   "M": prm["M"], "rc": prm["rc"], "tile": prm["tile"],
+                   "predicted_log10_err": prm["predicted_log10_err"] if src == "learned" else None},
+        "fp64_baseline": {"value": round(v64, 3), "ms_per_step": dt64 / args.steps * 1e3, **brief(p64)},
         "speedup_vs_fp64": value / v64,
-        "parity_vs_oracle": {"fp32": par32, "fp64": par64},
+        "fp32_analytic": {"value": round(va, 3), "ms_per_step": dta / args.steps * 1e3, **brief(pa)},
+        "learned_gain_vs_analytic": value / va,
+        **extra,
         "stage_ms_fp32": {k: v[0] / v[1] for k, v in stages.items()},
         "roofline": {"kernel": dominant, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_launch": bytes_dom, "avg_launch_us": avg_s * 1e6},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "bytes_per_launch": bytes_dom, "avg_launch_us": avg_s * 1e6, "workload_key": workload_key},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

@@ -84,7 +84,7 @@ enum { ESP_ISO = 0, ESP_SEMI = 1, ESP_ANISO = 2, ESP_FLEX = 3 };
  *   with sigma = grid_sigma.
  * With params = ESP_EXPLICIT the fields c_split, c_spread, P, M are used
  * as given (each must be set).  With ESP_LEARNED the parameters come from the
- * proposer registered with esp_set_proposer (analytic fallback otherwise). */
+ * proposer registered with esp_proposer_set (analytic fallback otherwise). */
 typedef struct {
   int precision;       /* ESP_FP32 (default) or ESP_FP64 */
   int params;          /* ESP_ANALYTIC (default), ESP_EXPLICIT, ESP_LEARNED */
@@ -115,6 +115,8 @@ typedef struct {
   double lambda0_split, C0_split, psi0_split;
   double volume;
   int params_source;   /* ESP_ANALYTIC / ESP_EXPLICIT / ESP_LEARNED actually used */
+  double predicted_log10_err[4];  /* ESP_LEARNED: the proposer's prediction, else 0 */
+  double predicted_cost;          /* ESP_LEARNED: cost-model value of the choice */
 } esp_params;
 
 void esp_opts_default(esp_opts *o);
@@ -209,6 +211,95 @@ double esp_c_from_delta(double delta);
 esp_status esp_profile_enable(esp_plan_t *p, unsigned stage_mask, int max_launches);
 esp_status esp_profile_read(esp_plan_t *p, double *total_ms, int64_t *launches);
 const char *esp_stage_name(int stage);
+
+/* ---- learned parameter proposer ------------------------------------------
+ * A small MLP (tanh hidden layers, linear output), trained and evaluated on
+ * the GPU by the library's own kernels (FP32).  Parameters are one flat
+ * array, layer by layer: W (dims[l+1] x dims[l], row-major) then b.
+ * All x / t / mask / y / grad / loss pointers are device pointers; B rows.
+ * esp_mlp_gradient: forward + backward of the masked mean squared error
+ *   sum mask (y - t)^2 / sum mask; writes the gradient (num_params floats)
+ *   and the loss (one float) when the pointers are non-NULL.
+ * esp_mlp_train_step: the same, then one Adam step (beta 0.9 / 0.999). */
+typedef struct esp_mlp_s esp_mlp_t;
+esp_status esp_mlp_create(int nlayer, const int *dims, uint64_t seed, esp_mlp_t **out);
+int64_t esp_mlp_num_params(const esp_mlp_t *m);
+esp_status esp_mlp_set_params(esp_mlp_t *m, const float *host, int64_t n);
+esp_status esp_mlp_get_params(const esp_mlp_t *m, float *host, int64_t n);
+esp_status esp_mlp_set_stream(esp_mlp_t *m, void *stream);
+esp_status esp_mlp_forward(esp_mlp_t *m, const float *x, int64_t B, float *y);
+esp_status esp_mlp_gradient(esp_mlp_t *m, const float *x, const float *t, const float *mask, int64_t B,
+                            float *grad, float *loss);
+esp_status esp_mlp_train_step(esp_mlp_t *m, const float *x, const float *t, const float *mask,
+                              int64_t B, float lr, float *loss);
+void esp_mlp_destroy(esp_mlp_t *m);
+
+/* Registration of a trained MLP as the ESP_LEARNED proposer.  The network
+ * maps the features (log10 Delta, P, sigma, log10 of the charge density
+ * n/V), each normalised as (f - in_mean) / in_std, to normalised log10
+ * relative errors of {energy, diagonal pressure, off-diagonal pressure, RMS
+ * force} (de-normalised with out_mean / out_std).  The cell shape enters
+ * through the grid rule, which sizes M_d per cell vector.  esp_plan with
+ * ESP_LEARNED scores a grid of candidates (Delta from 1e-2 to 1e-7 in
+ * quarter decades, P from ceil(-log10 Delta) - 1 (at least 3) to + 2, sigma
+ * from 0.85 to 1.3, plus the analytic rule's own choice) on the GPU, keeps
+ * those whose predicted errors of the components the coupling needs
+ * (energy, diagonal pressure and force; plus off-diagonal for ESP_FLEX) are
+ * below log10(tol) - margin[component], and picks the cheapest by the cost
+ * model t = cost[0] + cost[1] N P^3 + cost[2] G log2 G + cost[3] N
+ * + cost[4] G (G = M1 M2 M3).  If none qualifies it takes the candidate
+ * with the smallest predicted excess and returns ESP_WARN_FALLBACK; without
+ * a registered network ESP_LEARNED uses the analytic rule and returns
+ * ESP_WARN_FALLBACK.  The MLP is borrowed and must outlive the
+ * registration; NULL clears it. */
+#define ESP_PROPOSER_FEATURES 4
+typedef struct {
+  const esp_mlp_t *mlp;
+  double in_mean[ESP_PROPOSER_FEATURES], in_std[ESP_PROPOSER_FEATURES];
+  double out_mean[4], out_std[4];
+  double margin[4];
+  double cost[5];
+} esp_proposer;
+esp_status esp_proposer_set(const esp_proposer *p);
+
+/* ---- batches of independent systems ------------------------------------
+ * Many replicas (each its own cell, particle count and tolerance) evaluated
+ * together: every stage is ONE launch over all replicas (spreading and
+ * gather: one launch per distinct window support P and window degree), so
+ * the launch count per step does not grow with the number of replicas.
+ *   esp_batch_plan: nrep replicas; h: 9*nrep doubles (host), n, tol: nrep
+ *     entries (host); o applies to every replica (o->precision, coupling,
+ *     rc, params ...); tiles (host, may be NULL) overrides the spreading tile
+ *     edge per replica (0 = the plan's rule).
+ *   xyz, q, f: the replicas' arrays concatenated in replica order (3*sum n,
+ *     sum n, 3*sum n; device); out7: 7*nrep doubles (device), replica r at
+ *     out7 + 7*r.  out7 may be NULL for esp_batch_forces.
+ *   esp_batch_set_box: new cell of replica r (host, 9 doubles); the update
+ *     is enqueued on the batch stream.
+ *   esp_batch_set_graph: with enable != 0 each call records its launches
+ *     once into a HIP graph (re-recorded when the pointers or the kind of
+ *     call change) and replays it; the graph holds no memset nodes.
+ *   esp_batch_check: synchronise and report device-side errors of any
+ *     replica (as esp_check).
+ * Errors and warnings of a replica's planning are returned by
+ * esp_batch_plan with the replica index in the error text. */
+esp_status esp_batch_plan(int nrep, const double *h, const int64_t *n, const double *tol,
+                          const esp_opts *o, const int *tiles, esp_batch_t **out);
+esp_status esp_batch_energy_virial(esp_batch_t *b, const float *xyz, const float *q, double *out7);
+esp_status esp_batch_forces(esp_batch_t *b, const float *xyz, const float *q, float *f,
+                            double *out7);
+esp_status esp_batch_energy_virial_f64(esp_batch_t *b, const double *xyz, const double *q,
+                                       double *out7);
+esp_status esp_batch_forces_f64(esp_batch_t *b, const double *xyz, const double *q, double *f,
+                                double *out7);
+esp_status esp_batch_set_box(esp_batch_t *b, int r, const double h[9]);
+esp_status esp_batch_set_stream(esp_batch_t *b, void *stream);
+esp_status esp_batch_set_graph(esp_batch_t *b, int enable);
+esp_status esp_batch_check(esp_batch_t *b);
+esp_status esp_batch_get_params(const esp_batch_t *b, int r, esp_params *out);
+int esp_batch_num_launches(const esp_batch_t *b, int forces);
+const char *esp_batch_last_error(const esp_batch_t *b);
+void esp_batch_destroy(esp_batch_t *b);
 
 /* Library version string. */
 const char *esp_version(void);

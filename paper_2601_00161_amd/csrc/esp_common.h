@@ -275,8 +275,8 @@ __device__ __forceinline__ void atomic_add_global(R* p, R v) {
 // neutralising-background terms (eq. Corr).  Run by one workgroup of a kernel
 // launched after the z-pass, in a fixed order.
 template <typename R>
-__device__ void finalize_sums(const DevPlan<R>& d, const FinalConsts& fc, double* __restrict__ out,
-                              double* red) {
+__device__ void finalize_sums(const DevPlan<R>& d, double* __restrict__ out, double* red) {
+  const FinalConsts& fc = d.fin;
   double v[kNumSums];
 #pragma unroll
   for (int k = 0; k < kNumSums; ++k) v[k] = 0.0;
@@ -307,11 +307,35 @@ __device__ void finalize_sums(const DevPlan<R>& d, const FinalConsts& fc, double
 }
 
 
+// The plan of the current workgroup and the block index within that plan's
+// range: the kernel argument itself, or (batched launch) the plan whose block
+// range holds blockIdx.x, found by bisection of the block offsets.
+template <typename R>
+__device__ __forceinline__ const DevPlan<R>& plan_of(const KArg<R, false>& a, int& blk) {
+  blk = static_cast<int>(blockIdx.x);
+  return a.d;
+}
+template <typename R>
+__device__ __forceinline__ const DevPlan<R>& plan_of(const KArg<R, true>& a, int& blk) {
+  const int b = static_cast<int>(blockIdx.x);
+  int lo = 0, hi = a.nrep;                  // boff[lo] <= b < boff[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (a.boff[mid] <= b) lo = mid; else hi = mid;
+  }
+  blk = b - a.boff[lo];
+  return a.plans[lo];
+}
+
 // Spreading and gather launchers for one window support P (one translation
 // unit per P, see esp_stencil.hip).
 template <typename R, int P>
 hipError_t spread_launch(const DevPlan<R>& d, hipStream_t s);
 template <typename R, int P>
-hipError_t gather_launch(const DevPlan<R>& d, R* f, FinalConsts c, double* out7, hipStream_t s);
+hipError_t gather_launch(const DevPlan<R>& d, R* f, double* out7, hipStream_t s);
+template <typename R, int P>
+hipError_t spread_launch_batch(const BatchLaunch<R>& b, hipStream_t s);
+template <typename R, int P>
+hipError_t gather_launch_batch(const BatchLaunch<R>& b, R* f, double* out7, hipStream_t s);
 
 }  // namespace espx

@@ -48,6 +48,14 @@ struct FftLen {
   int tw;                // offset of exp(-2 pi i k / n), k < n, in the twiddle table
 };
 
+// Constants of the final sums (self energy, background, units).
+struct FinalConsts {
+  double inv2V;        // 1 / (2 V)
+  double self_coef;    // psi(0) / (2 C0 rc)
+  double bg_coef;      // 2 pi Ic / V  (U_corr = -bg_coef Q^2)
+  double coulomb_k;
+};
+
 template <typename R>
 struct DevPlan {
   // sizes
@@ -92,22 +100,48 @@ struct DevPlan {
   double* qpart;                   // nbin x 2 partial sums (sum q, sum q^2)
   int* flags;                      // bit 0: non-finite input; bit 1: inconsistent tile counts
   int bin_lds;                     // tile histogram of the binning pass fits in LDS
+  FinalConsts fin;                 // final-sum constants (updated by esp_set_box)
+  int64_t pofs;                    // batched launches: first particle of this plan in the
+  int rep;                         // concatenated inputs, and its index (0 for single plans)
+};
+
+// Lanes per particle of the gather kernel (a power of two >= P).
+constexpr int gather_lanes(int P) { return P <= 4 ? 4 : (P <= 8 ? 8 : 16); }
+
+// Kernel argument: one plan by value, or, for a batched launch, a device array
+// of plans and the first block of each plan's block range (nrep + 1 entries).
+template <typename R, bool BATCH>
+struct KArg;
+template <typename R>
+struct KArg<R, false> {
+  DevPlan<R> d;
+};
+template <typename R>
+struct KArg<R, true> {
+  const DevPlan<R>* plans;
+  const int* boff;
+  int nrep;
+};
+
+// Geometry of one batched launch (blocks, threads, dynamic LDS) over a range
+// of plans; P and nw select the spreading / gather instantiation.
+template <typename R>
+struct BatchLaunch {
+  const DevPlan<R>* plans;
+  const int* boff;
+  int nrep, nblk, nth;
+  size_t lds;
+  int P, nw;
 };
 
 // Launchers (defined in esp_kernels.hip, instantiated for float and double).
 template <typename R>
 hipError_t launch_bin(const DevPlan<R>& d, const R* xyz, const R* q, hipStream_t s);
-struct FinalConsts {
-  double inv2V;        // 1 / (2 V)
-  double self_coef;    // psi(0) / (2 C0 rc)
-  double bg_coef;      // 2 pi Ic / V  (U_corr = -bg_coef Q^2)
-  double coulomb_k;
-};
 template <typename R>
 hipError_t launch_scatter(const DevPlan<R>& d, hipStream_t s);
 // Final sums into out7 (one workgroup) after a z-pass in energy mode.
 template <typename R>
-hipError_t launch_finalize(const DevPlan<R>& d, FinalConsts c, double* out7, hipStream_t s);
+hipError_t launch_finalize(const DevPlan<R>& d, double* out7, hipStream_t s);
 template <typename R>
 hipError_t launch_spread(const DevPlan<R>& d, hipStream_t s);
 template <typename R>
@@ -121,7 +155,27 @@ template <typename R>
 hipError_t launch_fft_xy_inv(const DevPlan<R>& d, hipStream_t s);
 // Gather; when out7 is non-null its block 0 also writes the final sums.
 template <typename R>
-hipError_t launch_gather(const DevPlan<R>& d, R* f, FinalConsts c, double* out7, hipStream_t s);
+hipError_t launch_gather(const DevPlan<R>& d, R* f, double* out7, hipStream_t s);
+
+// Batched launches: one launch per stage covers every plan of the range
+// (xyz, q, f are the concatenated arrays, out7 holds 7 values per plan;
+// fft_xy works on each plan's own rho / spec).
+template <typename R>
+hipError_t launch_bin_batch(const BatchLaunch<R>& b, const R* xyz, const R* q, hipStream_t s);
+template <typename R>
+hipError_t launch_scatter_batch(const BatchLaunch<R>& b, hipStream_t s);
+template <typename R>
+hipError_t launch_spread_batch(const BatchLaunch<R>& b, hipStream_t s);
+template <typename R>
+hipError_t launch_fft_xy_batch(const BatchLaunch<R>& b, hipStream_t s);
+template <typename R>
+hipError_t launch_fft_z_batch(const BatchLaunch<R>& b, ZMode mode, hipStream_t s);
+template <typename R>
+hipError_t launch_fft_xy_inv_batch(const BatchLaunch<R>& b, hipStream_t s);
+template <typename R>
+hipError_t launch_gather_batch(const BatchLaunch<R>& b, R* f, double* out7, hipStream_t s);
+template <typename R>
+hipError_t launch_finalize_batch(const BatchLaunch<R>& b, double* out7, hipStream_t s);
 template <typename T>
 hipError_t launch_fill(T* p, size_t count, hipStream_t s);
 

@@ -55,16 +55,20 @@ __device__ void block_scan(const int* __restrict__ counts, int* offs, int n, int
 // tile.  Ranks come from an LDS histogram of the block's keys plus one global
 // atomic per occupied tile and block, so no global counter sees more than
 // one atomic per block.  Also accumulates sum q and sum q^2 per block in FP64.
-template <typename R>
-__global__ void __launch_bounds__(256) k_bin(DevPlan<R> d, const R* __restrict__ xyz,
+template <typename R, bool BATCH>
+__global__ void __launch_bounds__(256) k_bin(KArg<R, BATCH> ka, const R* __restrict__ xyz,
                                              const R* __restrict__ q) {
   extern __shared__ int hist[];            // ntiles entries when d.bin_lds
   __shared__ double red[2 * 16];
+  int blk;
+  const DevPlan<R>& d = plan_of(ka, blk);
+  xyz += 3 * d.pofs;
+  q += d.pofs;
   const bool lh = d.bin_lds != 0;
   if (lh)
     for (int k = threadIdx.x; k < d.ntiles; k += blockDim.x) hist[k] = 0;
   __syncthreads();
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t i = static_cast<int64_t>(blk) * blockDim.x + threadIdx.x;
   double v[2] = {0.0, 0.0};
   int key = 0, lr = 0;
   if (i < d.n) {
@@ -99,20 +103,22 @@ __global__ void __launch_bounds__(256) k_bin(DevPlan<R> d, const R* __restrict__
   }
   block_sum<2>(v, red);
   if (threadIdx.x == 0) {
-    d.qpart[2 * blockIdx.x] = v[0];
-    d.qpart[2 * blockIdx.x + 1] = v[1];
+    d.qpart[2 * blk] = v[0];
+    d.qpart[2 * blk + 1] = v[1];
   }
 }
 
 // Cell sort, pass 2.  Every block scans the tile counts itself (they are few)
 // and scatters its particles to offset[key] + rank; block 0 also publishes the
 // offsets for the spreading pass.
-template <typename R>
-__global__ void __launch_bounds__(1024) k_scatter(DevPlan<R> d) {
+template <typename R, bool BATCH>
+__global__ void __launch_bounds__(1024) k_scatter(KArg<R, BATCH> ka) {
   extern __shared__ int offs[];             // ntiles + 1
   __shared__ int part[1024];
+  int blk;
+  const DevPlan<R>& d = plan_of(ka, blk);
   block_scan(d.counts, offs, d.ntiles, part);
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t i = static_cast<int64_t>(blk) * blockDim.x + threadIdx.x;
   if (i < d.n) {
     const int pos = offs[d.keys[i]] + d.ranks[i];
     if (pos >= 0 && pos < d.n) {
@@ -122,21 +128,29 @@ __global__ void __launch_bounds__(1024) k_scatter(DevPlan<R> d) {
       atomicOr(d.flags, 2);                 // inconsistent tile counts
     }
   }
-  if (blockIdx.x == 0)
+  if (blk == 0)
     for (int k = threadIdx.x; k <= d.ntiles; k += blockDim.x) d.offsets[k] = offs[k];
 }
 
-template <typename R>
-__global__ void __launch_bounds__(256) k_finalize(DevPlan<R> d, FinalConsts fc, double* __restrict__ out7) {
+template <typename R, bool BATCH>
+__global__ void __launch_bounds__(256) k_finalize(KArg<R, BATCH> ka, double* __restrict__ out7) {
   __shared__ double red[kNumSums * 16];
-  finalize_sums(d, fc, out7, red);
+  int blk;
+  const DevPlan<R>& d = plan_of(ka, blk);
+  finalize_sums(d, out7 + kNumSums * d.rep, red);
 }
 
 // ------------------------------------------------------------------ FFT xy
-template <typename R>
-__global__ void __launch_bounds__(1024) k_fft_xy(DevPlan<R> d, const R* __restrict__ grid,
-                                                 Cplx<R>* __restrict__ spec, int clear) {
+// grid / spec: explicit operands of a single-plan launch, or null for the
+// plan's own rho / spec (batched launches).
+template <typename R, bool BATCH>
+__global__ void __launch_bounds__(1024) k_fft_xy(KArg<R, BATCH> ka, const R* __restrict__ grid_in,
+                                                 Cplx<R>* __restrict__ spec_in, int clear) {
   extern __shared__ __align__(16) unsigned char smem[];
+  int blk;
+  const DevPlan<R>& d = plan_of(ka, blk);
+  const R* grid = grid_in ? grid_in : d.rho;
+  Cplx<R>* spec = spec_in ? spec_in : d.spec;
   const int M1 = d.M1, M2 = d.M2, H = d.H;
   const int npairs = (M2 + 1) / 2;
   const int L = max(npairs * M1, M2 * H);
@@ -147,7 +161,7 @@ __global__ void __launch_bounds__(1024) k_fft_xy(DevPlan<R> d, const R* __restri
   const int nth = blockDim.x, tid = threadIdx.x;
   for (int k = tid; k < M1; k += nth) tw1[k] = d.tw[d.f1.tw + k];
   for (int k = tid; k < M2; k += nth) tw2[k] = d.tw[d.f2.tw + k];
-  const size_t zoff = static_cast<size_t>(blockIdx.x) * M2 * M1;
+  const size_t zoff = static_cast<size_t>(blk) * M2 * M1;
   const R* plane = grid + zoff;
   R* wplane = const_cast<R*>(grid) + zoff;
   for (int k = tid; k < npairs * M1; k += nth) {
@@ -175,13 +189,15 @@ __global__ void __launch_bounds__(1024) k_fft_xy(DevPlan<R> d, const R* __restri
   }
   __syncthreads();
   res = fft_lines(oth, res, d.f2, H, 1, H, tw2, false);
-  Cplx<R>* out = spec + static_cast<size_t>(blockIdx.x) * M2 * H;
+  Cplx<R>* out = spec + static_cast<size_t>(blk) * M2 * H;
   for (int k = tid; k < M2 * H; k += nth) out[k] = res[k];
 }
 
-template <typename R>
-__global__ void __launch_bounds__(1024) k_fft_xy_inv(DevPlan<R> d) {
+template <typename R, bool BATCH>
+__global__ void __launch_bounds__(1024) k_fft_xy_inv(KArg<R, BATCH> ka) {
   extern __shared__ __align__(16) unsigned char smem[];
+  int blk;
+  const DevPlan<R>& d = plan_of(ka, blk);
   const int M1 = d.M1, M2 = d.M2, H = d.H;
   const int npairs = (M2 + 1) / 2;
   const int L = max(npairs * M1, M2 * H);
@@ -192,7 +208,7 @@ __global__ void __launch_bounds__(1024) k_fft_xy_inv(DevPlan<R> d) {
   const int nth = blockDim.x, tid = threadIdx.x;
   for (int k = tid; k < M1; k += nth) tw1[k] = d.tw[d.f1.tw + k];
   for (int k = tid; k < M2; k += nth) tw2[k] = d.tw[d.f2.tw + k];
-  const Cplx<R>* in = d.spec + static_cast<size_t>(blockIdx.x) * M2 * H;
+  const Cplx<R>* in = d.spec + static_cast<size_t>(blk) * M2 * H;
   for (int k = tid; k < M2 * H; k += nth) A[k] = in[k];
   __syncthreads();
   Cplx<R>* res = fft_lines(A, B, d.f2, H, 1, H, tw2, true);
@@ -212,7 +228,7 @@ __global__ void __launch_bounds__(1024) k_fft_xy_inv(DevPlan<R> d) {
   }
   __syncthreads();
   res = fft_lines(oth, res, d.f1, npairs, M1, 1, tw1, true);
-  R* plane = d.phi + static_cast<size_t>(blockIdx.x) * M2 * M1;
+  R* plane = d.phi + static_cast<size_t>(blk) * M2 * M1;
   for (int k = tid; k < npairs * M1; k += nth) {
     const int p = k / M1, x = k - p * M1;
     plane[(2 * p) * M1 + x] = res[k].x;
@@ -248,13 +264,15 @@ struct Acc {
   }
 };
 
-template <typename R>
-__global__ void __launch_bounds__(256) k_fft_z(DevPlan<R> d, int mode) {
+template <typename R, bool BATCH>
+__global__ void __launch_bounds__(256) k_fft_z(KArg<R, BATCH> ka, int mode) {
   extern __shared__ __align__(16) unsigned char smem[];
+  int blk;
+  const DevPlan<R>& d = plan_of(ka, blk);
   const int M1 = d.M1, M2 = d.M2, M3 = d.M3, H = d.H, cz = d.cz;
   const int ngrp = (H + cz - 1) / cz;
-  const int y = blockIdx.x / ngrp;
-  const int k0 = (blockIdx.x - y * ngrp) * cz;
+  const int y = blk / ngrp;
+  const int k0 = (blk - y * ngrp) * cz;
   const int nc = min(cz, H - k0);
   double* red = reinterpret_cast<double*>(smem);                   // kNumSums x 16
   Cplx<R>* A = reinterpret_cast<Cplx<R>*>(red + kNumSums * 16);
@@ -326,7 +344,7 @@ __global__ void __launch_bounds__(256) k_fft_z(DevPlan<R> d, int mode) {
   block_sum<kNumSums>(sums, red);
   if (tid == 0)
 #pragma unroll
-    for (int k = 0; k < kNumSums; ++k) d.zpart[static_cast<size_t>(blockIdx.x) * kNumSums + k] = sums[k];
+    for (int k = 0; k < kNumSums; ++k) d.zpart[static_cast<size_t>(blk) * kNumSums + k] = sums[k];
   if (mode != Z_POTENTIAL) return;
   __syncthreads();
   Cplx<R>* oth = res == A ? B : A;
@@ -366,15 +384,26 @@ size_t lds_fft_z(const DevPlan<R>& d) {
 
 template <typename R>
 size_t lds_spread(const DevPlan<R>& d) {
-  const size_t cells = static_cast<size_t>(d.T1 + d.P - 1) * (d.T2 + d.P - 1) * (d.T3 + d.P - 1);
+  const size_t cells = ((static_cast<size_t>(d.T1 + d.P - 1) * (d.T2 + d.P - 1)) | 1) * (d.T3 + d.P - 1);
   return cells * sizeof(double) + (kSpreadChunk * 3 * d.P + d.P * (d.nw + 1)) * sizeof(R) +
          kSpreadChunk * 3 * sizeof(int) + 16;
+}
+
+// Raise the dynamic-LDS limit of a kernel when a launch needs more than 64 KiB.
+inline void allow_lds(const void* fn, size_t lds) {
+  if (lds > 65536)
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+}
+
+template <typename R>
+inline KArg<R, true> karg(const BatchLaunch<R>& b) {
+  return KArg<R, true>{b.plans, b.boff, b.nrep};
 }
 
 template <typename R>
 hipError_t launch_bin(const DevPlan<R>& d, const R* xyz, const R* q, hipStream_t s) {
   const size_t lds = d.bin_lds ? static_cast<size_t>(d.ntiles) * sizeof(int) : 0;
-  hipLaunchKernelGGL(k_bin<R>, dim3(d.nbin), dim3(256), lds, s, d, xyz, q);
+  hipLaunchKernelGGL((k_bin<R, false>), dim3(d.nbin), dim3(256), lds, s, KArg<R, false>{d}, xyz, q);
   return hipGetLastError();
 }
 
@@ -382,20 +411,19 @@ template <typename R>
 hipError_t launch_scatter(const DevPlan<R>& d, hipStream_t s) {
   const int nb = static_cast<int>((d.n + 1023) / 1024);
   const size_t lds = (static_cast<size_t>(d.ntiles) + 1) * sizeof(int);
-  if (lds > 65536) (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_scatter<R>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-  hipLaunchKernelGGL(k_scatter<R>, dim3(nb), dim3(1024), lds, s, d);
+  allow_lds(reinterpret_cast<const void*>(&k_scatter<R, false>), lds);
+  hipLaunchKernelGGL((k_scatter<R, false>), dim3(nb), dim3(1024), lds, s, KArg<R, false>{d});
   return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_finalize(const DevPlan<R>& d, FinalConsts c, double* out7, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize<R>, dim3(1), dim3(256), 0, s, d, c, out7);
+hipError_t launch_finalize(const DevPlan<R>& d, double* out7, hipStream_t s) {
+  hipLaunchKernelGGL((k_finalize<R, false>), dim3(1), dim3(256), 0, s, KArg<R, false>{d}, out7);
   return hipGetLastError();
 }
 
-#define ESP_P_SWITCH(FN, ...)                 \
-  switch (d.P) {                              \
+#define ESP_P_SWITCH(PV, FN, ...)             \
+  switch (PV) {                               \
     case 2: return FN<R, 2>(__VA_ARGS__);     \
     case 3: return FN<R, 3>(__VA_ARGS__);     \
     case 4: return FN<R, 4>(__VA_ARGS__);     \
@@ -412,41 +440,93 @@ hipError_t launch_finalize(const DevPlan<R>& d, FinalConsts c, double* out7, hip
 
 template <typename R>
 hipError_t launch_spread(const DevPlan<R>& d, hipStream_t s) {
-  ESP_P_SWITCH(spread_launch, d, s)
+  ESP_P_SWITCH(d.P, spread_launch, d, s)
 }
 
 template <typename R>
-hipError_t launch_gather(const DevPlan<R>& d, R* f, FinalConsts c, double* out7, hipStream_t s) {
-  ESP_P_SWITCH(gather_launch, d, f, c, out7, s)
+hipError_t launch_gather(const DevPlan<R>& d, R* f, double* out7, hipStream_t s) {
+  ESP_P_SWITCH(d.P, gather_launch, d, f, out7, s)
 }
 
 template <typename R>
 hipError_t launch_fft_xy(const DevPlan<R>& d, const R* grid, Cplx<R>* spec, bool clear_input,
                          hipStream_t s) {
   const size_t lds = lds_fft_xy(d);
-  if (lds > 65536) (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_xy<R>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+  allow_lds(reinterpret_cast<const void*>(&k_fft_xy<R, false>), lds);
   const int nth = fft_threads(d.M1 * d.M2);
-  hipLaunchKernelGGL(k_fft_xy<R>, dim3(d.M3), dim3(nth), lds, s, d, grid, spec, clear_input ? 1 : 0);
+  hipLaunchKernelGGL((k_fft_xy<R, false>), dim3(d.M3), dim3(nth), lds, s, KArg<R, false>{d}, grid, spec,
+                     clear_input ? 1 : 0);
   return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_fft_xy_inv(const DevPlan<R>& d, hipStream_t s) {
   const size_t lds = lds_fft_xy(d);
-  if (lds > 65536) (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_xy_inv<R>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+  allow_lds(reinterpret_cast<const void*>(&k_fft_xy_inv<R, false>), lds);
   const int nth = fft_threads(d.M1 * d.M2);
-  hipLaunchKernelGGL(k_fft_xy_inv<R>, dim3(d.M3), dim3(nth), lds, s, d);
+  hipLaunchKernelGGL((k_fft_xy_inv<R, false>), dim3(d.M3), dim3(nth), lds, s, KArg<R, false>{d});
   return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_fft_z(const DevPlan<R>& d, ZMode mode, hipStream_t s) {
   const size_t lds = lds_fft_z(d);
-  if (lds > 65536) (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_z<R>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-  hipLaunchKernelGGL(k_fft_z<R>, dim3(d.nzblk), dim3(256), lds, s, d, static_cast<int>(mode));
+  allow_lds(reinterpret_cast<const void*>(&k_fft_z<R, false>), lds);
+  hipLaunchKernelGGL((k_fft_z<R, false>), dim3(d.nzblk), dim3(256), lds, s, KArg<R, false>{d},
+                     static_cast<int>(mode));
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------- batched launchers
+template <typename R>
+hipError_t launch_bin_batch(const BatchLaunch<R>& b, const R* xyz, const R* q, hipStream_t s) {
+  allow_lds(reinterpret_cast<const void*>(&k_bin<R, true>), b.lds);
+  hipLaunchKernelGGL((k_bin<R, true>), dim3(b.nblk), dim3(b.nth), b.lds, s, karg(b), xyz, q);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_scatter_batch(const BatchLaunch<R>& b, hipStream_t s) {
+  allow_lds(reinterpret_cast<const void*>(&k_scatter<R, true>), b.lds);
+  hipLaunchKernelGGL((k_scatter<R, true>), dim3(b.nblk), dim3(b.nth), b.lds, s, karg(b));
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_spread_batch(const BatchLaunch<R>& b, hipStream_t s) {
+  ESP_P_SWITCH(b.P, spread_launch_batch, b, s)
+}
+
+template <typename R>
+hipError_t launch_gather_batch(const BatchLaunch<R>& b, R* f, double* out7, hipStream_t s) {
+  ESP_P_SWITCH(b.P, gather_launch_batch, b, f, out7, s)
+}
+
+template <typename R>
+hipError_t launch_fft_xy_batch(const BatchLaunch<R>& b, hipStream_t s) {
+  allow_lds(reinterpret_cast<const void*>(&k_fft_xy<R, true>), b.lds);
+  hipLaunchKernelGGL((k_fft_xy<R, true>), dim3(b.nblk), dim3(b.nth), b.lds, s, karg(b),
+                     static_cast<const R*>(nullptr), static_cast<Cplx<R>*>(nullptr), 1);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_fft_xy_inv_batch(const BatchLaunch<R>& b, hipStream_t s) {
+  allow_lds(reinterpret_cast<const void*>(&k_fft_xy_inv<R, true>), b.lds);
+  hipLaunchKernelGGL((k_fft_xy_inv<R, true>), dim3(b.nblk), dim3(b.nth), b.lds, s, karg(b));
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_fft_z_batch(const BatchLaunch<R>& b, ZMode mode, hipStream_t s) {
+  allow_lds(reinterpret_cast<const void*>(&k_fft_z<R, true>), b.lds);
+  hipLaunchKernelGGL((k_fft_z<R, true>), dim3(b.nblk), dim3(b.nth), b.lds, s, karg(b), static_cast<int>(mode));
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_finalize_batch(const BatchLaunch<R>& b, double* out7, hipStream_t s) {
+  hipLaunchKernelGGL((k_finalize<R, true>), dim3(b.nblk), dim3(256), 0, s, karg(b), out7);
   return hipGetLastError();
 }
 
@@ -461,12 +541,20 @@ hipError_t launch_fill(T* p, size_t count, hipStream_t s) {
 #define ESP_INSTANTIATE(R)                                                                    \
   template hipError_t launch_bin<R>(const DevPlan<R>&, const R*, const R*, hipStream_t);      \
   template hipError_t launch_scatter<R>(const DevPlan<R>&, hipStream_t);                      \
-  template hipError_t launch_finalize<R>(const DevPlan<R>&, FinalConsts, double*, hipStream_t); \
+  template hipError_t launch_finalize<R>(const DevPlan<R>&, double*, hipStream_t);            \
   template hipError_t launch_spread<R>(const DevPlan<R>&, hipStream_t);                       \
   template hipError_t launch_fft_xy<R>(const DevPlan<R>&, const R*, Cplx<R>*, bool, hipStream_t); \
   template hipError_t launch_fft_z<R>(const DevPlan<R>&, ZMode, hipStream_t);                 \
   template hipError_t launch_fft_xy_inv<R>(const DevPlan<R>&, hipStream_t);                   \
-  template hipError_t launch_gather<R>(const DevPlan<R>&, R*, FinalConsts, double*, hipStream_t); \
+  template hipError_t launch_gather<R>(const DevPlan<R>&, R*, double*, hipStream_t);          \
+  template hipError_t launch_bin_batch<R>(const BatchLaunch<R>&, const R*, const R*, hipStream_t); \
+  template hipError_t launch_scatter_batch<R>(const BatchLaunch<R>&, hipStream_t);            \
+  template hipError_t launch_spread_batch<R>(const BatchLaunch<R>&, hipStream_t);             \
+  template hipError_t launch_fft_xy_batch<R>(const BatchLaunch<R>&, hipStream_t);             \
+  template hipError_t launch_fft_z_batch<R>(const BatchLaunch<R>&, ZMode, hipStream_t);       \
+  template hipError_t launch_fft_xy_inv_batch<R>(const BatchLaunch<R>&, hipStream_t);         \
+  template hipError_t launch_gather_batch<R>(const BatchLaunch<R>&, R*, double*, hipStream_t); \
+  template hipError_t launch_finalize_batch<R>(const BatchLaunch<R>&, double*, hipStream_t);  \
   template hipError_t launch_fill<R>(R*, size_t, hipStream_t);                                \
   template size_t lds_fft_xy<R>(const DevPlan<R>&);                                           \
   template size_t lds_fft_z<R>(const DevPlan<R>&);                                            \

@@ -13,7 +13,9 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/esp.h"
@@ -35,6 +37,8 @@ struct Resolved {
   int params_source = ESP_ANALYTIC;
   int coupling = ESP_ISO;
   double window_tol = 0;
+  double pred[4] = {0, 0, 0, 0};
+  double pred_cost = 0;
 };
 
 bool smooth235(int m) {
@@ -105,10 +109,107 @@ esp_status check_box(const double* h, double rc, double* hinv, double* V, std::s
   return ESP_OK;
 }
 
-// Learned proposer hook (set from the learned-parameter module).
-typedef int (*proposer_fn)(const double* features, int nfeat, double* out, void* ctx);
-proposer_fn g_proposer = nullptr;
-void* g_proposer_ctx = nullptr;
+// ---- learned parameter proposer -------------------------------------------
+}  // namespace
+namespace espx {
+esp_status mlp_predict_host(esp_mlp_t* p, const float* xh, int64_t B, float* yh);
+int mlp_dim(const esp_mlp_t* p, int which);
+}  // namespace espx
+namespace {
+struct ProposerState {
+  bool set = false;
+  esp_proposer cfg{};
+  std::vector<double> deltas, cs;   // candidate Delta grid and c(Delta)
+};
+ProposerState g_prop;
+std::mutex g_prop_mu;
+
+constexpr double kSigmas[] = {0.85, 0.9, 0.95, 1.0, 1.07, 1.15, 1.22, 1.3};
+
+struct Proposal {
+  double delta, c, sigma, cost;
+  int P, M[3];
+  double pred[4];
+};
+
+// Score the candidate grid with the registered MLP (on the GPU) and return the
+// cheapest candidate predicted to meet tol; false if none does.
+// Score the candidate grid (plus the analytic choice) with the registered
+// MLP on the GPU.  Returns 1 with the cheapest candidate predicted to meet
+// tol, 2 with the candidate of smallest predicted excess when none does, and
+// 0 (err set) when no proposer is usable.
+int propose(const double* h, int64_t n, double tol, int coupling, double rc, double V, double sigma_rule,
+            Proposal& best, std::string& err) {
+  std::lock_guard<std::mutex> lock(g_prop_mu);
+  if (!g_prop.set) {
+    err = "no proposer registered";
+    return 0;
+  }
+  const esp_proposer& cfg = g_prop.cfg;
+  constexpr int NF = ESP_PROPOSER_FEATURES;
+  const double fdens = std::log10(static_cast<double>(n) / V);
+  std::vector<Proposal> cand;
+  std::vector<float> feat;
+  auto add = [&](double delta, double c, int P, double sg) {
+    Proposal pr{};
+    pr.delta = delta;
+    pr.c = c;
+    pr.sigma = sg;
+    pr.P = P;
+    for (int d = 0; d < 3; ++d) pr.M[d] = next_smooth(std::max({grid_rule(h, d, c, rc, sg), P, 2}));
+    const double f[NF] = {std::log10(delta), double(P), sg, fdens};
+    for (int j = 0; j < NF; ++j) feat.push_back(static_cast<float>((f[j] - cfg.in_mean[j]) / cfg.in_std[j]));
+    cand.push_back(pr);
+  };
+  for (size_t k = 0; k < g_prop.deltas.size(); ++k) {
+    const double delta = g_prop.deltas[k];
+    const int D = static_cast<int>(std::ceil(-std::log10(delta) - 1e-9));
+    for (int P = std::max(3, D - 1); P <= std::min(kMaxP, D + 2); ++P)
+      for (double sg : kSigmas) add(delta, g_prop.cs[k], P, sg);
+  }
+  {
+    // the analytic rule's own choice competes on the same terms
+    const double delta = coupling == ESP_FLEX ? tol / 5 : tol;
+    const int P = std::min(kMaxP, static_cast<int>(std::ceil(-std::log10(delta) - 1e-9)) + 1);
+    add(delta, c_from_delta(delta), P, sigma_rule);
+  }
+  const int64_t B = static_cast<int64_t>(cand.size());
+  std::vector<float> y(B * 4);
+  if (mlp_predict_host(const_cast<esp_mlp_t*>(cfg.mlp), feat.data(), B, y.data()) != ESP_OK) {
+    err = "proposer evaluation failed on the device";
+    return 0;
+  }
+  double lim[4];
+  for (int j = 0; j < 4; ++j) lim[j] = std::log10(tol) - cfg.margin[j];
+  int found = 0;
+  double best_excess = 0;
+  for (int64_t b = 0; b < B; ++b) {
+    Proposal& pr = cand[b];
+    for (int j = 0; j < 4; ++j) pr.pred[j] = y[b * 4 + j] * cfg.out_std[j] + cfg.out_mean[j];
+    double excess = std::max({pr.pred[0] - lim[0], pr.pred[1] - lim[1], pr.pred[3] - lim[3]});
+    if (coupling == ESP_FLEX) excess = std::max(excess, pr.pred[2] - lim[2]);
+    const double G = double(pr.M[0]) * pr.M[1] * pr.M[2];
+    pr.cost = cfg.cost[0] + cfg.cost[1] * n * double(pr.P) * pr.P * pr.P + cfg.cost[2] * G * std::log2(G) +
+              cfg.cost[3] * n + cfg.cost[4] * G;
+    if (excess <= 0) {
+      if (found != 1 || pr.cost < best.cost) {
+        best = pr;
+        found = 1;
+      }
+    } else if (found != 1 && (found == 0 || excess < best_excess)) {
+      best = pr;
+      best_excess = excess;
+      found = 2;
+    }
+  }
+  if (found == 2) {
+    char b[160];
+    std::snprintf(b, sizeof b, "no candidate is predicted to meet tol; the most accurate one is %.2f decades short",
+                  best_excess);
+    err = b;
+  }
+  return found;
+}
 
 void choose_tiles(Resolved& r, int tile) {
   int T = tile;
@@ -179,30 +280,24 @@ esp_status resolve(const double* h, int64_t n, double tol, const esp_opts* o, Re
   esp_status warn = ESP_OK;
   int src = o->params;
   if (src == ESP_LEARNED) {
-    bool ok = false;
-    if (g_proposer) {
-      // features: log10 tol, log10 N, edges / V^(1/3), coupling, rc
-      double V13 = std::cbrt(r.V);
-      double feat[8] = {std::log10(tol), std::log10(double(n)), col_norm(h, 0) / V13, col_norm(h, 1) / V13,
-                        col_norm(h, 2) / V13, double(o->coupling), r.rc, n / r.V};
-      double out[6];
-      if (g_proposer(feat, 8, out, g_proposer_ctx) == 0) {
-        // out: delta, P, sigma
-        double dl = out[0];
-        int P = static_cast<int>(std::lround(out[1]));
-        double sg = out[2];
-        if (dl >= 1e-14 && dl < 0.5 && P >= 2 && P <= kMaxP && sg >= 0.6 && sg <= 3.0) {
-          r.delta = dl;
-          r.c_split = r.c_spread = c_from_delta(dl);
-          r.P = P;
-          for (int d = 0; d < 3; ++d)
-            r.M[d] = next_smooth(std::max({grid_rule(h, d, r.c_split, r.rc, sg), P, 2}));
-          r.params_source = ESP_LEARNED;
-          ok = true;
-        }
+    Proposal pr{};
+    std::string why;
+    const int got = propose(h, n, tol, o->coupling, r.rc, r.V, r.sigma, pr, why);
+    if (got) {
+      r.delta = pr.delta;
+      r.c_split = r.c_spread = pr.c;
+      r.P = pr.P;
+      r.sigma = pr.sigma;
+      for (int d = 0; d < 3; ++d) r.M[d] = pr.M[d];
+      for (int j = 0; j < 4; ++j) r.pred[j] = pr.pred[j];
+      r.pred_cost = pr.cost;
+      r.params_source = ESP_LEARNED;
+      if (got == 2) {
+        err = "learned parameters: " + why;
+        warn = ESP_WARN_FALLBACK;
       }
-    }
-    if (!ok) {
+    } else {
+      err = "learned parameters unavailable (" + why + "); analytic rule used";
       warn = ESP_WARN_FALLBACK;
       src = ESP_ANALYTIC;
     }
@@ -317,6 +412,15 @@ esp_status dalloc(esp_plan_t* p, T** ptr, size_t count) {
   return ESP_OK;
 }
 
+FinalConsts final_consts(const esp_plan_t* p) {
+  FinalConsts c;
+  c.inv2V = 0.5 / p->r.V;
+  c.self_coef = p->self_coef;
+  c.bg_coef = kTwoPi * p->Ic / p->r.V;
+  c.coulomb_k = p->r.coulomb_k;
+  return c;
+}
+
 // Box-dependent fields of the device plan.
 template <typename R>
 void set_box_fields(esp_plan_t* p, DevPlan<R>& d) {
@@ -332,6 +436,7 @@ void set_box_fields(esp_plan_t* p, DevPlan<R>& d) {
       d.G[3 * a + m] = static_cast<R>(-r.hinv[3 * m + a] * r.M[m]);
     }
   d.inv_vol = static_cast<R>(1.0 / r.V);
+  d.fin = final_consts(p);
 }
 
 // Per-subinterval window polynomials (Sec. 4.3): polynomial p approximates
@@ -525,15 +630,6 @@ esp_status build_device(esp_plan_t* p) {
   return ESP_OK;
 }
 
-FinalConsts final_consts(const esp_plan_t* p) {
-  FinalConsts c;
-  c.inv2V = 0.5 / p->r.V;
-  c.self_coef = p->self_coef;
-  c.bg_coef = kTwoPi * p->Ic / p->r.V;
-  c.coulomb_k = p->r.coulomb_k;
-  return c;
-}
-
 // Launch one stage, bracketed by profiling events when that stage is profiled.
 template <class F>
 hipError_t stage(esp_plan_t* p, int st, F&& launch) {
@@ -576,7 +672,7 @@ esp_status energy_virial(esp_plan_t* p, const R* xyz, const R* q, double* out7) 
   if (st != ESP_OK) return st;
   hipError_t e = stage(p, ST_FFT_XY, [&] { return launch_fft_xy(d, d.rho, d.spec, true, p->stream); });
   if (e == hipSuccess) e = stage(p, ST_FFT_Z, [&] { return launch_fft_z(d, Z_ENERGY, p->stream); });
-  if (e == hipSuccess) e = launch_finalize(d, final_consts(p), out7, p->stream);
+  if (e == hipSuccess) e = launch_finalize(d, out7, p->stream);
   return e == hipSuccess ? ESP_OK : hip_fail(p, e, "kernel launch");
 }
 
@@ -600,7 +696,7 @@ esp_status forces(esp_plan_t* p, const R* xyz, const R* q, R* f, double* out7) {
   esp_status st = potential(p, xyz, q);
   if (st != ESP_OK) return st;
   DevPlan<R>& d = dev<R>(p);
-  hipError_t e = stage(p, ST_GATHER, [&] { return launch_gather(d, f, final_consts(p), out7, p->stream); });
+  hipError_t e = stage(p, ST_GATHER, [&] { return launch_gather(d, f, out7, p->stream); });
   return e == hipSuccess ? ESP_OK : hip_fail(p, e, "kernel launch");
 }
 
@@ -659,6 +755,8 @@ esp_status esp_resolve_params(const double h[9], int64_t n, double tol, const es
   out->ntiles = r.ntiles;
   out->volume = r.V;
   out->params_source = r.params_source;
+  for (int j = 0; j < 4; ++j) out->predicted_log10_err[j] = r.pred[j];
+  out->predicted_cost = r.pred_cost;
   Pswf ps(r.c_split);
   out->lambda0_split = ps.lambda0();
   out->C0_split = ps.C0();
@@ -800,6 +898,8 @@ esp_status esp_get_params(const esp_plan_t* p, esp_params* out) {
   out->psi0_split = p->split->psi0();
   out->volume = r.V;
   out->params_source = r.params_source;
+  for (int j = 0; j < 4; ++j) out->predicted_log10_err[j] = r.pred[j];
+  out->predicted_cost = r.pred_cost;
   return ESP_OK;
 }
 
@@ -972,6 +1072,382 @@ const char* esp_stage_name(int stage) {
   return stage >= 0 && stage < ST_COUNT ? kStageNames[stage] : "";
 }
 
+esp_status esp_proposer_set(const esp_proposer* p) {
+  std::lock_guard<std::mutex> lock(g_prop_mu);
+  if (!p) {
+    g_prop = ProposerState{};
+    return ESP_OK;
+  }
+  if (!p->mlp || esp_mlp_num_params(p->mlp) <= 0 || mlp_dim(p->mlp, 0) != ESP_PROPOSER_FEATURES ||
+      mlp_dim(p->mlp, 1) != 4)
+    return ESP_EINVAL;
+  for (int j = 0; j < ESP_PROPOSER_FEATURES; ++j)
+    if (!(p->in_std[j] > 0)) return ESP_EINVAL;
+  for (int j = 0; j < 4; ++j)
+    if (!(p->out_std[j] > 0) || !(p->margin[j] >= 0)) return ESP_EINVAL;
+  ProposerState st;
+  st.cfg = *p;
+  try {
+    for (int k = 0; k <= 20; ++k) {
+      const double delta = std::pow(10.0, -2.0 - 0.25 * k);
+      st.deltas.push_back(delta);
+      st.cs.push_back(c_from_delta(delta));
+    }
+  } catch (const std::exception&) {
+    return ESP_EINVAL;
+  }
+  st.set = true;
+  g_prop = st;
+  return ESP_OK;
+}
+
 const char* esp_version(void) { return "esp-mi355x 0.1.0 (gfx950)"; }
+
+}  // extern "C"
+
+// ============================================================================ batches
+// A batch holds one ordinary plan per replica (its tables and buffers) plus a
+// device array of their DevPlans, ordered so that replicas sharing a window
+// support P and window degree are adjacent.  Each stage is one launch over a
+// contiguous range of that array; a workgroup finds its replica by bisecting
+// the stage's block offsets.
+struct BatchStage {
+  size_t at = 0;          // index of this stage's offsets in the shared table
+  int* boff = nullptr;    // device: count + 1 block offsets
+  int nblk = 0, nth = 256;
+  size_t lds = 0;
+  int first = 0, count = 0;
+  int P = 0, nw = 0;
+};
+
+struct esp_batch_s {
+  int nrep = 0, precision = ESP_FP32;
+  std::vector<esp_plan_t*> reps;
+  std::vector<int> order;         // position in the device array -> replica
+  std::vector<int> pos;           // replica -> position
+  std::vector<int64_t> pofs;      // first particle of each replica (nrep + 1)
+  hipStream_t stream = nullptr;
+  void* dplans = nullptr;
+  int* dboff = nullptr;
+  unsigned char* hstage = nullptr;    // pinned staging of box updates, one slot per replica
+  std::vector<hipEvent_t> staged;
+  size_t plan_bytes = 0;
+  BatchStage bin, scatter, fxy, fz, fxyi, fin;
+  std::vector<BatchStage> spread, gather;
+  bool use_graph = false;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const void* key[5] = {};
+  std::string err;
+  void drop_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+  }
+  ~esp_batch_s() {
+    (void)hipStreamSynchronize(stream);
+    drop_graph();
+    if (cap) (void)hipStreamDestroy(cap);
+    for (hipEvent_t e : staged)
+      if (e) (void)hipEventDestroy(e);
+    if (hstage) (void)hipHostFree(hstage);
+    if (dplans) (void)hipFree(dplans);
+    if (dboff) (void)hipFree(dboff);
+    for (esp_plan_t* p : reps) delete p;
+  }
+};
+
+namespace {
+
+template <typename R>
+DevPlan<R> batch_entry(const esp_batch_t* b, int r) {
+  DevPlan<R> d = dev<R>(b->reps[r]);
+  d.pofs = b->pofs[r];
+  d.rep = r;
+  return d;
+}
+
+template <typename R>
+esp_status batch_build(esp_batch_t* b) {
+  const int nrep = b->nrep;
+  std::vector<DevPlan<R>> hp(nrep);
+  for (int k = 0; k < nrep; ++k) hp[k] = batch_entry<R>(b, b->order[k]);
+  std::vector<int> offs;
+  auto make = [&](BatchStage& st, int first, int count, auto nblk_of, auto lds_of, int nth) {
+    st.first = first;
+    st.count = count;
+    st.at = offs.size();
+    st.nth = nth;
+    st.lds = 0;
+    offs.push_back(0);
+    for (int k = first; k < first + count; ++k) {
+      offs.push_back(offs.back() + nblk_of(hp[k]));
+      st.lds = std::max(st.lds, lds_of(hp[k]));
+    }
+    st.nblk = offs.back();
+    st.P = hp[first].P;
+    st.nw = hp[first].nw;
+  };
+  auto zero = [](const DevPlan<R>&) { return size_t(0); };
+  make(b->bin, 0, nrep, [](const DevPlan<R>& d) { return d.nbin; },
+       [](const DevPlan<R>& d) { return d.bin_lds ? static_cast<size_t>(d.ntiles) * sizeof(int) : size_t(0); }, 256);
+  make(b->scatter, 0, nrep, [](const DevPlan<R>& d) { return static_cast<int>((d.n + 1023) / 1024); },
+       [](const DevPlan<R>& d) { return (static_cast<size_t>(d.ntiles) + 1) * sizeof(int); }, 1024);
+  int nth_xy = 256;
+  for (const DevPlan<R>& d : hp) nth_xy = std::max(nth_xy, fft_threads(d.M1 * d.M2));
+  make(b->fxy, 0, nrep, [](const DevPlan<R>& d) { return d.M3; }, [](const DevPlan<R>& d) { return lds_fft_xy(d); },
+       nth_xy);
+  make(b->fz, 0, nrep, [](const DevPlan<R>& d) { return d.nzblk; }, [](const DevPlan<R>& d) { return lds_fft_z(d); },
+       256);
+  make(b->fxyi, 0, nrep, [](const DevPlan<R>& d) { return d.M3; }, [](const DevPlan<R>& d) { return lds_fft_xy(d); },
+       nth_xy);
+  make(b->fin, 0, nrep, [](const DevPlan<R>&) { return 1; }, zero, 256);
+  b->spread.clear();
+  b->gather.clear();
+  for (int k = 0; k < nrep;) {
+    int e = k + 1;
+    while (e < nrep && hp[e].P == hp[k].P && hp[e].nw == hp[k].nw) ++e;
+    BatchStage sp, ga;
+    make(sp, k, e - k, [](const DevPlan<R>& d) { return d.ntiles; },
+         [](const DevPlan<R>& d) { return lds_spread(d); }, 256);
+    const int G = 256 / gather_lanes(hp[k].P);
+    make(ga, k, e - k, [G](const DevPlan<R>& d) { return static_cast<int>((d.n + G - 1) / G); }, zero, 256);
+    b->spread.push_back(sp);
+    b->gather.push_back(ga);
+    k = e;
+  }
+  b->plan_bytes = sizeof(DevPlan<R>);
+  void* dp = nullptr;
+  hipError_t e = hipMalloc(&dp, hp.size() * sizeof(DevPlan<R>));
+  if (e == hipSuccess) {
+    b->dplans = dp;
+    e = hipMalloc(&b->dboff, offs.size() * sizeof(int));
+  }
+  if (e == hipSuccess) e = hipMemcpy(b->dplans, hp.data(), hp.size() * sizeof(DevPlan<R>), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->dboff, offs.data(), offs.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&b->hstage), hp.size() * sizeof(DevPlan<R>));
+  if (e != hipSuccess) {
+    b->err = std::string("batch set-up: ") + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? ESP_ENOMEM : ESP_EDEVICE;
+  }
+  b->staged.assign(nrep, nullptr);
+  for (BatchStage* st : {&b->bin, &b->scatter, &b->fxy, &b->fz, &b->fxyi, &b->fin}) st->boff = b->dboff + st->at;
+  for (auto* v : {&b->spread, &b->gather})
+    for (BatchStage& st : *v) st.boff = b->dboff + st.at;
+  return ESP_OK;
+}
+
+template <typename R>
+BatchLaunch<R> batch_launch(const esp_batch_t* b, const BatchStage& st) {
+  return BatchLaunch<R>{static_cast<const DevPlan<R>*>(b->dplans) + st.first, st.boff, st.count, st.nblk, st.nth,
+                        st.lds, st.P, st.nw};
+}
+
+template <typename R>
+hipError_t batch_launches(const esp_batch_t* b, const R* xyz, const R* q, R* f, double* out7, bool forces,
+                          hipStream_t s) {
+  hipError_t e = launch_bin_batch(batch_launch<R>(b, b->bin), xyz, q, s);
+  if (e == hipSuccess) e = launch_scatter_batch(batch_launch<R>(b, b->scatter), s);
+  for (const BatchStage& g : b->spread)
+    if (e == hipSuccess) e = launch_spread_batch(batch_launch<R>(b, g), s);
+  if (e == hipSuccess) e = launch_fft_xy_batch(batch_launch<R>(b, b->fxy), s);
+  if (e == hipSuccess) e = launch_fft_z_batch(batch_launch<R>(b, b->fz), forces ? Z_POTENTIAL : Z_ENERGY, s);
+  if (forces) {
+    if (e == hipSuccess) e = launch_fft_xy_inv_batch(batch_launch<R>(b, b->fxyi), s);
+    for (const BatchStage& g : b->gather)
+      if (e == hipSuccess) e = launch_gather_batch(batch_launch<R>(b, g), f, out7, s);
+  } else if (e == hipSuccess) {
+    e = launch_finalize_batch(batch_launch<R>(b, b->fin), out7, s);
+  }
+  return e;
+}
+
+esp_status batch_fail(esp_batch_t* b, hipError_t e, const char* what) {
+  b->err = std::string(what) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? ESP_ENOMEM : ESP_EDEVICE;
+}
+
+template <typename R>
+esp_status batch_call(esp_batch_t* b, const R* xyz, const R* q, R* f, double* out7, bool forces) {
+  if (!b) return ESP_EINVAL;
+  if ((b->precision == ESP_FP32) != std::is_same<R, float>::value) {
+    b->err = "precision of the entry point differs from the batch's";
+    return ESP_EINVAL;
+  }
+  if (!xyz || !q || (forces && !f) || (!forces && !out7)) {
+    b->err = "null pointer argument";
+    return ESP_EINVAL;
+  }
+  if (!b->use_graph) {
+    const hipError_t e = batch_launches(b, xyz, q, f, out7, forces, b->stream);
+    return e == hipSuccess ? ESP_OK : batch_fail(b, e, "kernel launch");
+  }
+  const void* key[5] = {xyz, q, f, out7, forces ? b : nullptr};
+  if (b->exec && std::equal(key, key + 5, b->key)) {
+    const hipError_t e = hipGraphLaunch(b->exec, b->stream);
+    return e == hipSuccess ? ESP_OK : batch_fail(b, e, "graph launch");
+  }
+  // New pointers or kind of call: run eagerly (this call's result), then record
+  // the same launches on a private stream for the following calls.
+  hipError_t e = batch_launches(b, xyz, q, f, out7, forces, b->stream);
+  if (e != hipSuccess) return batch_fail(b, e, "kernel launch");
+  b->drop_graph();
+  if (!b->cap && (e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking)) != hipSuccess)
+    return batch_fail(b, e, "capture stream");
+  if ((e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+    return batch_fail(b, e, "begin capture");
+  const hipError_t el = batch_launches(b, xyz, q, f, out7, forces, b->cap);
+  e = hipStreamEndCapture(b->cap, &b->graph);
+  if (el != hipSuccess || e != hipSuccess) {
+    b->drop_graph();
+    return batch_fail(b, el != hipSuccess ? el : e, "graph capture");
+  }
+  if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess) {
+    b->drop_graph();
+    return batch_fail(b, e, "graph instantiate");
+  }
+  std::copy(key, key + 5, b->key);
+  return ESP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+esp_status esp_batch_plan(int nrep, const double* h, const int64_t* n, const double* tol, const esp_opts* o,
+                          const int* tiles, esp_batch_t** out) {
+  if (!out) return ESP_EINVAL;
+  *out = nullptr;
+  if (nrep < 1 || !h || !n || !tol) return ESP_EINVAL;
+  esp_opts base;
+  esp_opts_default(&base);
+  if (o) base = *o;
+  std::unique_ptr<esp_batch_s> b(new (std::nothrow) esp_batch_s());
+  if (!b) return ESP_ENOMEM;
+  b->nrep = nrep;
+  b->precision = base.precision;
+  b->stream = static_cast<hipStream_t>(base.stream);
+  b->reps.assign(nrep, nullptr);
+  b->pofs.assign(nrep + 1, 0);
+  esp_status warn = ESP_OK;
+  for (int r = 0; r < nrep; ++r) {
+    esp_opts opt = base;
+    if (tiles) opt.tile = tiles[r];
+    const esp_status st = esp_plan(h + 9 * r, n[r], tol[r], &opt, &b->reps[r]);
+    if (st < 0) {
+      std::fprintf(stderr, "esp_batch_plan: replica %d rejected (status %d)\n", r, st);
+      return st;
+    }
+    if (st > 0) warn = st;
+    b->pofs[r + 1] = b->pofs[r] + n[r];
+  }
+  b->order.resize(nrep);
+  for (int r = 0; r < nrep; ++r) b->order[r] = r;
+  std::stable_sort(b->order.begin(), b->order.end(), [&](int a, int c) {
+    const esp_plan_t* pa = b->reps[a];
+    const esp_plan_t* pc = b->reps[c];
+    return pa->r.P != pc->r.P ? pa->r.P < pc->r.P : pa->nw < pc->nw;
+  });
+  b->pos.resize(nrep);
+  for (int k = 0; k < nrep; ++k) b->pos[b->order[k]] = k;
+  const esp_status st = b->precision == ESP_FP32 ? batch_build<float>(b.get()) : batch_build<double>(b.get());
+  if (st != ESP_OK) {
+    std::fprintf(stderr, "esp_batch_plan: %s\n", b->err.c_str());
+    return st;
+  }
+  *out = b.release();
+  return warn;
+}
+
+esp_status esp_batch_energy_virial(esp_batch_t* b, const float* xyz, const float* q, double* out7) {
+  return batch_call<float>(b, xyz, q, nullptr, out7, false);
+}
+
+esp_status esp_batch_forces(esp_batch_t* b, const float* xyz, const float* q, float* f, double* out7) {
+  return batch_call<float>(b, xyz, q, f, out7, true);
+}
+
+esp_status esp_batch_energy_virial_f64(esp_batch_t* b, const double* xyz, const double* q, double* out7) {
+  return batch_call<double>(b, xyz, q, nullptr, out7, false);
+}
+
+esp_status esp_batch_forces_f64(esp_batch_t* b, const double* xyz, const double* q, double* f, double* out7) {
+  return batch_call<double>(b, xyz, q, f, out7, true);
+}
+
+esp_status esp_batch_set_box(esp_batch_t* b, int r, const double h[9]) {
+  if (!b || r < 0 || r >= b->nrep || !h) return ESP_EINVAL;
+  const esp_status st = esp_set_box(b->reps[r], h);
+  if (st < 0) {
+    b->err = "replica " + std::to_string(r) + ": " + b->reps[r]->err;
+    return st;
+  }
+  hipError_t e = hipSuccess;
+  if (b->staged[r]) e = hipEventSynchronize(b->staged[r]);      // slot r free again
+  else e = hipEventCreateWithFlags(&b->staged[r], hipEventDisableTiming);
+  if (e != hipSuccess) return batch_fail(b, e, "box staging");
+  unsigned char* slot = b->hstage + static_cast<size_t>(r) * b->plan_bytes;
+  const size_t at = static_cast<size_t>(b->pos[r]) * b->plan_bytes;
+  if (b->precision == ESP_FP32) {
+    const DevPlan<float> d = batch_entry<float>(b, r);
+    std::memcpy(slot, &d, sizeof d);
+  } else {
+    const DevPlan<double> d = batch_entry<double>(b, r);
+    std::memcpy(slot, &d, sizeof d);
+  }
+  e = hipMemcpyAsync(static_cast<unsigned char*>(b->dplans) + at, slot, b->plan_bytes, hipMemcpyHostToDevice,
+                     b->stream);
+  if (e == hipSuccess) e = hipEventRecord(b->staged[r], b->stream);
+  return e == hipSuccess ? st : batch_fail(b, e, "box upload");
+}
+
+esp_status esp_batch_set_stream(esp_batch_t* b, void* stream) {
+  if (!b) return ESP_EINVAL;
+  b->stream = static_cast<hipStream_t>(stream);
+  return ESP_OK;
+}
+
+esp_status esp_batch_set_graph(esp_batch_t* b, int enable) {
+  if (!b) return ESP_EINVAL;
+  b->use_graph = enable != 0;
+  if (!b->use_graph) {
+    (void)hipStreamSynchronize(b->stream);
+    b->drop_graph();
+  }
+  return ESP_OK;
+}
+
+esp_status esp_batch_check(esp_batch_t* b) {
+  if (!b) return ESP_EINVAL;
+  hipError_t e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return batch_fail(b, e, "stream synchronise");
+  esp_status worst = ESP_OK;
+  for (int r = 0; r < b->nrep; ++r) {
+    b->reps[r]->stream = b->stream;
+    const esp_status st = esp_check(b->reps[r]);
+    if (st != ESP_OK && (worst == ESP_OK || st == ESP_EDEVICE)) {
+      worst = st;
+      b->err = "replica " + std::to_string(r) + ": " + b->reps[r]->err;
+    }
+  }
+  return worst;
+}
+
+esp_status esp_batch_get_params(const esp_batch_t* b, int r, esp_params* out) {
+  if (!b || r < 0 || r >= b->nrep) return ESP_EINVAL;
+  return esp_get_params(b->reps[r], out);
+}
+
+int esp_batch_num_launches(const esp_batch_t* b, int forces) {
+  if (!b) return -1;
+  const int groups = static_cast<int>(b->spread.size());
+  return forces ? 2 + groups + 3 + groups : 2 + groups + 3;
+}
+
+const char* esp_batch_last_error(const esp_batch_t* b) { return b ? b->err.c_str() : "null batch"; }
+
+void esp_batch_destroy(esp_batch_t* b) { delete b; }
 
 }  // extern "C"

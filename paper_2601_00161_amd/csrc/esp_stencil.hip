@@ -52,17 +52,21 @@ __device__ __forceinline__ void eval_window_d(const R* __restrict__ win, R tau, 
 // is then added to the periodic grid.  The LDS tile accumulates in FP64 for
 // both precisions: products are formed in R, and ds_add_f64 is the fast LDS
 // atomic on gfx950 (ds_add_f32 is not).
-template <typename R, int P, int NW>
-__global__ void __launch_bounds__(256) k_spread(DevPlan<R> d) {
+template <typename R, int P, int NW, bool BATCH>
+__global__ void __launch_bounds__(256) k_spread(KArg<R, BATCH> ka) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int tile = blockIdx.x;
+  int tile;
+  const DevPlan<R>& d = plan_of(ka, tile);
   const int t1 = tile % d.nt1, t2 = (tile / d.nt1) % d.nt2, t3 = tile / (d.nt1 * d.nt2);
   const int o1 = t1 * d.T1, o2 = t2 * d.T2, o3 = t3 * d.T3;
   const int E1 = min(d.T1, d.M1 - o1) + P - 1;
   const int E2 = min(d.T2, d.M2 - o2) + P - 1;
   const int E3 = min(d.T3, d.M3 - o3) + P - 1;
-  const int ncell = E1 * E2 * E3;
-  const int maxcell = (d.T1 + P - 1) * (d.T2 + P - 1) * (d.T3 + P - 1);
+  // plane stride made odd: the P z-planes of one particle are touched by P
+  // adjacent lanes, and an even stride of doubles maps them onto few banks
+  const int S = (E1 * E2) | 1;
+  const int ncell = S * E3;
+  const int maxcell = (((d.T1 + P - 1) * (d.T2 + P - 1)) | 1) * (d.T3 + P - 1);
   double* grid = reinterpret_cast<double*>(smem);
   R* wts = reinterpret_cast<R*>(grid + maxcell);     // kSpreadChunk x 3 x P
   R* win = wts + kSpreadChunk * 3 * P;               // (NW + 1) x P
@@ -103,7 +107,7 @@ __global__ void __launch_bounds__(256) k_spread(DevPlan<R> d) {
         wy[a] = wj[P + a];
       }
       const R wz = wj[2 * P + cz];
-      double* plane = grid + ((base[j * 3 + 2] + cz) * E2 + base[j * 3 + 1]) * E1 + base[j * 3];
+      double* plane = grid + (base[j * 3 + 2] + cz) * S + base[j * 3 + 1] * E1 + base[j * 3];
 #pragma unroll
       for (int by = 0; by < P; ++by) {
         const R v = wy[by] * wz;
@@ -123,7 +127,7 @@ __global__ void __launch_bounds__(256) k_spread(DevPlan<R> d) {
     gy -= gy >= d.M2 ? d.M2 : 0;
     R* col = d.rho + static_cast<size_t>(gy) * d.M1 + gx;
     for (int z = 0; z < E3; ++z) {
-      const R val = static_cast<R>(grid[z * E12 + k0]);
+      const R val = static_cast<R>(grid[z * S + k0]);
       int gz = o3 + z;
       gz -= gz >= d.M3 ? d.M3 : 0;
       if (val != R(0)) atomic_add_global(col + gz * planesz, val);
@@ -138,17 +142,20 @@ __global__ void __launch_bounds__(256) k_spread(DevPlan<R> d) {
 // reduced with cross-lane shuffles.  F = q G grad_u, G = -h^-T diag(M).
 template <int P>
 struct GatherLanes {
-  static constexpr int L = P <= 2 ? 4 : (P <= 4 ? 4 : (P <= 8 ? 8 : 16));
+  static constexpr int L = gather_lanes(P);
 };
 
-template <typename R, int P, int NW>
-__global__ void __launch_bounds__(256) k_gather(DevPlan<R> d, R* __restrict__ f, FinalConsts fc,
+template <typename R, int P, int NW, bool BATCH>
+__global__ void __launch_bounds__(256) k_gather(KArg<R, BATCH> ka, R* __restrict__ f,
                                                 double* __restrict__ out7) {
   constexpr int L = GatherLanes<P>::L;
   constexpr int G = 256 / L;                          // particles per block
-  if (out7 && blockIdx.x == 0) {
+  int blk;
+  const DevPlan<R>& d = plan_of(ka, blk);
+  f += 3 * d.pofs;
+  if (out7 && blk == 0) {
     __shared__ double red[kNumSums * 16];
-    finalize_sums(d, fc, out7, red);
+    finalize_sums(d, out7 + kNumSums * d.rep, red);
   }
   extern __shared__ __align__(16) unsigned char smem[];
   R* win = reinterpret_cast<R*>(smem);                // (NW + 1) x P
@@ -156,7 +163,7 @@ __global__ void __launch_bounds__(256) k_gather(DevPlan<R> d, R* __restrict__ f,
   for (int k = threadIdx.x; k < (NW + 1) * P; k += blockDim.x) win[k] = d.win[k];
   __syncthreads();
   const int grp = threadIdx.x / L, lane = threadIdx.x - grp * L;
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * G + grp;
+  const int64_t i = static_cast<int64_t>(blk) * G + grp;
   const bool valid = i < d.n;
   const Record<R> rec = d.sorted[valid ? i : 0];
   int g1, g2, g3;
@@ -234,46 +241,79 @@ template <typename R, int P, int NW>
 static hipError_t spread_nw(const DevPlan<R>& d, hipStream_t s) {
   const size_t lds = lds_spread(d);
   if (lds > 65536)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spread<R, P, NW>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spread<R, P, NW, false>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-  hipLaunchKernelGGL((k_spread<R, P, NW>), dim3(d.ntiles), dim3(256), lds, s, d);
+  hipLaunchKernelGGL((k_spread<R, P, NW, false>), dim3(d.ntiles), dim3(256), lds, s, KArg<R, false>{d});
   return hipGetLastError();
 }
 
 template <typename R, int P, int NW>
-static hipError_t gather_nw(const DevPlan<R>& d, R* f, FinalConsts c, double* out7, hipStream_t s) {
+static size_t gather_lds() {
+  return ((NW + 1) * P + (256 / GatherLanes<P>::L) * 6 * P) * sizeof(R);
+}
+
+template <typename R, int P, int NW>
+static hipError_t gather_nw(const DevPlan<R>& d, R* f, double* out7, hipStream_t s) {
   constexpr int G = 256 / GatherLanes<P>::L;
   const int nb = static_cast<int>((d.n + G - 1) / G);
-  const size_t lds = ((NW + 1) * P + G * 6 * P) * sizeof(R);
-  hipLaunchKernelGGL((k_gather<R, P, NW>), dim3(nb), dim3(256), lds, s, d, f, c, out7);
+  hipLaunchKernelGGL((k_gather<R, P, NW, false>), dim3(nb), dim3(256), (gather_lds<R, P, NW>()), s,
+                     KArg<R, false>{d}, f, out7);
   return hipGetLastError();
 }
 
+template <typename R, int P, int NW>
+static hipError_t spread_nw_batch(const BatchLaunch<R>& b, hipStream_t s) {
+  if (b.lds > 65536)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spread<R, P, NW, true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(b.lds));
+  hipLaunchKernelGGL((k_spread<R, P, NW, true>), dim3(b.nblk), dim3(256), b.lds, s,
+                     KArg<R, true>{b.plans, b.boff, b.nrep});
+  return hipGetLastError();
+}
+
+template <typename R, int P, int NW>
+static hipError_t gather_nw_batch(const BatchLaunch<R>& b, R* f, double* out7, hipStream_t s) {
+  hipLaunchKernelGGL((k_gather<R, P, NW, true>), dim3(b.nblk), dim3(256), (gather_lds<R, P, NW>()), s,
+                     KArg<R, true>{b.plans, b.boff, b.nrep}, f, out7);
+  return hipGetLastError();
+}
+
+#define ESP_NW_SWITCH(NWV, FN, ...)                  \
+  switch (NWV) {                                     \
+    case 8: return FN<R, P, 8>(__VA_ARGS__);         \
+    case 12: return FN<R, P, 12>(__VA_ARGS__);       \
+    case 16: return FN<R, P, 16>(__VA_ARGS__);       \
+    default: return hipErrorInvalidValue;            \
+  }
+
 template <typename R, int P>
 hipError_t spread_launch(const DevPlan<R>& d, hipStream_t s) {
-  switch (d.nw) {
-    case 8: return spread_nw<R, P, 8>(d, s);
-    case 12: return spread_nw<R, P, 12>(d, s);
-    case 16: return spread_nw<R, P, 16>(d, s);
-    default: return hipErrorInvalidValue;
-  }
+  ESP_NW_SWITCH(d.nw, spread_nw, d, s)
 }
 
 template <typename R, int P>
-hipError_t gather_launch(const DevPlan<R>& d, R* f, FinalConsts c, double* out7, hipStream_t s) {
-  switch (d.nw) {
-    case 8: return gather_nw<R, P, 8>(d, f, c, out7, s);
-    case 12: return gather_nw<R, P, 12>(d, f, c, out7, s);
-    case 16: return gather_nw<R, P, 16>(d, f, c, out7, s);
-    default: return hipErrorInvalidValue;
-  }
+hipError_t gather_launch(const DevPlan<R>& d, R* f, double* out7, hipStream_t s) {
+  ESP_NW_SWITCH(d.nw, gather_nw, d, f, out7, s)
+}
+
+template <typename R, int P>
+hipError_t spread_launch_batch(const BatchLaunch<R>& b, hipStream_t s) {
+  ESP_NW_SWITCH(b.nw, spread_nw_batch, b, s)
+}
+
+template <typename R, int P>
+hipError_t gather_launch_batch(const BatchLaunch<R>& b, R* f, double* out7, hipStream_t s) {
+  ESP_NW_SWITCH(b.nw, gather_nw_batch, b, f, out7, s)
 }
 
 template hipError_t spread_launch<float, ESP_P>(const DevPlan<float>&, hipStream_t);
 template hipError_t spread_launch<double, ESP_P>(const DevPlan<double>&, hipStream_t);
-template hipError_t gather_launch<float, ESP_P>(const DevPlan<float>&, float*, FinalConsts, double*,
-                                                hipStream_t);
-template hipError_t gather_launch<double, ESP_P>(const DevPlan<double>&, double*, FinalConsts, double*,
-                                                 hipStream_t);
+template hipError_t gather_launch<float, ESP_P>(const DevPlan<float>&, float*, double*, hipStream_t);
+template hipError_t gather_launch<double, ESP_P>(const DevPlan<double>&, double*, double*, hipStream_t);
+template hipError_t spread_launch_batch<float, ESP_P>(const BatchLaunch<float>&, hipStream_t);
+template hipError_t spread_launch_batch<double, ESP_P>(const BatchLaunch<double>&, hipStream_t);
+template hipError_t gather_launch_batch<float, ESP_P>(const BatchLaunch<float>&, float*, double*, hipStream_t);
+template hipError_t gather_launch_batch<double, ESP_P>(const BatchLaunch<double>&, double*, double*,
+                                                       hipStream_t);
 
 }  // namespace espx

@@ -46,7 +46,8 @@ class Params(ctypes.Structure):
                 ("tile", ctypes.c_int * 3), ("ntiles", ctypes.c_int), ("window_degree", ctypes.c_int),
                 ("kernel_degree", ctypes.c_int), ("lambda0_split", ctypes.c_double),
                 ("C0_split", ctypes.c_double), ("psi0_split", ctypes.c_double),
-                ("volume", ctypes.c_double), ("params_source", ctypes.c_int)]
+                ("volume", ctypes.c_double), ("params_source", ctypes.c_int),
+                ("predicted_log10_err", ctypes.c_double * 4), ("predicted_cost", ctypes.c_double)]
 
     def as_dict(self):
         out = {}
@@ -54,6 +55,15 @@ class Params(ctypes.Structure):
             v = getattr(self, name)
             out[name] = list(v) if isinstance(v, ctypes.Array) else v
         return out
+
+
+PROPOSER_FEATURES = 4
+
+
+class Proposer(ctypes.Structure):
+    _fields_ = [("mlp", ctypes.c_void_p), ("in_mean", ctypes.c_double * PROPOSER_FEATURES),
+                ("in_std", ctypes.c_double * PROPOSER_FEATURES), ("out_mean", ctypes.c_double * 4),
+                ("out_std", ctypes.c_double * 4), ("margin", ctypes.c_double * 4), ("cost", ctypes.c_double * 5)]
 
 
 # (name, restype, argtypes) of every exported symbol declared in include/esp.h
@@ -83,6 +93,31 @@ SIGNATURES = [
     ("esp_profile_enable", ctypes.c_int, [_P, ctypes.c_uint, ctypes.c_int]),
     ("esp_profile_read", ctypes.c_int, [_P, _DP, ctypes.POINTER(ctypes.c_int64)]),
     ("esp_stage_name", ctypes.c_char_p, [ctypes.c_int]),
+    ("esp_mlp_create", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_uint64,
+                                      ctypes.POINTER(_P)]),
+    ("esp_mlp_num_params", ctypes.c_int64, [_P]),
+    ("esp_mlp_set_params", ctypes.c_int, [_P, _P, ctypes.c_int64]),
+    ("esp_mlp_get_params", ctypes.c_int, [_P, _P, ctypes.c_int64]),
+    ("esp_mlp_set_stream", ctypes.c_int, [_P, _P]),
+    ("esp_mlp_forward", ctypes.c_int, [_P, _P, ctypes.c_int64, _P]),
+    ("esp_mlp_gradient", ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int64, _P, _P]),
+    ("esp_mlp_train_step", ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int64, ctypes.c_float, _P]),
+    ("esp_mlp_destroy", None, [_P]),
+    ("esp_proposer_set", ctypes.c_int, [ctypes.POINTER(Proposer)]),
+    ("esp_batch_plan", ctypes.c_int, [ctypes.c_int, _DP, ctypes.POINTER(ctypes.c_int64), _DP,
+                                      ctypes.POINTER(Opts), ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_P)]),
+    ("esp_batch_energy_virial", ctypes.c_int, [_P, _P, _P, _P]),
+    ("esp_batch_forces", ctypes.c_int, [_P, _P, _P, _P, _P]),
+    ("esp_batch_energy_virial_f64", ctypes.c_int, [_P, _P, _P, _P]),
+    ("esp_batch_forces_f64", ctypes.c_int, [_P, _P, _P, _P, _P]),
+    ("esp_batch_set_box", ctypes.c_int, [_P, ctypes.c_int, _DP]),
+    ("esp_batch_set_stream", ctypes.c_int, [_P, _P]),
+    ("esp_batch_set_graph", ctypes.c_int, [_P, ctypes.c_int]),
+    ("esp_batch_check", ctypes.c_int, [_P]),
+    ("esp_batch_get_params", ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(Params)]),
+    ("esp_batch_num_launches", ctypes.c_int, [_P, ctypes.c_int]),
+    ("esp_batch_last_error", ctypes.c_char_p, [_P]),
+    ("esp_batch_destroy", None, [_P]),
     ("esp_version", ctypes.c_char_p, []),
 ]
 NUM_STAGES = 7
@@ -145,6 +180,9 @@ def make_opts(precision="fp32", params="analytic", coupling="iso", rc=0.9, c_spl
 def resolve_params(h, n, tol, **opts):
     """Parameters esp_plan would choose (host only, no device needed)."""
     o = make_opts(**opts)
+    if o.params == PARAMS["learned"]:
+        from . import learned
+        learned.ensure_default()
     _, hp = _cell(h)
     out = Params()
     st = lib().esp_resolve_params(hp, int(n), float(tol), ctypes.byref(o), ctypes.byref(out))
@@ -185,6 +223,9 @@ class Plan:
         self._torch = torch
         self._lib = lib()
         o = make_opts(**opts)
+        if o.params == PARAMS["learned"]:
+            from . import learned
+            learned.ensure_default()
         _, hp = _cell(h)
         handle = ctypes.c_void_p()
         st = self._lib.esp_plan(hp, int(n), float(tol), ctypes.byref(o), ctypes.byref(handle))
@@ -326,6 +367,124 @@ class Plan:
     def close(self):
         if getattr(self, "_h", None):
             self._lib.esp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent replicas evaluated together (one launch per stage).
+
+    ``cells``: sequence of 3x3 cells; ``ns``: particle counts; ``tols``:
+    tolerances.  Inputs are the replicas' arrays concatenated in order (torch
+    CUDA tensors); ``out7`` is (nrep, 7).
+    """
+
+    def __init__(self, cells, ns, tols, tiles=None, graph=False, **opts):
+        import torch
+        self._torch = torch
+        self._lib = lib()
+        o = make_opts(**opts)
+        if o.params == PARAMS["learned"]:
+            from . import learned
+            learned.ensure_default()
+        self.nrep = len(ns)
+        if not (len(cells) == len(tols) == self.nrep):
+            raise ValueError("cells, ns and tols must have one entry per replica")
+        h = np.ascontiguousarray(np.stack([np.asarray(c, np.float64).reshape(3, 3) for c in cells]))
+        n = np.ascontiguousarray(np.asarray(ns, np.int64))
+        tl = np.ascontiguousarray(np.asarray(tols, np.float64))
+        tp = None
+        if tiles is not None:
+            ta = (ctypes.c_int * self.nrep)(*[int(t) for t in tiles])
+            tp = ctypes.cast(ta, ctypes.POINTER(ctypes.c_int))
+        handle = ctypes.c_void_p()
+        st = self._lib.esp_batch_plan(self.nrep, h.ctypes.data_as(_DP), n.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                      tl.ctypes.data_as(_DP), ctypes.byref(o), tp, ctypes.byref(handle))
+        if st < 0:
+            raise EspError(st, "esp_batch_plan failed (see stderr)")
+        self.status = st
+        self._h = handle
+        self.ns = [int(v) for v in ns]
+        self.offsets = np.concatenate([[0], np.cumsum(self.ns)]).astype(np.int64)
+        self.params = []
+        for r in range(self.nrep):
+            prm = Params()
+            self._lib.esp_batch_get_params(self._h, r, ctypes.byref(prm))
+            self.params.append(prm.as_dict())
+        self.dtype = torch.float32 if self.params[0]["precision"] == 0 else torch.float64
+        if graph:
+            self.set_graph(True)
+
+    def _err(self, st, what):
+        msg = self._lib.esp_batch_last_error(self._h)
+        raise EspError(st, f"{what}: {msg.decode() if msg else ''}")
+
+    def _stream(self):
+        s = self._torch.cuda.current_stream().cuda_stream
+        self._lib.esp_batch_set_stream(self._h, ctypes.c_void_p(s))
+
+    def _check_in(self, xyz, q):
+        t = self._torch
+        N = int(self.offsets[-1])
+        for a, shape in ((xyz, (N, 3)), (q, (N,))):
+            if not a.is_cuda or a.dtype != self.dtype or tuple(a.shape) != shape or not a.is_contiguous():
+                raise ValueError(f"expected a contiguous {self.dtype} CUDA tensor of shape {shape}")
+        return t
+
+    def set_graph(self, enable):
+        st = self._lib.esp_batch_set_graph(self._h, 1 if enable else 0)
+        if st < 0:
+            self._err(st, "esp_batch_set_graph")
+
+    def num_launches(self, forces=True):
+        return int(self._lib.esp_batch_num_launches(self._h, 1 if forces else 0))
+
+    def energy_virial(self, xyz, q, out7=None):
+        t = self._check_in(xyz, q)
+        if out7 is None:
+            out7 = t.empty((self.nrep, 7), dtype=t.float64, device=xyz.device)
+        self._stream()
+        fn = self._lib.esp_batch_energy_virial if self.dtype == t.float32 else self._lib.esp_batch_energy_virial_f64
+        st = fn(self._h, _ptr(xyz), _ptr(q), _ptr(out7))
+        if st < 0:
+            self._err(st, "esp_batch_energy_virial")
+        return out7
+
+    def forces(self, xyz, q, f=None, out7=None, want_energy=True):
+        t = self._check_in(xyz, q)
+        if f is None:
+            f = t.empty((int(self.offsets[-1]), 3), dtype=self.dtype, device=xyz.device)
+        if out7 is None and want_energy:
+            out7 = t.empty((self.nrep, 7), dtype=t.float64, device=xyz.device)
+        self._stream()
+        fn = self._lib.esp_batch_forces if self.dtype == t.float32 else self._lib.esp_batch_forces_f64
+        st = fn(self._h, _ptr(xyz), _ptr(q), _ptr(f), _ptr(out7) if out7 is not None else None)
+        if st < 0:
+            self._err(st, "esp_batch_forces")
+        return f, out7
+
+    def set_box(self, r, h):
+        _, hp = _cell(h)
+        self._stream()
+        st = self._lib.esp_batch_set_box(self._h, int(r), hp)
+        if st < 0:
+            self._err(st, "esp_batch_set_box")
+        return st
+
+    def check(self):
+        st = self._lib.esp_batch_check(self._h)
+        if st < 0:
+            self._err(st, "esp_batch_check")
+        return st
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.esp_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

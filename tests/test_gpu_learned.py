@@ -1,0 +1,195 @@
+"""Learned parameter proposer on the GPU: the library's MLP kernels against
+the NumPy FP64 reference, training, registration with the planner, and the
+gain test (proposed parameters meet the tolerance against classical Ewald on
+systems that were not in the training data)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import mlp_reference as ref
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2601_00161_amd import esp, learned, synth  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _setup(dims, B, seed):
+    rng = np.random.default_rng(seed)
+    net = learned.Mlp(dims, seed=seed)
+    w = rng.normal(0, 0.4, net.num_params).astype(np.float32)
+    net.set_params(w)
+    x = rng.normal(size=(B, dims[0])).astype(np.float32)
+    t = rng.normal(size=(B, dims[-1])).astype(np.float32)
+    mask = (rng.random((B, dims[-1])) > 0.25).astype(np.float32)
+    return net, w.astype(np.float64), x, t, mask
+
+
+@pytest.mark.parametrize("dims,B", [([6, 16, 16, 4], 37), ([6, 48, 48, 4], 300), ([3, 5, 2], 1)])
+def test_mlp_forward_matches_numpy(dims, B):
+    net, w, x, _, _ = _setup(dims, B, 11)
+    y = net.forward(torch.tensor(x, device=DEV)).double().cpu().numpy()
+    y_ref = ref.forward(w, dims, x.astype(np.float64))[-1]
+    assert np.max(np.abs(y - y_ref)) < 1e-5 * max(1.0, np.max(np.abs(y_ref)))
+    net.close()
+
+
+@pytest.mark.parametrize("masked", [False, True])
+@pytest.mark.parametrize("dims,B", [([6, 16, 16, 4], 37), ([6, 48, 48, 4], 300)])
+def test_mlp_gradient_matches_numpy(dims, B, masked):
+    net, w, x, t, mask = _setup(dims, B, 12)
+    m = mask if masked else None
+    g, loss = net.gradient(torch.tensor(x, device=DEV), torch.tensor(t, device=DEV),
+                           None if m is None else torch.tensor(m, device=DEV))
+    g = g.double().cpu().numpy()
+    x64, t64 = x.astype(np.float64), t.astype(np.float64)
+    m64 = None if m is None else m.astype(np.float64)
+    g_ref = ref.gradient(w, dims, x64, t64, m64)
+    assert np.max(np.abs(g - g_ref)) < 2e-5 * np.max(np.abs(g_ref))
+    assert abs(float(loss.item()) - ref.loss(w, dims, x64, t64, m64)) < 1e-5 * ref.loss(w, dims, x64, t64, m64)
+    net.close()
+
+
+def test_adam_steps_match_numpy():
+    dims = [6, 12, 4]
+    net, w, x, t, _ = _setup(dims, 50, 13)
+    xt, tt = torch.tensor(x, device=DEV), torch.tensor(t, device=DEV)
+    m = np.zeros_like(w)
+    v = np.zeros_like(w)
+    x64, t64 = x.astype(np.float64), t.astype(np.float64)
+    for step in range(1, 4):
+        net.train_step(xt, tt, 1e-2)
+        w, m, v = ref.adam(w, ref.gradient(w, dims, x64, t64), m, v, step, 1e-2)
+    got = net.get_params().astype(np.float64)
+    assert np.max(np.abs(got - w)) < 1e-5
+    net.close()
+
+
+def test_training_fits_a_smooth_function():
+    rng = np.random.default_rng(5)
+    x = rng.uniform(-1, 1, size=(512, 6)).astype(np.float32)
+    t = np.stack([np.sin(2 * x[:, 0]) + x[:, 1] * x[:, 2], x[:, 3] ** 2 - x[:, 4],
+                  np.cos(x[:, 5]), x[:, 0] * x[:, 5]], axis=1).astype(np.float32)
+    net = learned.Mlp([6, 32, 32, 4], seed=3)
+    xt, tt = torch.tensor(x, device=DEV), torch.tensor(t, device=DEV)
+    _, l0 = net.gradient(xt, tt)
+    loss = torch.zeros(1, device=DEV)
+    for _ in range(1500):
+        net.train_step(xt, tt, 3e-3, loss=loss)
+    assert float(loss.item()) < 0.02 * float(l0.item())
+    net.close()
+
+
+def test_proposer_registration_validates():
+    net = learned.Mlp([esp.PROPOSER_FEATURES, 8, 3], seed=1)   # wrong output width
+    p = esp.Proposer()
+    p.mlp = net.handle.value
+    for i in range(esp.PROPOSER_FEATURES):
+        p.in_std[i] = 1.0
+    for i in range(4):
+        p.out_std[i] = 1.0
+    assert esp.lib().esp_proposer_set(p) == esp.ESP_EINVAL
+    net.close()
+
+
+def _shipped():
+    with open(learned.WEIGHTS_PATH) as f:
+        return json.load(f)
+
+
+@pytest.mark.skipif(not os.path.exists(learned.WEIGHTS_PATH), reason="no trained proposer weights shipped")
+@pytest.mark.parametrize("tol,coupling", [(1e-3, "iso"), (1e-4, "iso"), (1e-5, "iso"), (1e-6, "iso"),
+                                          (1e-5, "flex")])
+def test_learned_plan_meets_its_own_prediction(tol, coupling):
+    h, r, q = synth.config2()
+    rec = learned.ensure_default()
+    prm = esp.resolve_params(h, len(q), tol, params="learned", coupling=coupling)
+    assert prm["params_source"] == esp.PARAMS["learned"]
+    pred = prm["predicted_log10_err"]
+    need = [0, 1, 3] + ([2] if coupling == "flex" else [])
+    assert all(pred[j] <= np.log10(tol) - rec["margin"][j] + 1e-6 for j in need)
+    assert prm["predicted_cost"] > 0
+    # the plan takes the same parameters and runs
+    plan = esp.Plan(h, len(q), tol, params="learned", coupling=coupling)
+    assert plan.params["M"] == prm["M"] and plan.params["P"] == prm["P"]
+    xyz = torch.tensor(r, dtype=torch.float32, device=DEV)
+    out7 = plan.energy_virial(xyz, torch.tensor(q, dtype=torch.float32, device=DEV))
+    assert np.all(np.isfinite(out7.cpu().numpy()))
+    plan.close()
+
+
+# Held-out systems: seeds and boxes that are not in the training data.
+def _held_out():
+    tri = np.array([[2.9, 0.4, -0.3], [0, 2.9, 0.35], [0, 0, 2.9]])
+    ion = np.array([[3.8, 0.5, 0.3], [0, 3.8, 0.2], [0, 0, 3.8]])
+    return [
+        ("water_L3.1_seed41", synth.water(int(round(100 * 3.1 ** 3 / 3)), synth.cubic(3.1), config=1, seed=41)),
+        ("water_tri_L2.9_seed42", synth.water(int(round(100 * np.linalg.det(tri) / 3)), tri, config=1, seed=42)),
+        ("water_L2.7_seed44", synth.water(int(round(95 * 2.7 ** 3 / 3)), synth.cubic(2.7), config=1, seed=44)),
+        ("ionic_L3.8_seed43", synth.ionic(int(round(19200 / 16 / 729 * np.linalg.det(ion))), h=ion, config=3,
+                                          seed=43)),
+        # the membrane slab at the densities of the 25 x 25 x 20 nm system (10 dipole pairs per
+        # nm^2 of sheet, water triplets outside the bilayer)
+        ("membrane_3.2x3.2x4.3_seed45", synth.membrane(n_dipoles=int(round(125000 / 625 * 3.2 * 3.2)),
+                                                       n_water=int(round(250000 / (625 * 14) * 3.2 * 3.2 * (4.3 - 2.4))),
+                                                       L=(3.2, 3.2, 4.3), config=4, seed=45, sheet_offset=0.8,
+                                                       sheet_sigma=0.3, water_gap=1.2)),
+    ]
+
+
+def _errors(h, r, q, exact, plan, xyz, qt):
+    from oracle import esp_direct
+    prm = plan.params
+    f = torch.empty((len(q), 3), dtype=torch.float32, device=DEV)
+    out7 = torch.empty(7, dtype=torch.float64, device=DEV)
+    plan.forces(xyz, qt, f=f, out7=out7)
+    o = out7.cpu().numpy()
+    U_N, W_N, F_N = esp_direct.real_space(h, r, q, prm["c_split"], prm["rc"])
+    E = o[0] + U_N
+    W = np.array([[o[1], o[4], o[5]], [o[4], o[2], o[6]], [o[5], o[6], o[3]]]) + W_N
+    F = f.double().cpu().numpy() + F_N
+    Wr = exact.virial
+    e_E = abs(E - exact.energy) / abs(exact.energy)
+    e_d = np.sqrt(sum((W[a, a] - Wr[a, a]) ** 2 for a in range(3))) / np.sqrt(sum(Wr[a, a] ** 2 for a in range(3)))
+    e_F = np.sqrt(np.sum((F - exact.forces) ** 2) / np.sum(exact.forces ** 2))
+    return e_E, e_d, e_F
+
+
+@pytest.mark.skipif(not os.path.exists(learned.WEIGHTS_PATH), reason="no trained proposer weights shipped")
+def test_learned_parameters_meet_tolerance_against_ewald():
+    """Gain test (i): on held-out systems and tolerances 1e-3 ... 1e-6 the
+    learned parameters (FP32 path, total Coulomb = GPU reciprocal part +
+    oracle real-space part) meet the tolerance in energy, diagonal pressure
+    and RMS force against classical Ewald in at least 95 % of the cases.  The
+    analytic rule is scored on the same cases for comparison."""
+    from oracle import ewald
+    learned.ensure_default()
+    cases, passed, passed_ana = 0, 0, 0
+    for name, (h, r, q) in _held_out():
+        r = r.astype(np.float32).astype(np.float64)
+        q = q.astype(np.float32).astype(np.float64)
+        exact = ewald.ewald(h, r, q)
+        xyz = torch.tensor(r, dtype=torch.float32, device=DEV)
+        qt = torch.tensor(q, dtype=torch.float32, device=DEV)
+        for tol in (1e-3, 1e-4, 1e-5, 1e-6):
+            plan = esp.Plan(h, len(q), tol, params="learned")
+            err = _errors(h, r, q, exact, plan, xyz, qt)
+            ana = esp.Plan(h, len(q), tol)
+            err_a = _errors(h, r, q, exact, ana, xyz, qt)
+            prm, pa = plan.params, ana.params
+            ok, ok_a = max(err) <= tol, max(err_a) <= tol
+            cases += 1
+            passed += ok
+            passed_ana += ok_a
+            print(f"{name} tol={tol:g} learned(src={prm['params_source']} d={prm['delta']:.2g} P={prm['P']} "
+                  f"M={list(prm['M'])}) E/diag/F={err[0]:.1e}/{err[1]:.1e}/{err[2]:.1e} {'ok' if ok else 'FAIL'} | "
+                  f"analytic(P={pa['P']} M={list(pa['M'])}) {err_a[0]:.1e}/{err_a[1]:.1e}/{err_a[2]:.1e} "
+                  f"{'ok' if ok_a else 'FAIL'}", flush=True)
+            plan.close()
+            ana.close()
+    print(f"learned: {passed}/{cases} cases meet tol; analytic: {passed_ana}/{cases}", flush=True)
+    assert passed >= 0.95 * cases

@@ -113,3 +113,34 @@ def test_tiny_cell_rule_respects_support():
     """Grids never get fewer points than the window support."""
     p = esp.resolve_params(np.diag([1.9, 1.9, 1.9]), 12, 1e-7)
     assert min(p["M"]) >= p["P"]
+
+
+def test_learned_without_proposer_falls_back_to_analytic():
+    """No registered network: ESP_LEARNED resolves to the analytic rule with a
+    warning status (called through the C ABI directly; the Python binding
+    would register the shipped weights, which needs a GPU)."""
+    import ctypes
+    lib = esp.lib()
+    assert lib.esp_proposer_set(None) == esp.ESP_OK
+    h = np.diag([6.7, 6.7, 6.7])
+    hp = np.ascontiguousarray(h)
+    o = esp.make_opts(params="learned")
+    out = esp.Params()
+    st = lib.esp_resolve_params(hp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 30000, 1e-5,
+                                ctypes.byref(o), ctypes.byref(out))
+    assert st == esp.ESP_WARN_FALLBACK
+    ana = esp.resolve_params(h, 30000, 1e-5)
+    got = out.as_dict()
+    assert got["params_source"] == esp.PARAMS["analytic"]
+    for k in ("delta", "c_split", "P", "M"):
+        assert got[k] == ana[k]
+    assert list(got["predicted_log10_err"]) == [0.0] * 4
+
+
+def test_proposer_registration_rejects_missing_network():
+    p = esp.Proposer()
+    for i in range(esp.PROPOSER_FEATURES):
+        p.in_std[i] = 1.0
+    for i in range(4):
+        p.out_std[i] = 1.0
+    assert esp.lib().esp_proposer_set(p) == esp.ESP_EINVAL
