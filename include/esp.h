@@ -201,14 +201,15 @@ double esp_c_from_delta(double delta);
  * two make up the cell sort), 2 spread, 3 fft_xy, 4 fft_z (z transform +
  * scaling/reduction + final FP64 sums [+ G and inverse z]), 5 fft_xy_inv,
  * 6 gather.
- * esp_profile_enable: record a HIP event pair on the plan's stream around each
- *   launch of the stages in stage_mask (bit s = stage s), for up to
- *   max_launches launches per stage; mask 0 turns profiling off.  Synchronises.
+ * esp_profile_enable: record a HIP event pair on the plan's stream around
+ *   every stride-th launch (stride >= 1) of the stages in stage_mask (bit s =
+ *   stage s), for up to max_launches timed launches per stage; mask 0 turns
+ *   profiling off.  Synchronises.
  * esp_profile_read: synchronise and return, per stage (ESP_NUM_STAGES
  *   entries, host arrays), the accumulated milliseconds and launch counts
  *   since profiling was enabled. */
 #define ESP_NUM_STAGES 7
-esp_status esp_profile_enable(esp_plan_t *p, unsigned stage_mask, int max_launches);
+esp_status esp_profile_enable(esp_plan_t *p, unsigned stage_mask, int max_launches, int stride);
 esp_status esp_profile_read(esp_plan_t *p, double *total_ms, int64_t *launches);
 const char *esp_stage_name(int stage);
 

@@ -359,6 +359,8 @@ const char* kStageNames[ST_COUNT] = {"bin", "scatter", "spread", "fft_xy", "fft_
 struct Profiler {
   unsigned mask = 0;
   int cap = 0;
+  int stride = 1;                // time every stride-th launch of a stage
+  long long seen[ST_COUNT] = {};
   std::vector<hipEvent_t> ev[ST_COUNT];
   int used[ST_COUNT] = {};
   double ms[ST_COUNT] = {};
@@ -634,7 +636,7 @@ esp_status build_device(esp_plan_t* p) {
 template <class F>
 hipError_t stage(esp_plan_t* p, int st, F&& launch) {
   Profiler& pr = p->prof;
-  const bool on = ((pr.mask >> st) & 1u) && pr.used[st] < pr.cap;
+  const bool on = ((pr.mask >> st) & 1u) && pr.used[st] < pr.cap && pr.seen[st]++ % pr.stride == 0;
   if (on) (void)hipEventRecord(pr.ev[st][2 * pr.used[st]], p->stream);
   hipError_t e = launch();
   if (on) {
@@ -1021,16 +1023,18 @@ double esp_c_from_delta(double delta) {
   }
 }
 
-esp_status esp_profile_enable(esp_plan_t* p, unsigned stage_mask, int max_launches) {
-  if (!p || max_launches < 0 || max_launches > (1 << 20)) return ESP_EINVAL;
+esp_status esp_profile_enable(esp_plan_t* p, unsigned stage_mask, int max_launches, int stride) {
+  if (!p || max_launches < 0 || max_launches > (1 << 20) || stride < 1) return ESP_EINVAL;
   hipError_t e = hipStreamSynchronize(p->stream);
   if (e != hipSuccess) return hip_fail(p, e, "stream synchronise");
   Profiler& pr = p->prof;
   pr.release();
   pr.mask = stage_mask & ((1u << ST_COUNT) - 1);
   pr.cap = pr.mask ? max_launches : 0;
+  pr.stride = stride;
   for (int s = 0; s < ST_COUNT; ++s) {
     pr.used[s] = 0;
+    pr.seen[s] = 0;
     pr.ms[s] = 0;
     pr.cnt[s] = 0;
     if (!((pr.mask >> s) & 1u)) continue;

@@ -90,7 +90,7 @@ SIGNATURES = [
     ("esp_resolve_params", ctypes.c_int, [_DP, ctypes.c_int64, _D, ctypes.POINTER(Opts), ctypes.POINTER(Params)]),
     ("esp_pswf_eval", ctypes.c_int, [_D, ctypes.c_int64, _DP, _DP, _DP, _DP, _DP]),
     ("esp_c_from_delta", ctypes.c_double, [_D]),
-    ("esp_profile_enable", ctypes.c_int, [_P, ctypes.c_uint, ctypes.c_int]),
+    ("esp_profile_enable", ctypes.c_int, [_P, ctypes.c_uint, ctypes.c_int, ctypes.c_int]),
     ("esp_profile_read", ctypes.c_int, [_P, _DP, ctypes.POINTER(ctypes.c_int64)]),
     ("esp_stage_name", ctypes.c_char_p, [ctypes.c_int]),
     ("esp_mlp_create", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_uint64,
@@ -345,13 +345,13 @@ class Plan:
         return phi
 
     # -- per-stage timing ------------------------------------------------------
-    def profile(self, stages, max_launches):
-        """Record HIP events around every launch of the named stages."""
+    def profile(self, stages, max_launches, stride=1):
+        """Record HIP events around every stride-th launch of the named stages."""
         names = [self._lib.esp_stage_name(i).decode() for i in range(NUM_STAGES)]
         mask = 0
         for s in stages:
             mask |= 1 << names.index(s)
-        st = self._lib.esp_profile_enable(self._h, mask, int(max_launches))
+        st = self._lib.esp_profile_enable(self._h, mask, int(max_launches), int(stride))
         if st < 0:
             self._err(st, "esp_profile_enable")
 
