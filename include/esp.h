@@ -117,6 +117,8 @@ typedef struct {
   int params_source;   /* ESP_ANALYTIC / ESP_EXPLICIT / ESP_LEARNED actually used */
   double predicted_log10_err[4];  /* ESP_LEARNED: the proposer's prediction, else 0 */
   double predicted_cost;          /* ESP_LEARNED: cost-model value of the choice */
+  int gather_tiled;               /* 1: the gather stages each tile's potential in LDS */
+  int counter_copies;             /* tile-counter copies used by the cell sort */
 } esp_params;
 
 void esp_opts_default(esp_opts *o);

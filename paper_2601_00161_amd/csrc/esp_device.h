@@ -19,6 +19,9 @@ constexpr int kMaxRadix = 5;
 constexpr int kMaxStages = 16;
 constexpr int kNumSums = 7;        // energy + 6 virial components
 constexpr int kSpreadChunk = 64;   // particles staged per spreading round
+constexpr int kTiledGatherMin = 96;  // mean particles per tile above which the gather is tile-staged
+constexpr int kBinContention = 64;   // target same-address atomics per tile counter in binning
+constexpr int kMaxCounterCopies = 16;
 
 template <typename R>
 struct Cplx {
@@ -86,7 +89,7 @@ struct DevPlan {
   const Cplx<R>* tw;               // twiddles for the three lengths
   FftLen f1, f2, f3;
   // buffers
-  int* counts;                     // ntiles
+  int* counts;                     // nsub x ntiles
   int* offsets;                    // ntiles + 1
   int* keys;                       // n
   int* ranks;                      // n
@@ -100,6 +103,9 @@ struct DevPlan {
   double* qpart;                   // nbin x 2 partial sums (sum q, sum q^2)
   int* flags;                      // bit 0: non-finite input; bit 1: inconsistent tile counts
   int bin_lds;                     // tile histogram of the binning pass fits in LDS
+  int gather_tiled;                // gather stages each tile's potential box in LDS
+  int nsub;                        // tile counters per tile: binning block b uses copy b % nsub
+  int* sbase;                      // nsub > 1: nsub x ntiles first rank of each copy in its tile
   FinalConsts fin;                 // final-sum constants (updated by esp_set_box)
   int64_t pofs;                    // batched launches: first particle of this plan in the
   int rep;                         // concatenated inputs, and its index (0 for single plans)
@@ -139,6 +145,10 @@ template <typename R>
 hipError_t launch_bin(const DevPlan<R>& d, const R* xyz, const R* q, hipStream_t s);
 template <typename R>
 hipError_t launch_scatter(const DevPlan<R>& d, hipStream_t s);
+// nsub > 1 only: tile offsets and per-copy bases from the counter copies
+// (one workgroup), which also clears the counters.
+template <typename R>
+hipError_t launch_scan_sub(const DevPlan<R>& d, hipStream_t s);
 // Final sums into out7 (one workgroup) after a z-pass in energy mode.
 template <typename R>
 hipError_t launch_finalize(const DevPlan<R>& d, double* out7, hipStream_t s);
@@ -165,6 +175,8 @@ hipError_t launch_bin_batch(const BatchLaunch<R>& b, const R* xyz, const R* q, h
 template <typename R>
 hipError_t launch_scatter_batch(const BatchLaunch<R>& b, hipStream_t s);
 template <typename R>
+hipError_t launch_scan_sub_batch(const BatchLaunch<R>& b, hipStream_t s);
+template <typename R>
 hipError_t launch_spread_batch(const BatchLaunch<R>& b, hipStream_t s);
 template <typename R>
 hipError_t launch_fft_xy_batch(const BatchLaunch<R>& b, hipStream_t s);
@@ -187,6 +199,9 @@ template <typename R>
 size_t lds_fft_z(const DevPlan<R>& d);
 template <typename R>
 size_t lds_spread(const DevPlan<R>& d);
+// Potential box of the tile-staged gather: (T_d + P - 1) cells per dimension.
+template <typename R>
+size_t lds_gather_box(const DevPlan<R>& d);
 int fft_threads(int lines_x_len);
 
 }  // namespace espx

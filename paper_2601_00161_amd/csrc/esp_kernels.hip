@@ -86,15 +86,17 @@ __global__ void __launch_bounds__(256) k_bin(KArg<R, BATCH> ka, const R* __restr
     Coord<R>::stencil(rec, 1, d.M2, d.P, g2, t);
     Coord<R>::stencil(rec, 2, d.M3, d.P, g3, t);
     key = ((g3 / d.T3) * d.nt2 + g2 / d.T2) * d.nt1 + g1 / d.T1;
-    lr = lh ? atomicAdd(hist + key, 1) : atomicAdd(d.counts + key, 1);
+    lr = lh ? atomicAdd(hist + key, 1)
+            : atomicAdd(d.counts + static_cast<size_t>(blk % d.nsub) * d.ntiles + key, 1);
     v[0] = static_cast<double>(qi);
     v[1] = static_cast<double>(qi) * static_cast<double>(qi);
   }
   __syncthreads();
+  int* counts = d.counts + static_cast<size_t>(blk % d.nsub) * d.ntiles;
   if (lh)
     for (int k = threadIdx.x; k < d.ntiles; k += blockDim.x) {
       const int c = hist[k];
-      if (c) hist[k] = atomicAdd(d.counts + k, c);
+      if (c) hist[k] = atomicAdd(counts + k, c);
     }
   __syncthreads();
   if (i < d.n) {
@@ -108,17 +110,78 @@ __global__ void __launch_bounds__(256) k_bin(KArg<R, BATCH> ka, const R* __restr
   }
 }
 
-// Cell sort, pass 2.  Every block scans the tile counts itself (they are few)
-// and scatters its particles to offset[key] + rank; block 0 also publishes the
-// offsets for the spreading pass.
+// Tile offsets for nsub > 1 counter copies (large systems, where one counter
+// per tile would see hundreds of same-address atomics): one workgroup turns
+// the copies into per-copy bases within each tile and the tile offsets, and
+// clears the counters for the next call.
+template <typename R, bool BATCH>
+__global__ void __launch_bounds__(1024) k_scan_sub(KArg<R, BATCH> ka) {
+  __shared__ int part[1024];
+  int blk;
+  const DevPlan<R>& d = plan_of(ka, blk);
+  if (d.nsub <= 1) return;
+  const int nt = d.ntiles, nth = blockDim.x, tid = threadIdx.x;
+  const int chunk = (nt + nth - 1) / nth;
+  const int t0 = min(nt, tid * chunk), t1 = min(nt, t0 + chunk);
+  // pass 1 (own tiles only): bases within each tile; the tile total is kept
+  // in the first copy's counter until pass 2
+  int sum = 0;
+  for (int t = t0; t < t1; ++t) {
+    int run = 0;
+    for (int c = 0; c < d.nsub; ++c) {
+      const size_t k = static_cast<size_t>(c) * nt + t;
+      const int v = d.counts[k];
+      d.sbase[k] = run;
+      d.counts[k] = 0;
+      run += v;
+    }
+    d.counts[t] = run;
+    sum += run;
+  }
+  part[tid] = sum;
+  __syncthreads();
+  for (int off = 1; off < nth; off <<= 1) {
+    const int add = tid >= off ? part[tid - off] : 0;
+    __syncthreads();
+    part[tid] += add;
+    __syncthreads();
+  }
+  int run = part[tid] - sum;
+  for (int t = t0; t < t1; ++t) {
+    const int tot = d.counts[t];
+    d.counts[t] = 0;
+    d.offsets[t] = run;
+    for (int c = 0; c < d.nsub; ++c) d.sbase[static_cast<size_t>(c) * nt + t] += run;
+    run += tot;
+  }
+  if (tid == nth - 1) d.offsets[nt] = part[nth - 1];
+}
+
+// Cell sort, pass 2.  With one counter per tile every block scans the tile
+// counts itself (they are few) and scatters its particles to offset[key] +
+// rank, and block 0 publishes the offsets for the spreading pass; with
+// counter copies the bases come from k_scan_sub.
 template <typename R, bool BATCH>
 __global__ void __launch_bounds__(1024) k_scatter(KArg<R, BATCH> ka) {
   extern __shared__ int offs[];             // ntiles + 1
   __shared__ int part[1024];
   int blk;
   const DevPlan<R>& d = plan_of(ka, blk);
-  block_scan(d.counts, offs, d.ntiles, part);
   const int64_t i = static_cast<int64_t>(blk) * blockDim.x + threadIdx.x;
+  if (d.nsub > 1) {
+    if (i < d.n) {
+      const size_t copy = static_cast<size_t>((i / 256) % d.nsub);   // binning block of particle i
+      const int pos = d.sbase[copy * d.ntiles + d.keys[i]] + d.ranks[i];
+      if (pos >= 0 && pos < d.n) {
+        d.sorted[pos] = d.tmp[i];
+        d.perm[pos] = static_cast<int>(i);
+      } else {
+        atomicOr(d.flags, 2);
+      }
+    }
+    return;
+  }
+  block_scan(d.counts, offs, d.ntiles, part);
   if (i < d.n) {
     const int pos = offs[d.keys[i]] + d.ranks[i];
     if (pos >= 0 && pos < d.n) {
@@ -401,6 +464,13 @@ inline KArg<R, true> karg(const BatchLaunch<R>& b) {
 }
 
 template <typename R>
+size_t lds_gather_box(const DevPlan<R>& d) {
+  const size_t E1 = std::min(d.T1, d.M1) + d.P - 1, E2 = std::min(d.T2, d.M2) + d.P - 1,
+               E3 = std::min(d.T3, d.M3) + d.P - 1;
+  return E1 * E2 * E3 * sizeof(R);
+}
+
+template <typename R>
 hipError_t launch_bin(const DevPlan<R>& d, const R* xyz, const R* q, hipStream_t s) {
   const size_t lds = d.bin_lds ? static_cast<size_t>(d.ntiles) * sizeof(int) : 0;
   hipLaunchKernelGGL((k_bin<R, false>), dim3(d.nbin), dim3(256), lds, s, KArg<R, false>{d}, xyz, q);
@@ -413,6 +483,12 @@ hipError_t launch_scatter(const DevPlan<R>& d, hipStream_t s) {
   const size_t lds = (static_cast<size_t>(d.ntiles) + 1) * sizeof(int);
   allow_lds(reinterpret_cast<const void*>(&k_scatter<R, false>), lds);
   hipLaunchKernelGGL((k_scatter<R, false>), dim3(nb), dim3(1024), lds, s, KArg<R, false>{d});
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_scan_sub(const DevPlan<R>& d, hipStream_t s) {
+  hipLaunchKernelGGL((k_scan_sub<R, false>), dim3(1), dim3(1024), 0, s, KArg<R, false>{d});
   return hipGetLastError();
 }
 
@@ -493,6 +569,12 @@ hipError_t launch_scatter_batch(const BatchLaunch<R>& b, hipStream_t s) {
 }
 
 template <typename R>
+hipError_t launch_scan_sub_batch(const BatchLaunch<R>& b, hipStream_t s) {
+  hipLaunchKernelGGL((k_scan_sub<R, true>), dim3(b.nblk), dim3(1024), 0, s, karg(b));
+  return hipGetLastError();
+}
+
+template <typename R>
 hipError_t launch_spread_batch(const BatchLaunch<R>& b, hipStream_t s) {
   ESP_P_SWITCH(b.P, spread_launch_batch, b, s)
 }
@@ -541,6 +623,8 @@ hipError_t launch_fill(T* p, size_t count, hipStream_t s) {
 #define ESP_INSTANTIATE(R)                                                                    \
   template hipError_t launch_bin<R>(const DevPlan<R>&, const R*, const R*, hipStream_t);      \
   template hipError_t launch_scatter<R>(const DevPlan<R>&, hipStream_t);                      \
+  template hipError_t launch_scan_sub<R>(const DevPlan<R>&, hipStream_t);                     \
+  template hipError_t launch_scan_sub_batch<R>(const BatchLaunch<R>&, hipStream_t);           \
   template hipError_t launch_finalize<R>(const DevPlan<R>&, double*, hipStream_t);            \
   template hipError_t launch_spread<R>(const DevPlan<R>&, hipStream_t);                       \
   template hipError_t launch_fft_xy<R>(const DevPlan<R>&, const R*, Cplx<R>*, bool, hipStream_t); \
@@ -558,7 +642,8 @@ hipError_t launch_fill(T* p, size_t count, hipStream_t s) {
   template hipError_t launch_fill<R>(R*, size_t, hipStream_t);                                \
   template size_t lds_fft_xy<R>(const DevPlan<R>&);                                           \
   template size_t lds_fft_z<R>(const DevPlan<R>&);                                            \
-  template size_t lds_spread<R>(const DevPlan<R>&);
+  template size_t lds_spread<R>(const DevPlan<R>&);                                           \
+  template size_t lds_gather_box<R>(const DevPlan<R>&);
 
 ESP_INSTANTIATE(float)
 ESP_INSTANTIATE(double)

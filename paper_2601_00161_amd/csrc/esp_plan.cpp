@@ -616,7 +616,14 @@ esp_status build_device(esp_plan_t* p) {
   // ---- buffers -----------------------------------------------------------
   const size_t G = static_cast<size_t>(r.M[0]) * r.M[1] * r.M[2];
   const size_t S = static_cast<size_t>(d.H) * r.M[1] * r.M[2];
-  if ((st = dalloc(p, &d.counts, r.ntiles)) || (st = dalloc(p, &d.offsets, r.ntiles + 1)) ||
+  // counter copies: about kBinContention same-address atomics per counter at most
+  {
+    const double per = static_cast<double>(d.nbin) * std::min(256, r.ntiles) / r.ntiles;
+    d.nsub = std::max(1, std::min(kMaxCounterCopies, static_cast<int>(std::ceil(per / kBinContention))));
+  }
+  const size_t ncount = static_cast<size_t>(r.ntiles) * d.nsub;
+  if ((st = dalloc(p, &d.counts, ncount)) || (st = dalloc(p, &d.sbase, d.nsub > 1 ? ncount : 1)) ||
+      (st = dalloc(p, &d.offsets, r.ntiles + 1)) ||
       (st = dalloc(p, &d.keys, r.n)) || (st = dalloc(p, &d.ranks, r.n)) || (st = dalloc(p, &d.perm, r.n)) ||
       (st = dalloc(p, &d.tmp, r.n)) || (st = dalloc(p, &d.sorted, r.n)) || (st = dalloc(p, &d.rho, G)) ||
       (st = dalloc(p, &d.spec, S)) || (st = dalloc(p, &d.phi, G)) ||
@@ -624,7 +631,11 @@ esp_status build_device(esp_plan_t* p) {
       (st = dalloc(p, &d.qpart, static_cast<size_t>(d.nbin) * 2)) || (st = dalloc(p, &d.flags, 4)))
     return st;
   d.bin_lds = r.ntiles <= 8192 ? 1 : 0;
-  e = hipMemset(d.counts, 0, r.ntiles * sizeof(int));
+  // dense tiles: stage each tile's potential box in LDS for the gather
+  const size_t gather_base = ((p->nw + 1) * r.P + (256 / gather_lanes(r.P)) * 6 * r.P) * sizeof(R);
+  d.gather_tiled = r.n >= static_cast<int64_t>(kTiledGatherMin) * r.ntiles &&
+                   gather_base + lds_gather_box(d) <= static_cast<size_t>(maxlds);
+  e = hipMemset(d.counts, 0, ncount * sizeof(int));
   if (e == hipSuccess) e = hipMemset(d.rho, 0, G * sizeof(R));
   if (e == hipSuccess) e = hipMemset(d.flags, 0, 4 * sizeof(int));
   if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -650,7 +661,11 @@ hipError_t stage(esp_plan_t* p, int st, F&& launch) {
 template <typename R>
 hipError_t run_sort(esp_plan_t* p, const R* xyz, const R* q) {
   DevPlan<R>& d = dev<R>(p);
-  hipError_t e = stage(p, ST_BIN, [&] { return launch_bin(d, xyz, q, p->stream); });
+  hipError_t e = stage(p, ST_BIN, [&] {
+    hipError_t eb = launch_bin(d, xyz, q, p->stream);
+    if (eb == hipSuccess && d.nsub > 1) eb = launch_scan_sub(d, p->stream);
+    return eb;
+  });
   if (e == hipSuccess) e = stage(p, ST_SCATTER, [&] { return launch_scatter(d, p->stream); });
   return e;
 }
@@ -902,6 +917,8 @@ esp_status esp_get_params(const esp_plan_t* p, esp_params* out) {
   out->params_source = r.params_source;
   for (int j = 0; j < 4; ++j) out->predicted_log10_err[j] = r.pred[j];
   out->predicted_cost = r.pred_cost;
+  out->gather_tiled = r.precision == ESP_FP32 ? p->d32.gather_tiled : p->d64.gather_tiled;
+  out->counter_copies = r.precision == ESP_FP32 ? p->d32.nsub : p->d64.nsub;
   return ESP_OK;
 }
 
@@ -932,7 +949,8 @@ esp_status esp_stage_sort(esp_plan_t* p, const void* xyz, const void* q, int32_t
     counts = p->d64.counts;
   }
   // no spreading pass follows: clear the tile counts here
-  if (e == hipSuccess) e = launch_fill(counts, p->r.ntiles, p->stream);
+  const int nsub = p->r.precision == ESP_FP32 ? p->d32.nsub : p->d64.nsub;
+  if (e == hipSuccess) e = launch_fill(counts, static_cast<size_t>(p->r.ntiles) * nsub, p->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(perm_out, perm, p->r.n * sizeof(int), hipMemcpyDeviceToDevice, p->stream);
   if (e == hipSuccess)
@@ -1138,6 +1156,7 @@ struct esp_batch_s {
   size_t plan_bytes = 0;
   BatchStage bin, scatter, fxy, fz, fxyi, fin;
   std::vector<BatchStage> spread, gather;
+  bool any_sub = false;           // some replica bins into counter copies
   bool use_graph = false;
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
@@ -1208,6 +1227,8 @@ esp_status batch_build(esp_batch_t* b) {
   make(b->fxyi, 0, nrep, [](const DevPlan<R>& d) { return d.M3; }, [](const DevPlan<R>& d) { return lds_fft_xy(d); },
        nth_xy);
   make(b->fin, 0, nrep, [](const DevPlan<R>&) { return 1; }, zero, 256);
+  b->any_sub = false;
+  for (const DevPlan<R>& d : hp) b->any_sub = b->any_sub || d.nsub > 1;
   b->spread.clear();
   b->gather.clear();
   for (int k = 0; k < nrep;) {
@@ -1253,6 +1274,7 @@ template <typename R>
 hipError_t batch_launches(const esp_batch_t* b, const R* xyz, const R* q, R* f, double* out7, bool forces,
                           hipStream_t s) {
   hipError_t e = launch_bin_batch(batch_launch<R>(b, b->bin), xyz, q, s);
+  if (e == hipSuccess && b->any_sub) e = launch_scan_sub_batch(batch_launch<R>(b, b->fin), s);
   if (e == hipSuccess) e = launch_scatter_batch(batch_launch<R>(b, b->scatter), s);
   for (const BatchStage& g : b->spread)
     if (e == hipSuccess) e = launch_spread_batch(batch_launch<R>(b, g), s);
@@ -1447,7 +1469,8 @@ esp_status esp_batch_get_params(const esp_batch_t* b, int r, esp_params* out) {
 int esp_batch_num_launches(const esp_batch_t* b, int forces) {
   if (!b) return -1;
   const int groups = static_cast<int>(b->spread.size());
-  return forces ? 2 + groups + 3 + groups : 2 + groups + 3;
+  const int sort = b->any_sub ? 3 : 2;
+  return forces ? sort + groups + 3 + groups : sort + groups + 3;
 }
 
 const char* esp_batch_last_error(const esp_batch_t* b) { return b ? b->err.c_str() : "null batch"; }

@@ -236,6 +236,114 @@ __global__ void __launch_bounds__(256) k_gather(KArg<R, BATCH> ka, R* __restrict
   }
 }
 
+// Tile-staged gather, for dense tiles: one workgroup per tile.  The
+// potential on the tile's stencil box (its cells plus P - 1 more along each
+// cell vector, cyclically) is staged in LDS once, then the tile's particles
+// (contiguous after the sort) are processed as in k_gather, reading the
+// potential from LDS instead of L2.
+template <typename R, int P, int NW, bool BATCH>
+__global__ void __launch_bounds__(256) k_gather_tile(KArg<R, BATCH> ka, R* __restrict__ f,
+                                                double* __restrict__ out7) {
+  constexpr int L = GatherLanes<P>::L;
+  constexpr int G = 256 / L;                          // particles per round
+  int tile;
+  const DevPlan<R>& d = plan_of(ka, tile);
+  f += 3 * d.pofs;
+  if (out7 && tile == 0) {
+    __shared__ double red[kNumSums * 16];
+    finalize_sums(d, out7 + kNumSums * d.rep, red);
+  }
+  extern __shared__ __align__(16) unsigned char smem[];
+  R* win = reinterpret_cast<R*>(smem);                // (NW + 1) x P
+  R* wt = win + (NW + 1) * P;                         // G x 6 x P: w1 d1 w2 d2 w3 d3
+  R* box = wt + G * 6 * P;                            // E1 x E2 x E3 potential values
+  const int start = d.offsets[tile], end = d.offsets[tile + 1];
+  if (start == end) return;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int t1 = tile % d.nt1, t2 = (tile / d.nt1) % d.nt2, t3 = tile / (d.nt1 * d.nt2);
+  const int o1 = t1 * d.T1, o2 = t2 * d.T2, o3 = t3 * d.T3;
+  const int E1 = min(d.T1, d.M1 - o1) + P - 1;
+  const int E2 = min(d.T2, d.M2 - o2) + P - 1;
+  const int E3 = min(d.T3, d.M3 - o3) + P - 1;
+  for (int k = tid; k < (NW + 1) * P; k += nth) win[k] = d.win[k];
+  for (int k = tid; k < E1 * E2 * E3; k += nth) {
+    const int x = k % E1, y = (k / E1) % E2, z = k / (E1 * E2);
+    int gx = o1 + x, gy = o2 + y, gz = o3 + z;
+    gx -= gx >= d.M1 ? d.M1 : 0;
+    gy -= gy >= d.M2 ? d.M2 : 0;
+    gz -= gz >= d.M3 ? d.M3 : 0;
+    box[k] = d.phi[(static_cast<size_t>(gz) * d.M2 + gy) * d.M1 + gx];
+  }
+  const int grp = tid / L, lane = tid - grp * L;
+  R* my = wt + grp * 6 * P;
+  for (int base = start; base < end; base += G) {
+    const int i = base + grp;
+    const bool valid = i < end;
+    const Record<R> rec = d.sorted[valid ? i : start];
+    int g1, g2, g3;
+    R u1, u2, u3;
+    Coord<R>::stencil(rec, 0, d.M1, P, g1, u1);
+    Coord<R>::stencil(rec, 1, d.M2, P, g2, u2);
+    Coord<R>::stencil(rec, 2, d.M3, P, g3, u3);
+    __syncthreads();                                  // box staged / previous round done with wt
+    if (lane < 3) {
+      const R tau = lane == 0 ? u1 : (lane == 1 ? u2 : u3);
+      R w[P], dw[P];
+      eval_window_d<R, P, NW>(win, tau, w, dw);
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        my[2 * lane * P + p] = w[p];
+        my[(2 * lane + 1) * P + p] = dw[p];
+      }
+    }
+    __syncthreads();
+    // the base lies in this tile: box-local base = g0 - o (no wrap)
+    const int b1 = g1 - o1, b2 = g2 - o2, b3 = g3 - o3;
+    R gx = R(0), gy = R(0), gz = R(0);
+    if (lane < P) {
+      R w1[P], d1[P];
+#pragma unroll
+      for (int a = 0; a < P; ++a) {
+        w1[a] = my[a];
+        d1[a] = my[P + a];
+      }
+      const R* plane = box + (b3 + lane) * E1 * E2 + b2 * E1 + b1;
+      R sxz = R(0), syz = R(0), s0z = R(0);
+#pragma unroll
+      for (int b = 0; b < P; ++b) {
+        const R* row = plane + b * E1;
+        R sx = R(0), s0 = R(0);
+#pragma unroll
+        for (int a = 0; a < P; ++a) {
+          const R v = row[a];
+          sx += v * d1[a];
+          s0 += v * w1[a];
+        }
+        const R w2 = my[2 * P + b], d2 = my[3 * P + b];
+        sxz += sx * w2;
+        s0z += s0 * w2;
+        syz += s0 * d2;
+      }
+      gx = sxz * my[4 * P + lane];
+      gy = syz * my[4 * P + lane];
+      gz = s0z * my[5 * P + lane];
+    }
+#pragma unroll
+    for (int off = L / 2; off > 0; off >>= 1) {
+      gx += __shfl_xor(gx, off, 64);
+      gy += __shfl_xor(gy, off, 64);
+      gz += __shfl_xor(gz, off, 64);
+    }
+    if (lane == 0 && valid) {
+      const R qk = rec.q * d.coulomb_k;
+      const int64_t j = d.perm[i];
+      f[3 * j + 0] = qk * (d.G[0] * gx + d.G[1] * gy + d.G[2] * gz);
+      f[3 * j + 1] = qk * (d.G[3] * gx + d.G[4] * gy + d.G[5] * gz);
+      f[3 * j + 2] = qk * (d.G[6] * gx + d.G[7] * gy + d.G[8] * gz);
+    }
+  }
+}
+
 // ---------------------------------------------------------------- launchers
 template <typename R, int P, int NW>
 static hipError_t spread_nw(const DevPlan<R>& d, hipStream_t s) {
@@ -254,6 +362,15 @@ static size_t gather_lds() {
 
 template <typename R, int P, int NW>
 static hipError_t gather_nw(const DevPlan<R>& d, R* f, double* out7, hipStream_t s) {
+  if (d.gather_tiled) {
+    const size_t lds = gather_lds<R, P, NW>() + lds_gather_box(d);
+    if (lds > 65536)
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather_tile<R, P, NW, false>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    hipLaunchKernelGGL((k_gather_tile<R, P, NW, false>), dim3(d.ntiles), dim3(256), lds, s, KArg<R, false>{d},
+                       f, out7);
+    return hipGetLastError();
+  }
   constexpr int G = 256 / GatherLanes<P>::L;
   const int nb = static_cast<int>((d.n + G - 1) / G);
   hipLaunchKernelGGL((k_gather<R, P, NW, false>), dim3(nb), dim3(256), (gather_lds<R, P, NW>()), s,

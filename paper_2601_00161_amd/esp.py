@@ -47,7 +47,8 @@ class Params(ctypes.Structure):
                 ("kernel_degree", ctypes.c_int), ("lambda0_split", ctypes.c_double),
                 ("C0_split", ctypes.c_double), ("psi0_split", ctypes.c_double),
                 ("volume", ctypes.c_double), ("params_source", ctypes.c_int),
-                ("predicted_log10_err", ctypes.c_double * 4), ("predicted_cost", ctypes.c_double)]
+                ("predicted_log10_err", ctypes.c_double * 4), ("predicted_cost", ctypes.c_double),
+                ("gather_tiled", ctypes.c_int), ("counter_copies", ctypes.c_int)]
 
     def as_dict(self):
         out = {}

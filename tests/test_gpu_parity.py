@@ -48,7 +48,22 @@ def systems():
     out.append(("ionic_triclinic_P4", h, r, q, dict(paper_params(h, 1e-3), P=4)))
     h, r, q = synth.water(200, np.diag([2.5, 3.0, 2.0]), config=1, seed=13)
     out.append(("orthorhombic_oddgrid_P7", h, r, q, dict(paper_params(h, 1e-6), M=(27, 30, 25))))
+    # dense tiles (coarse grid, many particles per tile): the tile-staged gather
+    # and the binning with tile-counter copies
+    h, r, q = synth.water(7200, synth.cubic(6.0), config=1, seed=14)
+    out.append(("water_dense_tiles_tol1e-3", h, r, q, paper_params(h, 1e-3)))
     return out
+
+
+def test_paths_are_covered(dev):
+    """The systems above exercise both gather variants and both binning modes."""
+    modes = set()
+    for name, h, r, q, prm in SYSTEMS:
+        plan = make_plan(h, len(q), prm, "fp32")
+        modes.add(("tiled", plan.params["gather_tiled"]))
+        modes.add(("copies", plan.params["counter_copies"] > 1))
+        plan.close()
+    assert {("tiled", 0), ("tiled", 1), ("copies", False), ("copies", True)} <= modes, modes
 
 
 SYSTEMS = systems()
