@@ -86,8 +86,69 @@ struct Dft<R, 5> {
   }
 };
 
+// Radix 6 = 2 x 3: X[k] = E[k mod 3] + w^k O[k mod 3], w = exp(sgn 2 pi i / 6),
+// with E, O the 3-point transforms of the even and odd samples.
+template <typename R>
+struct Dft<R, 6> {
+  __device__ static void run(Cplx<R>* v, R sgn) {
+    const R s60 = R(0.86602540378443864676);
+    Cplx<R> e[3] = {v[0], v[2], v[4]}, o[3] = {v[1], v[3], v[5]};
+    Dft<R, 3>::run(e, sgn);
+    Dft<R, 3>::run(o, sgn);
+    const Cplx<R> w1 = {R(0.5), sgn * s60}, w2 = {R(-0.5), sgn * s60};
+    const Cplx<R> o1 = cmul(o[1], w1), o2 = cmul(o[2], w2);
+    v[0] = cadd(e[0], o[0]);
+    v[3] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);
+    v[4] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);
+    v[5] = csub(e[2], o2);
+  }
+};
+
+// Radix 8 = 2 x 4, w = exp(sgn 2 pi i / 8).
+template <typename R>
+struct Dft<R, 8> {
+  __device__ static void run(Cplx<R>* v, R sgn) {
+    const R h = R(0.70710678118654752440);
+    Cplx<R> e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+    Dft<R, 4>::run(e, sgn);
+    Dft<R, 4>::run(o, sgn);
+    const Cplx<R> o1 = cmul(o[1], Cplx<R>{h, sgn * h});
+    const Cplx<R> o2 = cadd_i(Cplx<R>{R(0), R(0)}, o[2], sgn);      // i sgn o2
+    const Cplx<R> o3 = cmul(o[3], Cplx<R>{-h, sgn * h});
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);
+    v[5] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);
+    v[6] = csub(e[2], o2);
+    v[3] = cadd(e[3], o3);
+    v[7] = csub(e[3], o3);
+  }
+};
+
+// floor(a / b) and a mod b for 0 <= a < 2^24, 1 <= b, with rb = 1 / b
+// (a float product plus one integer correction instead of a division).
+__device__ __forceinline__ int fast_div(int a, int b, float rb, int& rem) {
+  int q = static_cast<int>(static_cast<float>(a) * rb);
+  int r = a - q * b;
+  if (r >= b) {
+    ++q;
+    r -= b;
+  } else if (r < 0) {
+    --q;
+    r += b;
+  }
+  rem = r;
+  return q;
+}
+
 // One Stockham stage of nlines independent length-n transforms held in LDS:
-// element e of line l lives at base[l * lstride + e * estride].
+// element e of line l lives at base[l * lstride + e * estride].  Adjacent
+// threads take adjacent elements of a line when elements are contiguous
+// (estride 1), else adjacent lines (lstride 1), so LDS accesses stay
+// unit-stride and free of bank conflicts either way.
 template <typename R, int RAD>
 __device__ void fft_stage(const Cplx<R>* __restrict__ in, Cplx<R>* __restrict__ out, int n, int Ns,
                           int nlines, int lstride, int estride, const Cplx<R>* __restrict__ tw,
@@ -95,10 +156,15 @@ __device__ void fft_stage(const Cplx<R>* __restrict__ in, Cplx<R>* __restrict__ 
   const int nb = n / RAD;
   const int total = nlines * nb;
   const int tunit = n / (Ns * RAD);
+  const bool by_line = estride != 1;
+  const int inner = by_line ? nlines : nb;
+  const float rin = 1.0f / static_cast<float>(inner), rns = 1.0f / static_cast<float>(Ns);
   for (int id = threadIdx.x; id < total; id += blockDim.x) {
-    const int line = id / nb;
-    const int i = id - line * nb;
-    const int j = i % Ns;
+    int rem, j;
+    const int q = fast_div(id, inner, rin, rem);
+    const int line = by_line ? rem : q;
+    const int i = by_line ? q : rem;
+    const int blk = fast_div(i, Ns, rns, j);
     const Cplx<R>* src = in + line * lstride;
     Cplx<R>* dst = out + line * lstride;
     Cplx<R> v[RAD];
@@ -113,7 +179,7 @@ __device__ void fft_stage(const Cplx<R>* __restrict__ in, Cplx<R>* __restrict__ 
       }
     }
     Dft<R, RAD>::run(v, sgn);
-    const int ob = (i / Ns) * Ns * RAD + j;
+    const int ob = blk * Ns * RAD + j;
 #pragma unroll
     for (int r = 0; r < RAD; ++r) dst[(ob + r * Ns) * estride] = v[r];
   }
@@ -133,7 +199,9 @@ __device__ Cplx<R>* fft_lines(Cplx<R>* a, Cplx<R>* b, const FftLen& f, int nline
       case 2: fft_stage<R, 2>(in, out, f.n, Ns, nlines, lstride, estride, tw, sgn); break;
       case 3: fft_stage<R, 3>(in, out, f.n, Ns, nlines, lstride, estride, tw, sgn); break;
       case 4: fft_stage<R, 4>(in, out, f.n, Ns, nlines, lstride, estride, tw, sgn); break;
-      default: fft_stage<R, 5>(in, out, f.n, Ns, nlines, lstride, estride, tw, sgn); break;
+      case 5: fft_stage<R, 5>(in, out, f.n, Ns, nlines, lstride, estride, tw, sgn); break;
+      case 6: fft_stage<R, 6>(in, out, f.n, Ns, nlines, lstride, estride, tw, sgn); break;
+      default: fft_stage<R, 8>(in, out, f.n, Ns, nlines, lstride, estride, tw, sgn); break;
     }
     Ns *= f.rad[s];
     Cplx<R>* t = in;

@@ -15,7 +15,7 @@ namespace espx {
 constexpr int kMaxP = 12;          // largest window support per dimension
 constexpr int kMaxWinDeg = 16;     // largest degree of the window polynomials (classes 8, 12, 16)
 constexpr int kMaxKerDeg = 48;     // largest Chebyshev degree of the kernel fits
-constexpr int kMaxRadix = 5;
+constexpr int kMaxRadix = 8;
 constexpr int kMaxStages = 16;
 constexpr int kNumSums = 7;        // energy + 6 virial components
 constexpr int kSpreadChunk = 64;   // particles staged per spreading round

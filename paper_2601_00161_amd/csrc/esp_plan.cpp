@@ -338,11 +338,13 @@ esp_status resolve(const double* h, int64_t n, double tol, const esp_opts* o, Re
   return warn;
 }
 
-// radices for a 2,3,5-smooth length: 4s first, then a 2, then 3s and 5s
+// radices for a 2,3,5-smooth length: 8s, 6s, 4s, then a 2, then 3s and 5s
 void factor(int n, FftLen& f) {
   f.n = n;
   f.nstage = 0;
   int m = n;
+  while (m % 8 == 0) { f.rad[f.nstage++] = 8; m /= 8; }
+  while (m % 6 == 0) { f.rad[f.nstage++] = 6; m /= 6; }
   while (m % 4 == 0) { f.rad[f.nstage++] = 4; m /= 4; }
   while (m % 2 == 0) { f.rad[f.nstage++] = 2; m /= 2; }
   while (m % 3 == 0) { f.rad[f.nstage++] = 3; m /= 3; }
@@ -528,7 +530,12 @@ esp_status build_device(esp_plan_t* p) {
   d.T1 = r.T[0]; d.T2 = r.T[1]; d.T3 = r.T[2];
   d.nt1 = r.nt[0]; d.nt2 = r.nt[1]; d.nt3 = r.nt[2];
   d.ntiles = r.ntiles;
-  d.cz = std::max(1, std::min(d.H, 256 / std::max(1, d.M3)));
+  // columns per z-pass workgroup: ~256 elements, at least 8 columns (64-byte
+  // rows of the spectrum) for long columns
+  {
+    const int per = 256 / std::max(1, d.M3);
+    d.cz = std::max(1, std::min(d.H, per >= 6 ? per : 8));
+  }
   d.nzblk = ((d.H + d.cz - 1) / d.cz) * d.M2;
   d.nbin = static_cast<int>((r.n + 255) / 256);
   d.kcut2 = static_cast<R>((r.c_split / r.rc) * (r.c_split / r.rc));
