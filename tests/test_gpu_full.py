@@ -1,0 +1,120 @@
+"""Parity at the full sizes of the benchmark workloads, in the launch
+configuration the benchmark uses (plans made the same way), against the
+oracle's gridded ESP at the plan's own parameters."""
+import numpy as np
+import pytest
+
+from gpu_util import TOL, as_inputs, oracle, rel_rms, tensor_rel
+from paper_2601_00161_amd import esp, synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+
+
+def gpu(plan, r_, q_, energy_only=False):
+    xyz, qq = torch.from_numpy(r_).to(DEV), torch.from_numpy(q_).to(DEV)
+    if energy_only:
+        out = plan.energy_virial(xyz, qq)
+        f = None
+    else:
+        f, out = plan.forces(xyz, qq)
+    assert plan.check() == esp.ESP_OK
+    return (None if f is None else f.double().cpu().numpy()), out.cpu().numpy()
+
+
+def compare(h, r64, q64, plan, f, out, precision, forces=True):
+    prm = plan.params
+    print(f"P={prm['P']} M={prm['M']} tile={prm['tile']} gather_tiled={prm['gather_tiled']} "
+          f"copies={prm['counter_copies']}", flush=True)
+    ref = oracle(h, r64, q64, prm, forces=forces)
+    e_E = abs(out[0] - ref.energy) / abs(ref.energy)
+    e_W = tensor_rel(out, ref.virial)
+    e_F = rel_rms(f, ref.forces) if forces else 0.0
+    print(f"energy {e_E:.2e} virial {e_W:.2e} forces {e_F:.2e}", flush=True)
+    assert e_E < TOL[precision] and e_W < TOL[precision] and e_F < TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_water_3k_tol1e4(precision):
+    h, r, q = synth.config1()
+    r_, q_, r64, q64 = as_inputs(r, q, precision)
+    kw = {"window_tol": 1e-13} if precision == "fp64" else {}
+    plan = esp.Plan(h, len(q), 1e-4, precision=precision, **kw)
+    f, out = gpu(plan, r_, q_)
+    compare(h, r64, q64, plan, f, out, precision)
+    plan.close()
+
+
+@pytest.mark.parametrize("tol", [1e-5, 1e-7])
+@pytest.mark.parametrize("precision,params", [("fp32", "learned"), ("fp32", "analytic"), ("fp64", "analytic")])
+def test_water_30k_bench_plans(precision, params, tol):
+    """The benchmark's three plans (same constructor arguments) at both tolerances."""
+    h, r, q = synth.config2()
+    r_, q_, r64, q64 = as_inputs(r, q, precision)
+    plan = esp.Plan(h, len(q), tol, precision=precision, params=params, tile=0)
+    f, out = gpu(plan, r_, q_)
+    bar = TOL[precision] if precision == "fp32" else 1e-3 * tol + TOL["fp64"]
+    prm = plan.params
+    ref = oracle(h, r64, q64, prm)
+    e = (abs(out[0] - ref.energy) / abs(ref.energy), tensor_rel(out, ref.virial), rel_rms(f, ref.forces))
+    print(f"{precision} {params} tol={tol:g}: P={prm['P']} M={prm['M']} errors {e}", flush=True)
+    assert max(e) < bar
+    plan.close()
+
+
+def test_ionic_19k_flexible_fp32():
+    """Fully flexible cell: both the pressure-only path (one FFT) and the force path."""
+    h, r, q = synth.config3()
+    r_, q_, r64, q64 = as_inputs(r, q, "fp32")
+    plan = esp.Plan(h, len(q), 1e-5, coupling="flex")
+    _, out_ev = gpu(plan, r_, q_, energy_only=True)
+    f, out = gpu(plan, r_, q_)
+    compare(h, r64, q64, plan, f, out, "fp32")
+    assert np.max(np.abs(out - out_ev)) <= 1e-6 * np.max(np.abs(out_ev))
+    plan.close()
+
+
+def test_membrane_1m_semi_fp32():
+    """N = 10^6 membrane-shaped slab (the FP64 plan does not fit its plane in LDS)."""
+    h, r, q = synth.config4()
+    r_, q_, r64, q64 = as_inputs(r, q, "fp32")
+    plan = esp.Plan(h, len(q), 1e-5, coupling="semi")
+    f, out = gpu(plan, r_, q_)
+    compare(h, r64, q64, plan, f, out, "fp32")
+    plan.close()
+
+
+def test_batch_64_replicas():
+    """The 64-replica batch (N in [2,000, 60,000], tol in {1e-3 ... 1e-6}) in one
+    graph-replayed call per step: replicas against their own single plans, and
+    three of them against the oracle."""
+    reps = synth.replicas()
+    cells = [x[0] for x in reps]
+    ns = [len(x[2]) for x in reps]
+    tols = [x[3] for x in reps]
+    b = esp.Batch(cells, ns, tols, graph=True)
+    xyz = torch.tensor(np.concatenate([x[1] for x in reps]), dtype=torch.float32, device=DEV)
+    qq = torch.tensor(np.concatenate([x[2] for x in reps]), dtype=torch.float32, device=DEV)
+    f, out = b.forces(xyz, qq)
+    b.forces(xyz, qq, f=f, out7=out)                  # graph replay
+    assert b.check() == esp.ESP_OK
+    f = f.double().cpu().numpy()
+    out = out.cpu().numpy()
+    for k in range(0, 64, 8):
+        h, r, q, tol = reps[k]
+        plan = esp.Plan(h, len(q), tol)
+        fs, os_ = gpu(plan, r.astype(np.float32), q.astype(np.float32))
+        sl = slice(b.offsets[k], b.offsets[k + 1])
+        assert rel_rms(f[sl], fs) < 2e-6
+        assert np.max(np.abs(out[k] - os_)) <= 2e-6 * np.max(np.abs(os_))
+        plan.close()
+    for k in (0, 21, 42):
+        h, r, q, tol = reps[k]
+        _, _, r64, q64 = as_inputs(r, q, "fp32")
+        ref = oracle(h, r64, q64, b.params[k])
+        sl = slice(b.offsets[k], b.offsets[k + 1])
+        assert abs(out[k, 0] - ref.energy) / abs(ref.energy) < TOL["fp32"]
+        assert tensor_rel(out[k], ref.virial) < TOL["fp32"]
+        assert rel_rms(f[sl], ref.forces) < TOL["fp32"]
+    b.close()
