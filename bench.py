@@ -167,6 +167,52 @@ def oracle_leg(h, r32, q32, plans, headline):
     return out
 
 
+def batch_throughput(torch, dev, steps=20):
+    """The 64-replica batch (N in [2,000, 60,000], per-replica tol in
+    {1e-3 ... 1e-6}, FP32, learned parameters): particle-steps per second of
+    one graph-replayed call per step, next to the same replicas run as 64
+    single-plan calls."""
+    from paper_2601_00161_amd import synth
+    from paper_2601_00161_amd.esp import Batch, Plan
+    reps = synth.replicas()
+    cells = [x[0] for x in reps]
+    ns = [len(x[2]) for x in reps]
+    tols = [x[3] for x in reps]
+    xyz = torch.tensor(np.concatenate([x[1] for x in reps]), dtype=torch.float32, device=dev)
+    q = torch.tensor(np.concatenate([x[2] for x in reps]), dtype=torch.float32, device=dev)
+    b = Batch(cells, ns, tols, graph=True, params="learned")
+    f, out = b.forces(xyz, q)
+    for _ in range(3):
+        b.forces(xyz, q, f=f, out7=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.forces(xyz, q, f=f, out7=out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    b.check()
+    launches = b.num_launches(True)
+    b.close()
+    # the same replicas as single plans, one after the other
+    plans = [Plan(c, n, t, params="learned") for c, n, t in zip(cells, ns, tols)]
+    offs = np.concatenate([[0], np.cumsum(ns)])
+    views = [(xyz[offs[k]:offs[k + 1]], q[offs[k]:offs[k + 1]]) for k in range(len(ns))]
+    outs = [p.forces(*v) for p, v in zip(plans, views)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for p, v, (fo, oo) in zip(plans, views, outs):
+            p.forces(*v, f=fo, out7=oo)
+    torch.cuda.synchronize()
+    ds = (time.perf_counter() - t0) / steps
+    for p in plans:
+        p.close()
+    total = int(sum(ns))
+    return {"replicas": len(ns), "particles": total, "launches_per_step": launches,
+            "ms_per_step": dt * 1e3, "value": total / dt / 1e6, "unit": "M particle-steps/s",
+            "single_plans_ms_per_step": ds * 1e3, "speedup_vs_single_plans": ds / dt}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,6 +224,8 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="spreading tile edge (0 = plan default)")
     ap.add_argument("--params", default="learned", choices=["learned", "analytic"],
                     help="parameter source of the FP32 headline plan")
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner (plan defaults)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-replica batch measurement")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="first run 5 plain device copies of MIB MiB (float32), the known-size "
                          "kernel that calibrates the FETCH_SIZE / WRITE_SIZE counters")
@@ -208,8 +256,19 @@ def main():
     x32, c32 = torch.from_numpy(r32).to(dev), torch.from_numpy(q32).to(dev)
     x64, c64 = torch.from_numpy(r32.astype(np.float64)).to(dev), torch.from_numpy(q32.astype(np.float64)).to(dev)
 
-    # ---- FP32 headline path (learned parameters) --------------------------------
-    p32 = Plan(h, N, args.tol, precision="fp32", params=args.params, tile=args.tile)
+    import tempfile
+    from paper_2601_00161_amd import autotune
+    tune_dir = tempfile.TemporaryDirectory()
+
+    def make_plan(precision, params, xyz, q):
+        """A plan with the autotuned launch shape (tile edge, gather variant)."""
+        if args.no_tune or args.tile:
+            return Plan(h, N, args.tol, precision=precision, params=params, tile=args.tile), None
+        return autotune.tuned_plan(h, N, args.tol, xyz, q, cache=os.path.join(tune_dir.name, "tune.json"),
+                                   precision=precision, params=params)
+
+    # ---- FP32 headline path (learned parameters, autotuned launch shape) ------------
+    p32, tuned = make_plan("fp32", args.params, x32, c32)
     for _ in range(10):                      # first launches load code objects
         p32.forces(x32, c32)
     torch.cuda.synchronize()
@@ -226,12 +285,14 @@ def main():
     p32.profile([], 0)
 
     # ---- FP32 with the analytic rule (the proposer's gain) ---------------------
-    pa = Plan(h, N, args.tol, precision="fp32", tile=args.tile)
+    pa, tuned_a = make_plan("fp32", "analytic", x32, c32)
     dta, fa, oa = run_plan(pa, x32, c32, args.steps, args.warmup, torch)
 
     # ---- plain FP64 path, analytic parameters -------------------------------------
-    p64 = Plan(h, N, args.tol, precision="fp64", tile=args.tile)
+    p64, tuned_64 = make_plan("fp64", "analytic", x64, c64)
     dt64, f64, o64 = run_plan(p64, x64, c64, args.steps, args.warmup, torch)
+
+    batch = None if args.no_batch else batch_throughput(torch, dev)
 
     cpu = None
     extra = {}
@@ -255,7 +316,8 @@ def main():
 
     def brief(p):
         return {"source": {v: k for k, v in PARAMS.items()}[p.params["params_source"]],
-                "delta": p.params["delta"], "c": p.params["c_split"], "P": p.params["P"], "M": p.params["M"]}
+                "delta": p.params["delta"], "c": p.params["c_split"], "P": p.params["P"], "M": p.params["M"],
+                "tile": p.params["tile"], "gather_tiled": p.params["gather_tiled"]}
 
     line = {
         "metric": "M particle-steps/s (E+F+virial) at 1e-5 rel err: FP32+learned vs plain FP64",
@@ -272,12 +334,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": "bulk-water-shaped, 10,000 rigid 3-site triplets, cubic 6.7 nm, N=30000, tol 1e-5",
                    "seed": args.seed, "params": src, "delta": prm["delta"], "c": prm["c_split"], "P": prm["P"],
-                   "M": prm["M"], "rc": prm["rc"], "tile": prm["tile"],
+                   "M": prm["M"], "rc": prm["rc"], "tile": prm["tile"], "gather_tiled": prm["gather_tiled"],
+                   "autotune": tuned,
                    "predicted_log10_err": prm["predicted_log10_err"] if src == "learned" else None},
         "fp64_baseline": {"value": round(v64, 3), "ms_per_step": dt64 / args.steps * 1e3, **brief(p64)},
         "speedup_vs_fp64": value / v64,
         "fp32_analytic": {"value": round(va, 3), "ms_per_step": dta / args.steps * 1e3, **brief(pa)},
         "learned_gain_vs_analytic": value / va,
+        "batch_64_replicas": batch,
         **extra,
         "stage_ms_fp32": {k: v[0] / v[1] for k, v in stages.items()},
         "roofline": {"kernel": dominant, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,

@@ -101,7 +101,13 @@ typedef struct {
   double window_tol;   /* max error of the window polynomials relative to psi(0);
                           0 = automatic: max(Delta/100, 2e-8) for FP32, Delta/1000
                           for FP64 */
+  int gather;          /* ESP_GATHER_AUTO (0): tile-staged gather when tiles hold
+                          96+ particles on average; ESP_GATHER_PARTICLE (1) or
+                          ESP_GATHER_TILE (2) force one variant (the tile variant
+                          is refused if its potential box does not fit in LDS) */
 } esp_opts;
+
+enum { ESP_GATHER_AUTO = 0, ESP_GATHER_PARTICLE = 1, ESP_GATHER_TILE = 2 };
 
 /* Parameters a plan resolved to (returned by esp_get_params). */
 typedef struct {

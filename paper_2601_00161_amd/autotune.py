@@ -1,0 +1,121 @@
+"""Autotuner for the launch shape of a plan: the spreading tile edge and the
+gather variant (per particle, or tile-staged potential in LDS).
+
+Each admissible candidate is timed on the GPU with the caller's own
+particles (one esp_forces call = one step, HIP events over repeated calls)
+and the fastest is kept.  Results are cached in a JSON file keyed by what
+the choice depends on: precision, grid, window support, window degree class
+and particle count (two significant digits).  Tuning never changes results
+beyond FP32 reassociation: every candidate computes the same sums.
+
+    plan, info = autotune.tuned_plan(h, n, tol, xyz, q, cache="tune.json", precision="fp32")
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+from . import esp
+
+TILES = (4, 5, 6, 8, 10, 12)
+GATHERS = ("particle", "tile")
+DEFAULT_CACHE = os.environ.get("ESP_AUTOTUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache",
+                                                                  "esp_mi355x_autotune.json"))
+
+
+def _key(params):
+    n = params["n"]
+    n2 = int(round(n, -max(0, int(math.floor(math.log10(n))) - 1)))
+    cls = 8 if params["window_degree"] <= 8 else (12 if params["window_degree"] <= 12 else 16)
+    return (f"{'fp32' if params['precision'] == 0 else 'fp64'}:M{params['M'][0]}x{params['M'][1]}x{params['M'][2]}"
+            f":P{params['P']}:W{cls}:N{n2}")
+
+
+def _load(path):
+    if path and os.path.exists(path):
+        with open(path) as f:
+            return json.load(f)
+    return {}
+
+
+def _save(path, data):
+    if not path:
+        return
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def time_step(plan, xyz, q, reps=20, warmup=3):
+    """Microseconds per esp_forces call (HIP events around `reps` calls)."""
+    import torch
+    f, out = plan.forces(xyz, q)
+    for _ in range(warmup):
+        plan.forces(xyz, q, f=f, out7=out)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        plan.forces(xyz, q, f=f, out7=out)
+    b.record()
+    b.synchronize()
+    return a.elapsed_time(b) * 1e3 / reps
+
+
+def tune(h, n, tol, xyz, q, reps=20, tiles=TILES, gathers=GATHERS, **opts):
+    """Time every admissible (tile, gather) pair; returns {"tile", "gather", "us", "table"}."""
+    table = {}
+    best = None
+    for t in tiles:
+        for g in gathers:
+            try:
+                plan = esp.Plan(h, n, tol, tile=t, gather=g, **opts)
+            except esp.EspError:
+                continue                      # not admissible for this grid (LDS, tile count)
+            us = time_step(plan, xyz, q, reps=reps)
+            plan.close()
+            table[f"{t}:{g}"] = round(us, 2)
+            if best is None or us < best[2]:
+                best = (t, g, us)
+    if best is None:
+        raise RuntimeError("no admissible launch shape")
+    return {"tile": best[0], "gather": best[1], "us": round(best[2], 2), "table": table}
+
+
+def tuned_plan(h, n, tol, xyz, q, cache=DEFAULT_CACHE, retune=False, **opts):
+    """A plan with the cached (or freshly tuned) launch shape for this problem."""
+    probe = esp.Plan(h, n, tol, **opts)
+    key = _key(probe.params)
+    probe.close()
+    data = _load(cache)
+    if retune or key not in data:
+        data[key] = tune(h, n, tol, xyz, q, **opts)
+        _save(cache, data)
+    rec = data[key]
+    plan = esp.Plan(h, n, tol, tile=rec["tile"], gather=rec["gather"], **opts)
+    return plan, dict(rec, key=key)
+
+
+def tuned_tiles(cells, ns, tols, positions, charges, cache=DEFAULT_CACHE, **opts):
+    """Per-replica tile edges for esp.Batch, tuning each distinct problem key once
+    on that replica's own particles."""
+    import torch
+    data = _load(cache)
+    tiles = []
+    changed = False
+    for h, n, tol, r, qq in zip(cells, ns, tols, positions, charges):
+        probe = esp.Plan(h, n, tol, **opts)
+        key = _key(probe.params)
+        dt = probe.dtype
+        probe.close()
+        if key not in data:
+            xyz = torch.as_tensor(r, dtype=dt, device="cuda").contiguous()
+            qt = torch.as_tensor(qq, dtype=dt, device="cuda").contiguous()
+            data[key] = tune(h, n, tol, xyz, qt, gathers=("particle",), **opts)
+            changed = True
+        tiles.append(data[key]["tile"])
+    if changed:
+        _save(cache, data)
+    return tiles

@@ -37,6 +37,7 @@ struct Resolved {
   int params_source = ESP_ANALYTIC;
   int coupling = ESP_ISO;
   double window_tol = 0;
+  int gather = ESP_GATHER_AUTO;
   double pred[4] = {0, 0, 0, 0};
   double pred_cost = 0;
 };
@@ -273,6 +274,11 @@ esp_status resolve(const double* h, int64_t n, double tol, const esp_opts* o, Re
     return ESP_EINVAL;
   }
   r.window_tol = o->window_tol;
+  if (o->gather < ESP_GATHER_AUTO || o->gather > ESP_GATHER_TILE) {
+    err = "gather must be ESP_GATHER_AUTO, ESP_GATHER_PARTICLE or ESP_GATHER_TILE";
+    return ESP_EINVAL;
+  }
+  r.gather = o->gather;
   std::memcpy(r.h, h, 9 * sizeof(double));
   esp_status st = check_box(h, r.rc, r.hinv, &r.V, err);
   if (st != ESP_OK) return st;
@@ -640,8 +646,14 @@ esp_status build_device(esp_plan_t* p) {
   d.bin_lds = r.ntiles <= 8192 ? 1 : 0;
   // dense tiles: stage each tile's potential box in LDS for the gather
   const size_t gather_base = ((p->nw + 1) * r.P + (256 / gather_lanes(r.P)) * 6 * r.P) * sizeof(R);
-  d.gather_tiled = r.n >= static_cast<int64_t>(kTiledGatherMin) * r.ntiles &&
-                   gather_base + lds_gather_box(d) <= static_cast<size_t>(maxlds);
+  const bool box_fits = gather_base + lds_gather_box(d) <= static_cast<size_t>(maxlds);
+  if (r.gather == ESP_GATHER_TILE && !box_fits) {
+    p->err = "the tile-staged gather's potential box does not fit in LDS for this tile";
+    return ESP_EINVAL;
+  }
+  d.gather_tiled = r.gather == ESP_GATHER_TILE ||
+                   (r.gather == ESP_GATHER_AUTO && box_fits &&
+                    r.n >= static_cast<int64_t>(kTiledGatherMin) * r.ntiles);
   e = hipMemset(d.counts, 0, ncount * sizeof(int));
   if (e == hipSuccess) e = hipMemset(d.rho, 0, G * sizeof(R));
   if (e == hipSuccess) e = hipMemset(d.flags, 0, 4 * sizeof(int));

@@ -23,6 +23,7 @@ STATUS_NAMES = {0: "ESP_OK", 1: "ESP_WARN_REPLAN", 2: "ESP_WARN_FALLBACK", -1: "
 PRECISION = {"fp32": 0, "fp64": 1}
 PARAMS = {"analytic": 0, "explicit": 1, "learned": 2}
 COUPLING = {"iso": 0, "semi": 1, "aniso": 2, "flex": 3}
+GATHER = {"auto": 0, "particle": 1, "tile": 2}
 
 
 class EspError(RuntimeError):
@@ -36,7 +37,7 @@ class Opts(ctypes.Structure):
                 ("rc", ctypes.c_double), ("c_split", ctypes.c_double), ("c_spread", ctypes.c_double),
                 ("P", ctypes.c_int), ("M", ctypes.c_int * 3), ("grid_sigma", ctypes.c_double),
                 ("coulomb_k", ctypes.c_double), ("tile", ctypes.c_int), ("stream", ctypes.c_void_p),
-                ("window_tol", ctypes.c_double)]
+                ("window_tol", ctypes.c_double), ("gather", ctypes.c_int)]
 
 
 class Params(ctypes.Structure):
@@ -149,7 +150,7 @@ def _cell(h):
 
 def make_opts(precision="fp32", params="analytic", coupling="iso", rc=0.9, c_split=None,
               c_spread=None, P=None, M=None, grid_sigma=1.07, coulomb_k=1.0, tile=0, stream=None,
-              window_tol=0.0):
+              window_tol=0.0, gather="auto"):
     o = Opts()
     lib().esp_opts_default(ctypes.byref(o))
     o.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
@@ -175,6 +176,7 @@ def make_opts(precision="fp32", params="analytic", coupling="iso", rc=0.9, c_spl
     o.tile = int(tile)
     o.stream = stream
     o.window_tol = float(window_tol)
+    o.gather = GATHER[gather] if isinstance(gather, str) else int(gather)
     return o
 
 

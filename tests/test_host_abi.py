@@ -144,3 +144,16 @@ def test_proposer_registration_rejects_missing_network():
     for i in range(4):
         p.out_std[i] = 1.0
     assert esp.lib().esp_proposer_set(p) == esp.ESP_EINVAL
+
+
+def test_autotune_cache_key():
+    from paper_2601_00161_amd import autotune
+    k = autotune._key({"n": 31234, "precision": 0, "M": [36, 36, 40], "P": 6, "window_degree": 9})
+    assert k == "fp32:M36x36x40:P6:W12:N31000"
+    assert autotune._key({"n": 987, "precision": 1, "M": [15, 15, 15], "P": 5, "window_degree": 14}) == \
+        "fp64:M15x15x15:P5:W16:N990"
+
+
+def test_gather_option_is_validated():
+    with pytest.raises(esp.EspError):
+        esp.resolve_params(np.diag([3.0, 3.0, 3.0]), 100, 1e-4, gather=7)
