@@ -29,6 +29,14 @@ Readings taken where the paper is silent or inconsistent:
 
 The FFT is numpy's full complex transform (sign exp(-2 pi i m.g/M)); no
 half-spectrum symmetry is used.
+
+`esp_grid_ik` is the other force option of App. C, ik-differentiation
+(eq. rhodiagforce): the field i k F_hat rho_hat / (V W_hat^2) is brought back
+by three inverse FFTs and gathered with the plain window.  Reading: a mode
+whose index is the Nyquist index M_d/2 of an even M_d has no partner -m_d,
+so its i k_d term is not the transform of a real field; such modes are
+dropped from the field (with the grid rule they lie outside the cutoff
+sphere anyway), which keeps the net force exactly zero.
 """
 from __future__ import annotations
 
@@ -167,3 +175,45 @@ def esp_grid(h, r, q, prm: GridParams, forces=True):
         hinvT = np.linalg.inv(h).T
         F = -q[:, None] * ((grad * M[None, :].astype(np.float64)) @ hinvT.T)
     return GridResult(U_F + U_self + U_corr, W_F + W_corr, F, U_F, U_self, U_corr, rho, phi)
+
+
+def nyquist_mask(M):
+    """False on modes with m_d = -M_d/2 for an even M_d (full DFT grid)."""
+    keep = np.ones(tuple(int(m) for m in M), dtype=bool)
+    for d, Md in enumerate(M):
+        if Md % 2 == 0:
+            sl = [slice(None)] * 3
+            sl[d] = Md // 2
+            keep[tuple(sl)] = False
+    return keep
+
+
+def esp_grid_ik(h, r, q, prm: GridParams):
+    """Energy, virial and ik-differentiated forces (App. C, eq. rhodiagforce):
+    F_i = -q_i sum_g W(u_i - g) E(g), E = unnormalised inverse FFT of
+    i k F_hat rho_hat / (V W_hat^2)."""
+    h = np.asarray(h, np.float64)
+    r = np.asarray(r, np.float64)
+    q = np.asarray(q, np.float64)
+    V = lattice.volume(h)
+    M = np.asarray(prm.M, dtype=np.int64)
+    base = esp_grid(h, r, q, prm, forces=False)
+    rho_hat = np.fft.fftn(base.rho_grid)
+    k, What, Fhat, _ = mode_weights(h, prm)
+    G = Fhat / (V * What ** 2) * nyquist_mask(M)
+    u = grid_coordinates(h, r, M)
+    g0, w, _ = stencil(u, prm.P, prm.c_spread)
+    F = np.zeros((r.shape[0], 3))
+    P = prm.P
+    for a in range(3):
+        E = np.real(np.fft.ifftn(1j * k[..., a] * G * rho_hat)) * float(np.prod(M))
+        acc = np.zeros(r.shape[0])
+        for i1 in range(P):
+            ia = (g0[:, 0] + i1) % M[0]
+            for i2 in range(P):
+                ib = (g0[:, 1] + i2) % M[1]
+                for i3 in range(P):
+                    ic = (g0[:, 2] + i3) % M[2]
+                    acc += E[ia, ib, ic] * w[:, 0, i1] * w[:, 1, i2] * w[:, 2, i3]
+        F[:, a] = -q * acc
+    return GridResult(base.energy, base.virial, F, base.U_F, base.U_self, base.U_corr, base.rho_grid, None)
