@@ -118,9 +118,9 @@ def oracle_leg(h, r32, q32, plans, headline):
     refs = {}
     for name, (plan, f, o) in plans.items():
         prm = plan.params
-        key = (prm["c_split"], prm["P"], tuple(prm["M"]))
+        key = (prm["c_split"], prm["P"], tuple(prm["M"]), prm["force"])
         if key not in refs:
-            refs[key] = esp_grid.esp_grid(h, r64, q64, gp(prm))
+            refs[key] = (esp_grid.esp_grid_ik if prm["force"] == 1 else esp_grid.esp_grid)(h, r64, q64, gp(prm))
         ref = refs[key]
         fo, oo = f.cpu().numpy().astype(np.float64), o.cpu().numpy()
         out["parity_vs_oracle"][name] = {
@@ -288,6 +288,10 @@ def main():
     pa, tuned_a = make_plan("fp32", "analytic", x32, c32)
     dta, fa, oa = run_plan(pa, x32, c32, args.steps, args.warmup, torch)
 
+    # ---- FP32 with ik-differentiated forces (momentum-conserving option) ------------
+    pik = Plan(h, N, args.tol, precision="fp32", params=args.params, force="ik", tile=p32.params["tile"][0])
+    dtik, fik, oik = run_plan(pik, x32, c32, args.steps, args.warmup, torch)
+
     # ---- plain FP64 path, analytic parameters -------------------------------------
     p64, tuned_64 = make_plan("fp64", "analytic", x64, c64)
     dt64, f64, o64 = run_plan(p64, x64, c64, args.steps, args.warmup, torch)
@@ -298,7 +302,8 @@ def main():
     extra = {}
     if not args.no_cpu:
         extra = oracle_leg(h, r32, q32, {"fp32_headline": (p32, f32, o32), "fp32_analytic": (pa, fa, oa),
-                                         "fp64_analytic": (p64, f64, o64)}, "fp32_headline")
+                                         "fp64_analytic": (p64, f64, o64), "fp32_ik": (pik, fik, oik)},
+                           "fp32_headline")
         cpu = extra.pop("cpu_baseline")
 
     prm = p32.params
@@ -342,6 +347,9 @@ def main():
         "fp32_analytic": {"value": round(va, 3), "ms_per_step": dta / args.steps * 1e3, **brief(pa)},
         "learned_gain_vs_analytic": value / va,
         "batch_64_replicas": batch,
+        "ik_forces_fp32": {"value": round(N * args.steps / dtik / 1e6, 3), "ms_per_step": dtik / args.steps * 1e3,
+                           "net_force_over_rms": float(np.linalg.norm(fik.double().sum(0).cpu().numpy())
+                                                       / np.sqrt(np.sum(fik.double().cpu().numpy() ** 2)))},
         **extra,
         "stage_ms_fp32": {k: v[0] / v[1] for k, v in stages.items()},
         "roofline": {"kernel": dominant, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,

@@ -105,9 +105,16 @@ typedef struct {
                           96+ particles on average; ESP_GATHER_PARTICLE (1) or
                           ESP_GATHER_TILE (2) force one variant (the tile variant
                           is refused if its potential box does not fit in LDS) */
+  int force;           /* ESP_FORCE_AD (0, default): analytic differentiation,
+                          one inverse FFT and a window-gradient gather (App. C,
+                          eq. AD); ESP_FORCE_IK (1): ik-differentiation, three
+                          inverse FFTs of i k F_hat rho_hat / W_hat^2 and a
+                          plain-window gather (App. C, eq. rhodiagforce), which
+                          conserves momentum.  Energy and virial are the same. */
 } esp_opts;
 
 enum { ESP_GATHER_AUTO = 0, ESP_GATHER_PARTICLE = 1, ESP_GATHER_TILE = 2 };
+enum { ESP_FORCE_AD = 0, ESP_FORCE_IK = 1 };
 
 /* Parameters a plan resolved to (returned by esp_get_params). */
 typedef struct {
@@ -125,6 +132,7 @@ typedef struct {
   double predicted_cost;          /* ESP_LEARNED: cost-model value of the choice */
   int gather_tiled;               /* 1: the gather stages each tile's potential in LDS */
   int counter_copies;             /* tile-counter copies used by the cell sort */
+  int force;                      /* ESP_FORCE_AD or ESP_FORCE_IK */
 } esp_params;
 
 void esp_opts_default(esp_opts *o);
@@ -290,6 +298,7 @@ esp_status esp_proposer_set(const esp_proposer *p);
  *     call change) and replays it; the graph holds no memset nodes.
  *   esp_batch_check: synchronise and report device-side errors of any
  *     replica (as esp_check).
+ * Batched forces use analytic differentiation (o->force must be ESP_FORCE_AD).
  * Errors and warnings of a replica's planning are returned by
  * esp_batch_plan with the replica index in the error text. */
 esp_status esp_batch_plan(int nrep, const double *h, const int64_t *n, const double *tol,

@@ -271,7 +271,9 @@ __global__ void __launch_bounds__(1024) k_fft_xy_inv(KArg<R, BATCH> ka) {
   const int nth = blockDim.x, tid = threadIdx.x;
   for (int k = tid; k < M1; k += nth) tw1[k] = d.tw[d.f1.tw + k];
   for (int k = tid; k < M2; k += nth) tw2[k] = d.tw[d.f2.tw + k];
-  const Cplx<R>* in = d.spec + static_cast<size_t>(blk) * M2 * H;
+  // block = component * M3 + plane (one component unless the plan uses ik forces)
+  const int comp = blk / d.M3, zp = blk - comp * d.M3;
+  const Cplx<R>* in = d.spec + static_cast<size_t>(comp) * d.M3 * M2 * H + static_cast<size_t>(zp) * M2 * H;
   for (int k = tid; k < M2 * H; k += nth) A[k] = in[k];
   __syncthreads();
   Cplx<R>* res = fft_lines(A, B, d.f2, H, 1, H, tw2, true);
@@ -291,7 +293,7 @@ __global__ void __launch_bounds__(1024) k_fft_xy_inv(KArg<R, BATCH> ka) {
   }
   __syncthreads();
   res = fft_lines(oth, res, d.f1, npairs, M1, 1, tw1, true);
-  R* plane = d.phi + static_cast<size_t>(blk) * M2 * M1;
+  R* plane = d.phi + static_cast<size_t>(comp) * d.M3 * M2 * M1 + static_cast<size_t>(zp) * M2 * M1;
   for (int k = tid; k < npairs * M1; k += nth) {
     const int p = k / M1, x = k - p * M1;
     plane[(2 * p) * M1 + x] = res[k].x;
@@ -340,7 +342,8 @@ __global__ void __launch_bounds__(256) k_fft_z(KArg<R, BATCH> ka, int mode) {
   double* red = reinterpret_cast<double*>(smem);                   // kNumSums x 16
   Cplx<R>* A = reinterpret_cast<Cplx<R>*>(red + kNumSums * 16);
   Cplx<R>* B = A + cz * M3;
-  Cplx<R>* tw3 = B + cz * M3;
+  Cplx<R>* C = B + cz * M3;                                        // third column buffer (Z_IK)
+  Cplx<R>* tw3 = C + (mode == Z_IK ? cz * M3 : 0);
   R* kf = reinterpret_cast<R*>(tw3 + M3);
   R* kg = kf + d.nker + 1;
   const int nth = blockDim.x, tid = threadIdx.x;
@@ -399,7 +402,7 @@ __global__ void __launch_bounds__(256) k_fft_z(KArg<R, BATCH> ka, int mode) {
       acc[6].add(be * ky * kz);
       g = Fh * iw * d.inv_vol;
     }
-    if (mode == Z_POTENTIAL) res[k] = cscale(v, g);
+    if (mode >= Z_POTENTIAL) res[k] = cscale(v, g);
   }
   double sums[kNumSums];
 #pragma unroll
@@ -408,13 +411,42 @@ __global__ void __launch_bounds__(256) k_fft_z(KArg<R, BATCH> ka, int mode) {
   if (tid == 0)
 #pragma unroll
     for (int k = 0; k < kNumSums; ++k) d.zpart[static_cast<size_t>(blk) * kNumSums + k] = sums[k];
-  if (mode != Z_POTENTIAL) return;
+  if (mode == Z_ENERGY) return;
   __syncthreads();
   Cplx<R>* oth = res == A ? B : A;
-  res = fft_lines(res, oth, d.f3, nc, 1, nc, tw3, true);
-  for (int k = tid; k < nc * M3; k += nth) {
-    const int z = k / nc, c = k - z * nc;
-    col[z * colstride + c] = res[k];
+  if (mode == Z_POTENTIAL) {
+    res = fft_lines(res, oth, d.f3, nc, 1, nc, tw3, true);
+    for (int k = tid; k < nc * M3; k += nth) {
+      const int z = k / nc, c = k - z * nc;
+      col[z * colstride + c] = res[k];
+    }
+    return;
+  }
+  // Z_IK: the three components i k_a G rho_hat of the field (App. C,
+  // eq. rhodiagforce), each inverse-transformed along z into its own half
+  // spectrum.  Nyquist modes of even grids have no -m partner and are dropped.
+  const size_t S = static_cast<size_t>(H) * M2 * M3;
+  const bool nyq2 = (M2 % 2 == 0) && 2 * y == M2;
+  for (int a = 0; a < 3; ++a) {
+    for (int k = tid; k < nc * M3; k += nth) {
+      const int z = k / nc, c = k - z * nc;
+      const int i1 = k0 + c;
+      const int m1 = i1 <= (M1 - 1) / 2 ? i1 : i1 - M1;
+      const int m3 = z <= (M3 - 1) / 2 ? z : z - M3;
+      const bool nyq = nyq2 || ((M1 % 2 == 0) && 2 * i1 == M1) || ((M3 % 2 == 0) && 2 * z == M3);
+      const R fm1 = R(m1), fm2 = R(m2), fm3 = R(m3);
+      const R ka = d.B[3 * a] * fm1 + d.B[3 * a + 1] * fm2 + d.B[3 * a + 2] * fm3;
+      const Cplx<R> v = res[k];
+      C[k] = nyq ? Cplx<R>{R(0), R(0)} : Cplx<R>{-ka * v.y, ka * v.x};     // i k_a (G rho_hat)
+    }
+    __syncthreads();
+    Cplx<R>* out = fft_lines(C, oth, d.f3, nc, 1, nc, tw3, true);
+    Cplx<R>* dst = col + a * S;
+    for (int k = tid; k < nc * M3; k += nth) {
+      const int z = k / nc, c = k - z * nc;
+      dst[z * colstride + c] = out[k];
+    }
+    __syncthreads();
   }
 }
 
@@ -441,7 +473,7 @@ size_t lds_fft_xy(const DevPlan<R>& d) {
 
 template <typename R>
 size_t lds_fft_z(const DevPlan<R>& d) {
-  return (2 * static_cast<size_t>(d.cz) * d.M3 + d.M3) * sizeof(Cplx<R>) +
+  return ((d.ik ? 3 : 2) * static_cast<size_t>(d.cz) * d.M3 + d.M3) * sizeof(Cplx<R>) +
          (2 * (d.nker + 1) + 2) * sizeof(R) + kNumSums * 16 * sizeof(double) + 16;
 }
 
@@ -521,6 +553,9 @@ hipError_t launch_spread(const DevPlan<R>& d, hipStream_t s) {
 
 template <typename R>
 hipError_t launch_gather(const DevPlan<R>& d, R* f, double* out7, hipStream_t s) {
+  if (d.ik) {
+    ESP_P_SWITCH(d.P, gather_ik_launch, d, f, out7, s)
+  }
   ESP_P_SWITCH(d.P, gather_launch, d, f, out7, s)
 }
 
@@ -540,7 +575,7 @@ hipError_t launch_fft_xy_inv(const DevPlan<R>& d, hipStream_t s) {
   const size_t lds = lds_fft_xy(d);
   allow_lds(reinterpret_cast<const void*>(&k_fft_xy_inv<R, false>), lds);
   const int nth = fft_threads(d.M1 * d.M2);
-  hipLaunchKernelGGL((k_fft_xy_inv<R, false>), dim3(d.M3), dim3(nth), lds, s, KArg<R, false>{d});
+  hipLaunchKernelGGL((k_fft_xy_inv<R, false>), dim3(d.M3 * (d.ik ? 3 : 1)), dim3(nth), lds, s, KArg<R, false>{d});
   return hipGetLastError();
 }
 

@@ -38,6 +38,7 @@ struct Resolved {
   int coupling = ESP_ISO;
   double window_tol = 0;
   int gather = ESP_GATHER_AUTO;
+  int force = ESP_FORCE_AD;
   double pred[4] = {0, 0, 0, 0};
   double pred_cost = 0;
 };
@@ -279,6 +280,11 @@ esp_status resolve(const double* h, int64_t n, double tol, const esp_opts* o, Re
     return ESP_EINVAL;
   }
   r.gather = o->gather;
+  if (o->force != ESP_FORCE_AD && o->force != ESP_FORCE_IK) {
+    err = "force must be ESP_FORCE_AD or ESP_FORCE_IK";
+    return ESP_EINVAL;
+  }
+  r.force = o->force;
   std::memcpy(r.h, h, 9 * sizeof(double));
   esp_status st = check_box(h, r.rc, r.hinv, &r.V, err);
   if (st != ESP_OK) return st;
@@ -544,6 +550,7 @@ esp_status build_device(esp_plan_t* p) {
   }
   d.nzblk = ((d.H + d.cz - 1) / d.cz) * d.M2;
   d.nbin = static_cast<int>((r.n + 255) / 256);
+  d.ik = r.force == ESP_FORCE_IK ? 1 : 0;
   d.kcut2 = static_cast<R>((r.c_split / r.rc) * (r.c_split / r.rc));
   d.ysc = static_cast<R>((r.rc / r.c_split) * (r.rc / r.c_split));
   d.A = static_cast<R>(p->A);
@@ -639,7 +646,7 @@ esp_status build_device(esp_plan_t* p) {
       (st = dalloc(p, &d.offsets, r.ntiles + 1)) ||
       (st = dalloc(p, &d.keys, r.n)) || (st = dalloc(p, &d.ranks, r.n)) || (st = dalloc(p, &d.perm, r.n)) ||
       (st = dalloc(p, &d.tmp, r.n)) || (st = dalloc(p, &d.sorted, r.n)) || (st = dalloc(p, &d.rho, G)) ||
-      (st = dalloc(p, &d.spec, S)) || (st = dalloc(p, &d.phi, G)) ||
+      (st = dalloc(p, &d.spec, S * (d.ik ? 3 : 1))) || (st = dalloc(p, &d.phi, G * (d.ik ? 3 : 1))) ||
       (st = dalloc(p, &d.zpart, static_cast<size_t>(d.nzblk) * kNumSums)) ||
       (st = dalloc(p, &d.qpart, static_cast<size_t>(d.nbin) * 2)) || (st = dalloc(p, &d.flags, 4)))
     return st;
@@ -712,13 +719,16 @@ esp_status energy_virial(esp_plan_t* p, const R* xyz, const R* q, double* out7) 
   return e == hipSuccess ? ESP_OK : hip_fail(p, e, "kernel launch");
 }
 
+// Sort, spread, forward FFT and the z pass in the given mode (Z_POTENTIAL:
+// the potential grid; Z_IK: the three field components), then the inverse
+// xy pass of every component.
 template <typename R>
-esp_status potential(esp_plan_t* p, const R* xyz, const R* q) {
+esp_status potential(esp_plan_t* p, const R* xyz, const R* q, ZMode mode = Z_POTENTIAL) {
   DevPlan<R>& d = dev<R>(p);
   esp_status st = run_sort_spread(p, xyz, q);
   if (st != ESP_OK) return st;
   hipError_t e = stage(p, ST_FFT_XY, [&] { return launch_fft_xy(d, d.rho, d.spec, true, p->stream); });
-  if (e == hipSuccess) e = stage(p, ST_FFT_Z, [&] { return launch_fft_z(d, Z_POTENTIAL, p->stream); });
+  if (e == hipSuccess) e = stage(p, ST_FFT_Z, [&] { return launch_fft_z(d, mode, p->stream); });
   if (e == hipSuccess) e = stage(p, ST_FFT_XY_INV, [&] { return launch_fft_xy_inv(d, p->stream); });
   return e == hipSuccess ? ESP_OK : hip_fail(p, e, "kernel launch");
 }
@@ -729,9 +739,9 @@ esp_status forces(esp_plan_t* p, const R* xyz, const R* q, R* f, double* out7) {
     p->err = "null pointer argument";
     return ESP_EINVAL;
   }
-  esp_status st = potential(p, xyz, q);
-  if (st != ESP_OK) return st;
   DevPlan<R>& d = dev<R>(p);
+  esp_status st = potential(p, xyz, q, d.ik ? Z_IK : Z_POTENTIAL);
+  if (st != ESP_OK) return st;
   hipError_t e = stage(p, ST_GATHER, [&] { return launch_gather(d, f, out7, p->stream); });
   return e == hipSuccess ? ESP_OK : hip_fail(p, e, "kernel launch");
 }
@@ -938,6 +948,7 @@ esp_status esp_get_params(const esp_plan_t* p, esp_params* out) {
   out->predicted_cost = r.pred_cost;
   out->gather_tiled = r.precision == ESP_FP32 ? p->d32.gather_tiled : p->d64.gather_tiled;
   out->counter_copies = r.precision == ESP_FP32 ? p->d32.nsub : p->d64.nsub;
+  out->force = r.force;
   return ESP_OK;
 }
 
@@ -1369,6 +1380,10 @@ esp_status esp_batch_plan(int nrep, const double* h, const int64_t* n, const dou
   esp_opts base;
   esp_opts_default(&base);
   if (o) base = *o;
+  if (base.force != ESP_FORCE_AD) {
+    std::fprintf(stderr, "esp_batch_plan: batched forces use analytic differentiation\n");
+    return ESP_EINVAL;
+  }
   std::unique_ptr<esp_batch_s> b(new (std::nothrow) esp_batch_s());
   if (!b) return ESP_ENOMEM;
   b->nrep = nrep;

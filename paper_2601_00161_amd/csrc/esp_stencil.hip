@@ -236,6 +236,95 @@ __global__ void __launch_bounds__(256) k_gather(KArg<R, BATCH> ka, R* __restrict
   }
 }
 
+// Gather of the ik-differentiated field (App. C, eq. rhodiagforce): the three
+// Cartesian components E_a of the gradient of the smoothed potential are
+// separate grids (phi + a M1 M2 M3); the force is F = -q sum_g W(u - g) E(g)
+// with the plain window.  Lane layout as in k_gather.
+template <typename R, int P, int NW, bool BATCH>
+__global__ void __launch_bounds__(256) k_gather_ik(KArg<R, BATCH> ka, R* __restrict__ f,
+                                                   double* __restrict__ out7) {
+  constexpr int L = GatherLanes<P>::L;
+  constexpr int G = 256 / L;
+  int blk;
+  const DevPlan<R>& d = plan_of(ka, blk);
+  f += 3 * d.pofs;
+  if (out7 && blk == 0) {
+    __shared__ double red[kNumSums * 16];
+    finalize_sums(d, out7 + kNumSums * d.rep, red);
+  }
+  extern __shared__ __align__(16) unsigned char smem[];
+  R* win = reinterpret_cast<R*>(smem);                // (NW + 1) x P
+  R* wt = win + (NW + 1) * P;                         // G x 3 x P: w1 w2 w3
+  for (int k = threadIdx.x; k < (NW + 1) * P; k += blockDim.x) win[k] = d.win[k];
+  __syncthreads();
+  const int grp = threadIdx.x / L, lane = threadIdx.x - grp * L;
+  const int64_t i = static_cast<int64_t>(blk) * G + grp;
+  const bool valid = i < d.n;
+  const Record<R> rec = d.sorted[valid ? i : 0];
+  int g1, g2, g3;
+  R t1, t2, t3;
+  Coord<R>::stencil(rec, 0, d.M1, P, g1, t1);
+  Coord<R>::stencil(rec, 1, d.M2, P, g2, t2);
+  Coord<R>::stencil(rec, 2, d.M3, P, g3, t3);
+  R* my = wt + grp * 3 * P;
+  if (lane < 3) {
+    R w[P];
+    eval_window<R, P, NW>(win, lane == 0 ? t1 : (lane == 1 ? t2 : t3), w);
+#pragma unroll
+    for (int p = 0; p < P; ++p) my[lane * P + p] = w[p];
+  }
+  __syncthreads();
+  R ex = R(0), ey = R(0), ez = R(0);
+  if (lane < P) {
+    const size_t G3 = static_cast<size_t>(d.M1) * d.M2 * d.M3;
+    int xi[P];
+#pragma unroll
+    for (int a = 0; a < P; ++a) {
+      const int x = g1 + a;
+      xi[a] = x >= d.M1 ? x - d.M1 : x;
+    }
+    R w1[P];
+#pragma unroll
+    for (int a = 0; a < P; ++a) w1[a] = my[a];
+    int z = g3 + lane;
+    z -= z >= d.M3 ? d.M3 : 0;
+#pragma unroll
+    for (int b = 0; b < P; ++b) {
+      int y = g2 + b;
+      y -= y >= d.M2 ? d.M2 : 0;
+      const R* row = d.phi + (static_cast<size_t>(z) * d.M2 + y) * d.M1;
+      R sx = R(0), sy = R(0), sz = R(0);
+#pragma unroll
+      for (int a = 0; a < P; ++a) {
+        sx += row[xi[a]] * w1[a];
+        sy += row[G3 + xi[a]] * w1[a];
+        sz += row[2 * G3 + xi[a]] * w1[a];
+      }
+      const R w2 = my[P + b];
+      ex += sx * w2;
+      ey += sy * w2;
+      ez += sz * w2;
+    }
+    const R w3 = my[2 * P + lane];
+    ex *= w3;
+    ey *= w3;
+    ez *= w3;
+  }
+#pragma unroll
+  for (int off = L / 2; off > 0; off >>= 1) {
+    ex += __shfl_xor(ex, off, 64);
+    ey += __shfl_xor(ey, off, 64);
+    ez += __shfl_xor(ez, off, 64);
+  }
+  if (lane == 0 && valid) {
+    const R qk = -rec.q * d.coulomb_k;
+    const int64_t j = d.perm[i];
+    f[3 * j + 0] = qk * ex;
+    f[3 * j + 1] = qk * ey;
+    f[3 * j + 2] = qk * ez;
+  }
+}
+
 // Tile-staged gather, for dense tiles: one workgroup per tile.  The
 // potential on the tile's stencil box (its cells plus P - 1 more along each
 // cell vector, cyclically) is staged in LDS once, then the tile's particles
@@ -413,6 +502,20 @@ hipError_t gather_launch(const DevPlan<R>& d, R* f, double* out7, hipStream_t s)
   ESP_NW_SWITCH(d.nw, gather_nw, d, f, out7, s)
 }
 
+template <typename R, int P, int NW>
+static hipError_t gather_ik_nw(const DevPlan<R>& d, R* f, double* out7, hipStream_t s) {
+  constexpr int G = 256 / GatherLanes<P>::L;
+  const int nb = static_cast<int>((d.n + G - 1) / G);
+  const size_t lds = ((NW + 1) * P + G * 3 * P) * sizeof(R);
+  hipLaunchKernelGGL((k_gather_ik<R, P, NW, false>), dim3(nb), dim3(256), lds, s, KArg<R, false>{d}, f, out7);
+  return hipGetLastError();
+}
+
+template <typename R, int P>
+hipError_t gather_ik_launch(const DevPlan<R>& d, R* f, double* out7, hipStream_t s) {
+  ESP_NW_SWITCH(d.nw, gather_ik_nw, d, f, out7, s)
+}
+
 template <typename R, int P>
 hipError_t spread_launch_batch(const BatchLaunch<R>& b, hipStream_t s) {
   ESP_NW_SWITCH(b.nw, spread_nw_batch, b, s)
@@ -427,6 +530,8 @@ template hipError_t spread_launch<float, ESP_P>(const DevPlan<float>&, hipStream
 template hipError_t spread_launch<double, ESP_P>(const DevPlan<double>&, hipStream_t);
 template hipError_t gather_launch<float, ESP_P>(const DevPlan<float>&, float*, double*, hipStream_t);
 template hipError_t gather_launch<double, ESP_P>(const DevPlan<double>&, double*, double*, hipStream_t);
+template hipError_t gather_ik_launch<float, ESP_P>(const DevPlan<float>&, float*, double*, hipStream_t);
+template hipError_t gather_ik_launch<double, ESP_P>(const DevPlan<double>&, double*, double*, hipStream_t);
 template hipError_t spread_launch_batch<float, ESP_P>(const BatchLaunch<float>&, hipStream_t);
 template hipError_t spread_launch_batch<double, ESP_P>(const BatchLaunch<double>&, hipStream_t);
 template hipError_t gather_launch_batch<float, ESP_P>(const BatchLaunch<float>&, float*, double*, hipStream_t);

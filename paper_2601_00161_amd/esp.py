@@ -24,6 +24,7 @@ PRECISION = {"fp32": 0, "fp64": 1}
 PARAMS = {"analytic": 0, "explicit": 1, "learned": 2}
 COUPLING = {"iso": 0, "semi": 1, "aniso": 2, "flex": 3}
 GATHER = {"auto": 0, "particle": 1, "tile": 2}
+FORCE = {"ad": 0, "ik": 1}
 
 
 class EspError(RuntimeError):
@@ -37,7 +38,7 @@ class Opts(ctypes.Structure):
                 ("rc", ctypes.c_double), ("c_split", ctypes.c_double), ("c_spread", ctypes.c_double),
                 ("P", ctypes.c_int), ("M", ctypes.c_int * 3), ("grid_sigma", ctypes.c_double),
                 ("coulomb_k", ctypes.c_double), ("tile", ctypes.c_int), ("stream", ctypes.c_void_p),
-                ("window_tol", ctypes.c_double), ("gather", ctypes.c_int)]
+                ("window_tol", ctypes.c_double), ("gather", ctypes.c_int), ("force", ctypes.c_int)]
 
 
 class Params(ctypes.Structure):
@@ -49,7 +50,7 @@ class Params(ctypes.Structure):
                 ("C0_split", ctypes.c_double), ("psi0_split", ctypes.c_double),
                 ("volume", ctypes.c_double), ("params_source", ctypes.c_int),
                 ("predicted_log10_err", ctypes.c_double * 4), ("predicted_cost", ctypes.c_double),
-                ("gather_tiled", ctypes.c_int), ("counter_copies", ctypes.c_int)]
+                ("gather_tiled", ctypes.c_int), ("counter_copies", ctypes.c_int), ("force", ctypes.c_int)]
 
     def as_dict(self):
         out = {}
@@ -150,7 +151,7 @@ def _cell(h):
 
 def make_opts(precision="fp32", params="analytic", coupling="iso", rc=0.9, c_split=None,
               c_spread=None, P=None, M=None, grid_sigma=1.07, coulomb_k=1.0, tile=0, stream=None,
-              window_tol=0.0, gather="auto"):
+              window_tol=0.0, gather="auto", force="ad"):
     o = Opts()
     lib().esp_opts_default(ctypes.byref(o))
     o.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
@@ -177,6 +178,7 @@ def make_opts(precision="fp32", params="analytic", coupling="iso", rc=0.9, c_spl
     o.stream = stream
     o.window_tol = float(window_tol)
     o.gather = GATHER[gather] if isinstance(gather, str) else int(gather)
+    o.force = FORCE[force] if isinstance(force, str) else int(force)
     return o
 
 

@@ -118,3 +118,21 @@ def test_batch_64_replicas():
         assert tensor_rel(out[k], ref.virial) < TOL["fp32"]
         assert rel_rms(f[sl], ref.forces) < TOL["fp32"]
     b.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_water_30k_ik_forces(precision):
+    """ik-differentiation at the benchmark size against the oracle's ik forces."""
+    from oracle import esp_grid
+    h, r, q = synth.config2()
+    r_, q_, r64, q64 = as_inputs(r, q, precision)
+    kw = {"window_tol": 1e-13} if precision == "fp64" else {}
+    plan = esp.Plan(h, len(q), 1e-5, precision=precision, force="ik", **kw)
+    f, out = gpu(plan, r_, q_)
+    prm = plan.params
+    ref = esp_grid.esp_grid_ik(h, r64, q64, esp_grid.GridParams(prm["c_split"], prm["c_spread"], prm["P"],
+                                                                tuple(prm["M"]), prm["rc"]))
+    e = (abs(out[0] - ref.energy) / abs(ref.energy), tensor_rel(out, ref.virial), rel_rms(f, ref.forces))
+    print(f"ik {precision}: {e}", flush=True)
+    assert max(e) < TOL[precision]
+    plan.close()

@@ -186,3 +186,28 @@ def test_forces(case, precision, dev):
     assert tensor_rel(out, ref.virial) < TOL[precision]
     assert np.max(np.abs(out - out_ev)) <= 1e-6 * np.max(np.abs(out_ev)) + 1e-12
     plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("case", SYSTEMS, ids=IDS)
+def test_forces_ik(case, precision, dev):
+    """ik-differentiation (App. C, eq. rhodiagforce): forces against the oracle's
+    ik forces, energy and virial unchanged, and the net force zero up to the
+    rounding of the forces themselves."""
+    from oracle import esp_grid
+    name, h, r, q, prm = case
+    r_, q_, r64, q64 = as_inputs(r, q, precision)
+    plan = make_plan(h, len(q), prm, precision, force="ik")
+    assert plan.params["force"] == 1
+    f, out = plan.forces(to_dev(r_, dev), to_dev(q_, dev))
+    f = f.cpu().numpy().astype(np.float64)
+    out = out.cpu().numpy()
+    ref = esp_grid.esp_grid_ik(h, r64, q64, esp_grid.GridParams(prm["c_split"], prm["c_spread"], prm["P"],
+                                                                tuple(prm["M"]), prm["rc"]))
+    assert rel_rms(f, ref.forces) < TOL[precision]
+    assert abs(out[0] - ref.energy) / abs(ref.energy) < TOL[precision]
+    assert tensor_rel(out, ref.virial) < TOL[precision]
+    fscale = np.sqrt(np.mean(np.sum(ref.forces ** 2, axis=1)))
+    eps = 1e-6 if precision == "fp32" else 1e-12
+    assert np.linalg.norm(f.sum(axis=0)) < eps * np.sqrt(len(q)) * fscale
+    plan.close()

@@ -157,3 +157,9 @@ def test_autotune_cache_key():
 def test_gather_option_is_validated():
     with pytest.raises(esp.EspError):
         esp.resolve_params(np.diag([3.0, 3.0, 3.0]), 100, 1e-4, gather=7)
+
+
+def test_force_option_is_validated():
+    with pytest.raises(esp.EspError):
+        esp.resolve_params(np.diag([3.0, 3.0, 3.0]), 100, 1e-4, force=5)
+    assert esp.resolve_params(np.diag([3.0, 3.0, 3.0]), 100, 1e-4, force="ik")["P"] >= 2
