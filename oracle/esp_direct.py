@@ -94,6 +94,22 @@ def fourier_space(h, r, q, c, rc, forces=True):
     return U, W, F
 
 
+def fourier_local_virial(h, r, q, c, rc):
+    """Per-particle share of the Fourier-space virial (Sec. 4.4, eq. PinsFind
+    with explicit sums): W^i = q_i / (2V) sum_k P_hat(k) Re[exp(-i k.r_i) rho(k)],
+    (N, 3, 3).  The shares add up to W_F of `fourier_space`."""
+    h = np.asarray(h, np.float64)
+    q = np.asarray(q, np.float64)
+    V = lattice.volume(h)
+    mmax = lattice.mode_box(h, c / rc)
+    _, k = lattice.mode_vectors(h, mmax)
+    Phat = splitting.pressure_kernel(k, c, rc)
+    S = lattice.structure_factor(h, r, q, mmax)
+    X = np.moveaxis((Phat * S[..., None, None]).reshape(S.shape + (9,)), -1, 0)
+    T = lattice.back_transform(h, r, X, mmax)
+    return (q[:, None] / (2.0 * V) * T.real).reshape(-1, 3, 3)
+
+
 def esp_direct(h, r, q, c, rc, forces=True):
     """All terms of the PSWF split with explicit Fourier sums."""
     h = np.asarray(h, np.float64)

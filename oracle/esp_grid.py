@@ -30,6 +30,13 @@ Readings taken where the paper is silent or inconsistent:
 The FFT is numpy's full complex transform (sign exp(-2 pi i m.g/M)); no
 half-spectrum symmetry is used.
 
+`local_virial` is the per-particle split of the Fourier virial (Sec. 4.4,
+eq. rhodiag, eq. PinsFind): Pi = inverse FFT of P_hat rho_hat / W_hat^2 per
+tensor component, gathered with the plain window and scaled by q_i / (2V),
+so that the shares add up to W_F exactly on the grid (the spreading weights
+are a partition of the grid charge).  The background term of eq. Corr is not
+split.
+
 `esp_grid_ik` is the other force option of App. C, ik-differentiation
 (eq. rhodiagforce): the field i k F_hat rho_hat / (V W_hat^2) is brought back
 by three inverse FFTs and gathered with the plain window.  Reading: a mode
@@ -217,3 +224,32 @@ def esp_grid_ik(h, r, q, prm: GridParams):
                     acc += E[ia, ib, ic] * w[:, 0, i1] * w[:, 1, i2] * w[:, 2, i3]
         F[:, a] = -q * acc
     return GridResult(base.energy, base.virial, F, base.U_F, base.U_self, base.U_corr, base.rho_grid, None)
+
+
+def local_virial(h, r, q, prm: GridParams):
+    """Per-particle Fourier virial W^i (N, 3, 3): q_i / (2V) sum_g W(u_i - g) Pi(g),
+    Pi = unnormalised inverse FFT of P_hat rho_hat / W_hat^2 (eq. rhodiag, eq. PinsFind)."""
+    h = np.asarray(h, np.float64)
+    r = np.asarray(r, np.float64)
+    q = np.asarray(q, np.float64)
+    V = lattice.volume(h)
+    M = np.asarray(prm.M, dtype=np.int64)
+    rho_hat = np.fft.fftn(spread(h, r, q, prm))
+    _, What, _, Phat = mode_weights(h, prm)
+    u = grid_coordinates(h, r, M)
+    g0, w, _ = stencil(u, prm.P, prm.c_spread)
+    out = np.zeros((r.shape[0], 3, 3))
+    P = prm.P
+    for a in range(3):
+        for b in range(a, 3):
+            Pi = np.real(np.fft.ifftn(Phat[..., a, b] / What ** 2 * rho_hat)) * float(np.prod(M))
+            acc = np.zeros(r.shape[0])
+            for i1 in range(P):
+                ia = (g0[:, 0] + i1) % M[0]
+                for i2 in range(P):
+                    ib = (g0[:, 1] + i2) % M[1]
+                    for i3 in range(P):
+                        ic = (g0[:, 2] + i3) % M[2]
+                        acc += Pi[ia, ib, ic] * w[:, 0, i1] * w[:, 1, i2] * w[:, 2, i3]
+            out[:, a, b] = out[:, b, a] = q * acc / (2.0 * V)
+    return out

@@ -212,3 +212,34 @@ def test_nyquist_modes_dropped_only_for_even_grids():
     assert m.shape == (4, 5, 6)
     assert not m[2].any() and not m[:, :, 3].any()
     assert m.sum() == 3 * 5 * 5
+
+
+# ---- per-particle (local) virial (Sec. 4.4, eq. rhodiag, eq. PinsFind) ------
+def test_direct_local_virial_adds_up(sysA):
+    h, r, q, _ = sysA
+    c = c_from_tol(1e-6)
+    _, W_F, _ = esp_direct.fourier_space(h, r, q, c, RC, forces=False)
+    Wi = esp_direct.fourier_local_virial(h, r, q, c, RC)
+    assert np.max(np.abs(Wi.sum(axis=0) - W_F)) < 1e-12 * np.max(np.abs(W_F))
+    assert np.array_equal(Wi, np.transpose(Wi, (0, 2, 1)))
+
+
+def test_grid_local_virial_adds_up(water_small):
+    """The shares add up to the gridded Fourier virial (no background term for
+    a neutral system) to rounding."""
+    h, r, q, prm = water_small
+    g = esp_grid.esp_grid(h, r, q, prm, forces=False)
+    Wi = esp_grid.local_virial(h, r, q, prm)
+    assert np.max(np.abs(Wi.sum(axis=0) - g.virial)) < 1e-12 * np.max(np.abs(g.virial))
+
+
+def test_grid_local_virial_converges_to_direct(sysA):
+    """Refining window and grid drives each particle's share to the explicit
+    Fourier-sum share (pins P_hat per component, the deconvolution and the
+    q_i / 2V factor particle by particle)."""
+    h, r, q, _ = sysA
+    c = c_from_tol(1e-6)
+    ref = esp_direct.fourier_local_virial(h, r, q, c, RC)
+    prm = _grid_params(h, c, c_from_tol(1e-13), 16, 2.0)
+    Wi = esp_grid.local_virial(h, r, q, prm)
+    assert np.max(np.abs(Wi - ref)) < 1e-10 * np.max(np.abs(ref))
