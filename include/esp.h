@@ -111,6 +111,8 @@ typedef struct {
                           inverse FFTs of i k F_hat rho_hat / W_hat^2 and a
                           plain-window gather (App. C, eq. rhodiagforce), which
                           conserves momentum.  Energy and virial are the same. */
+  int local_virial;    /* nonzero: allocate the six tensor-component grids used by
+                          esp_local_virial */
 } esp_opts;
 
 enum { ESP_GATHER_AUTO = 0, ESP_GATHER_PARTICLE = 1, ESP_GATHER_TILE = 2 };
@@ -133,6 +135,7 @@ typedef struct {
   int gather_tiled;               /* 1: the gather stages each tile's potential in LDS */
   int counter_copies;             /* tile-counter copies used by the cell sort */
   int force;                      /* ESP_FORCE_AD or ESP_FORCE_IK */
+  int local_virial;               /* the plan supports esp_local_virial */
 } esp_params;
 
 void esp_opts_default(esp_opts *o);
@@ -161,6 +164,19 @@ esp_status esp_energy_virial_f64(esp_plan_t *p, const double *xyz, const double 
 esp_status esp_forces(esp_plan_t *p, const float *xyz, const float *q, float *f, double *out7);
 esp_status esp_forces_f64(esp_plan_t *p, const double *xyz, const double *q, double *f,
                           double *out7);
+
+/* Per-particle share of the Fourier virial (Sec. 4.4, eq. rhodiag,
+ * eq. PinsFind), for pressure profiles of inhomogeneous systems: the six
+ * components of P_hat rho_hat / (2 V W_hat^2) are brought back by inverse
+ * FFTs and gathered with the plain window,
+ *   w6[6 i + c] = q_i sum_g W(u_i - g) Pi_c(g),  c = xx, yy, zz, xy, xz, yz,
+ * in input order (device, 6n reals of the plan's precision).  The shares add
+ * up to the Fourier virial W_F (out7 minus the background term of eq. Corr,
+ * which is not split).  out7 may be NULL.  Needs a plan made with
+ * o->local_virial != 0 (ESP_EINVAL otherwise). */
+esp_status esp_local_virial(esp_plan_t *p, const float *xyz, const float *q, float *w6, double *out7);
+esp_status esp_local_virial_f64(esp_plan_t *p, const double *xyz, const double *q, double *w6,
+                                double *out7);
 
 /* Synchronise the plan's stream and report device-side errors
  * (ESP_ENONFINITE) seen since the last check; clears the flag. */

@@ -404,6 +404,8 @@ hipError_t gather_launch(const DevPlan<R>& d, R* f, double* out7, hipStream_t s)
 template <typename R, int P>
 hipError_t gather_ik_launch(const DevPlan<R>& d, R* f, double* out7, hipStream_t s);
 template <typename R, int P>
+hipError_t gather_local_launch(const DevPlan<R>& d, R* w6, double* out7, hipStream_t s);
+template <typename R, int P>
 hipError_t spread_launch_batch(const BatchLaunch<R>& b, hipStream_t s);
 template <typename R, int P>
 hipError_t gather_launch_batch(const BatchLaunch<R>& b, R* f, double* out7, hipStream_t s);

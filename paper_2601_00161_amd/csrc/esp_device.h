@@ -97,14 +97,16 @@ struct DevPlan {
   Record<R>* tmp;                  // n: records in input order
   Record<R>* sorted;               // n
   R* rho;                          // M1 M2 M3 real grid (kept zero between calls)
-  Cplx<R>* spec;                   // H M2 M3 half spectrum (x 3 components for ik forces)
-  R* phi;                          // M1 M2 M3 potential grid (x 3 field components for ik forces)
+  Cplx<R>* spec;                   // ncomp x H M2 M3 half spectra
+  R* phi;                          // ncomp x M1 M2 M3 real grids (potential, ik field or Pi)
   double* zpart;                   // nzblk x 7 partial mode sums of the z-pass
   double* qpart;                   // nbin x 2 partial sums (sum q, sum q^2)
   int* flags;                      // bit 0: non-finite input; bit 1: inconsistent tile counts
   int bin_lds;                     // tile histogram of the binning pass fits in LDS
   int gather_tiled;                // gather stages each tile's potential box in LDS
   int ik;                          // forces by ik-differentiation (3 field components)
+  int local;                       // per-particle virial enabled (6 field components)
+  int ncomp;                       // spectra / real grids allocated (1, 3 or 6)
   int nsub;                        // tile counters per tile: binning block b uses copy b % nsub
   int* sbase;                      // nsub > 1: nsub x ntiles first rank of each copy in its tile
   FinalConsts fin;                 // final-sum constants (updated by esp_set_box)
@@ -159,13 +161,18 @@ template <typename R>
 hipError_t launch_fft_xy(const DevPlan<R>& d, const R* grid, Cplx<R>* spec, bool clear_input,
                          hipStream_t s);
 // Z_POTENTIAL: G rho_hat, inverse z; Z_IK: the three components i k_a G rho_hat,
-// each inverse z into its own half spectrum (spec + a * H M2 M3).
-enum ZMode { Z_FFT_ONLY = 0, Z_ENERGY = 1, Z_POTENTIAL = 2, Z_IK = 3 };
+// each inverse z into its own half spectrum (spec + a * H M2 M3); Z_LOCAL: the
+// six components of P_hat rho_hat / (2 V W_hat^2) (xx, yy, zz, xy, xz, yz).
+enum ZMode { Z_FFT_ONLY = 0, Z_ENERGY = 1, Z_POTENTIAL = 2, Z_IK = 3, Z_LOCAL = 4 };
 // z-pass; unless mode is Z_FFT_ONLY it writes nzblk x 7 partial mode sums.
 template <typename R>
 hipError_t launch_fft_z(const DevPlan<R>& d, ZMode mode, hipStream_t s);
+// Inverse xy pass of the first ncomp half spectra into the real grids.
 template <typename R>
-hipError_t launch_fft_xy_inv(const DevPlan<R>& d, hipStream_t s);
+hipError_t launch_fft_xy_inv(const DevPlan<R>& d, int ncomp, hipStream_t s);
+// Per-particle virial from the six Pi grids: w6[6 j + c], input order.
+template <typename R>
+hipError_t launch_gather_local(const DevPlan<R>& d, R* w6, double* out7, hipStream_t s);
 // Gather; when out7 is non-null its block 0 also writes the final sums.
 template <typename R>
 hipError_t launch_gather(const DevPlan<R>& d, R* f, double* out7, hipStream_t s);

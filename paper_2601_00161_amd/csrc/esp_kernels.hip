@@ -271,7 +271,7 @@ __global__ void __launch_bounds__(1024) k_fft_xy_inv(KArg<R, BATCH> ka) {
   const int nth = blockDim.x, tid = threadIdx.x;
   for (int k = tid; k < M1; k += nth) tw1[k] = d.tw[d.f1.tw + k];
   for (int k = tid; k < M2; k += nth) tw2[k] = d.tw[d.f2.tw + k];
-  // block = component * M3 + plane (one component unless the plan uses ik forces)
+  // block = component * M3 + plane
   const int comp = blk / d.M3, zp = blk - comp * d.M3;
   const Cplx<R>* in = d.spec + static_cast<size_t>(comp) * d.M3 * M2 * H + static_cast<size_t>(zp) * M2 * H;
   for (int k = tid; k < M2 * H; k += nth) A[k] = in[k];
@@ -342,10 +342,12 @@ __global__ void __launch_bounds__(256) k_fft_z(KArg<R, BATCH> ka, int mode) {
   double* red = reinterpret_cast<double*>(smem);                   // kNumSums x 16
   Cplx<R>* A = reinterpret_cast<Cplx<R>*>(red + kNumSums * 16);
   Cplx<R>* B = A + cz * M3;
-  Cplx<R>* C = B + cz * M3;                                        // third column buffer (Z_IK)
-  Cplx<R>* tw3 = C + (mode == Z_IK ? cz * M3 : 0);
+  Cplx<R>* C = B + cz * M3;                                        // component buffer (Z_IK, Z_LOCAL)
+  Cplx<R>* tw3 = C + (mode >= Z_IK ? cz * M3 : 0);
   R* kf = reinterpret_cast<R*>(tw3 + M3);
   R* kg = kf + d.nker + 1;
+  R* fw = kg + d.nker + 1;                                         // Z_LOCAL: F_hat / (2 V W_hat^2)
+  R* bw = fw + (mode == Z_LOCAL ? cz * M3 : 0);                    //          beta / (2 V W_hat^2)
   const int nth = blockDim.x, tid = threadIdx.x;
   for (int k = tid; k < M3; k += nth) tw3[k] = d.tw[d.f3.tw + k];
   for (int k = tid; k <= d.nker; k += nth) {
@@ -381,7 +383,7 @@ __global__ void __launch_bounds__(256) k_fft_z(KArg<R, BATCH> ka, int mode) {
     const R kz = d.B[6] * fm1 + d.B[7] * fm2 + d.B[8] * fm3;
     const R kk = kx * kx + ky * ky + kz * kz;
     const bool inside = (m1 | m2 | m3) != 0 && kk <= d.kcut2;
-    R g = R(0);
+    R g = R(0), fl = R(0), bl = R(0);
     if (inside) {
       const R zc = R(2) * kk * d.ysc - R(1);
       const R f = chebyshev(kf, d.nker, zc);
@@ -401,8 +403,14 @@ __global__ void __launch_bounds__(256) k_fft_z(KArg<R, BATCH> ka, int mode) {
       acc[5].add(be * kx * kz);
       acc[6].add(be * ky * kz);
       g = Fh * iw * d.inv_vol;
+      fl = R(0.5) * g;
+      bl = R(0.5) * beta * iw * d.inv_vol;
     }
-    if (mode >= Z_POTENTIAL) res[k] = cscale(v, g);
+    if (mode == Z_POTENTIAL || mode == Z_IK) res[k] = cscale(v, g);
+    if (mode == Z_LOCAL) {
+      fw[k] = fl;
+      bw[k] = bl;
+    }
   }
   double sums[kNumSums];
 #pragma unroll
@@ -425,9 +433,12 @@ __global__ void __launch_bounds__(256) k_fft_z(KArg<R, BATCH> ka, int mode) {
   // Z_IK: the three components i k_a G rho_hat of the field (App. C,
   // eq. rhodiagforce), each inverse-transformed along z into its own half
   // spectrum.  Nyquist modes of even grids have no -m partner and are dropped.
+  // Z_LOCAL: the six components P_hat_ab rho_hat / (2 V W_hat^2) (Sec. 4.4,
+  // eq. rhodiag), P_hat = F_hat I + beta k k^T.
   const size_t S = static_cast<size_t>(H) * M2 * M3;
   const bool nyq2 = (M2 % 2 == 0) && 2 * y == M2;
-  for (int a = 0; a < 3; ++a) {
+  const int ncomp = mode == Z_IK ? 3 : 6;
+  for (int a = 0; a < ncomp; ++a) {
     for (int k = tid; k < nc * M3; k += nth) {
       const int z = k / nc, c = k - z * nc;
       const int i1 = k0 + c;
@@ -435,9 +446,18 @@ __global__ void __launch_bounds__(256) k_fft_z(KArg<R, BATCH> ka, int mode) {
       const int m3 = z <= (M3 - 1) / 2 ? z : z - M3;
       const bool nyq = nyq2 || ((M1 % 2 == 0) && 2 * i1 == M1) || ((M3 % 2 == 0) && 2 * z == M3);
       const R fm1 = R(m1), fm2 = R(m2), fm3 = R(m3);
-      const R ka = d.B[3 * a] * fm1 + d.B[3 * a + 1] * fm2 + d.B[3 * a + 2] * fm3;
       const Cplx<R> v = res[k];
-      C[k] = nyq ? Cplx<R>{R(0), R(0)} : Cplx<R>{-ka * v.y, ka * v.x};     // i k_a (G rho_hat)
+      if (mode == Z_IK) {
+        const R ka = d.B[3 * a] * fm1 + d.B[3 * a + 1] * fm2 + d.B[3 * a + 2] * fm3;
+        C[k] = nyq ? Cplx<R>{R(0), R(0)} : Cplx<R>{-ka * v.y, ka * v.x};   // i k_a (G rho_hat)
+      } else {
+        // component a -> (i, j): xx yy zz xy xz yz
+        const int ci = a < 3 ? a : (a == 5 ? 1 : 0);
+        const int cj = a < 3 ? a : (a == 3 ? 1 : 2);
+        const R ki = d.B[3 * ci] * fm1 + d.B[3 * ci + 1] * fm2 + d.B[3 * ci + 2] * fm3;
+        const R kj = d.B[3 * cj] * fm1 + d.B[3 * cj + 1] * fm2 + d.B[3 * cj + 2] * fm3;
+        C[k] = cscale(v, (ci == cj ? fw[k] : R(0)) + bw[k] * ki * kj);
+      }
     }
     __syncthreads();
     Cplx<R>* out = fft_lines(C, oth, d.f3, nc, 1, nc, tw3, true);
@@ -473,8 +493,9 @@ size_t lds_fft_xy(const DevPlan<R>& d) {
 
 template <typename R>
 size_t lds_fft_z(const DevPlan<R>& d) {
-  return ((d.ik ? 3 : 2) * static_cast<size_t>(d.cz) * d.M3 + d.M3) * sizeof(Cplx<R>) +
-         (2 * (d.nker + 1) + 2) * sizeof(R) + kNumSums * 16 * sizeof(double) + 16;
+  const size_t col = static_cast<size_t>(d.cz) * d.M3;
+  return ((d.ncomp > 1 ? 3 : 2) * col + d.M3) * sizeof(Cplx<R>) +
+         (2 * (d.nker + 1) + 2 + (d.local ? 2 * col : 0)) * sizeof(R) + kNumSums * 16 * sizeof(double) + 16;
 }
 
 template <typename R>
@@ -552,6 +573,11 @@ hipError_t launch_spread(const DevPlan<R>& d, hipStream_t s) {
 }
 
 template <typename R>
+hipError_t launch_gather_local(const DevPlan<R>& d, R* w6, double* out7, hipStream_t s) {
+  ESP_P_SWITCH(d.P, gather_local_launch, d, w6, out7, s)
+}
+
+template <typename R>
 hipError_t launch_gather(const DevPlan<R>& d, R* f, double* out7, hipStream_t s) {
   if (d.ik) {
     ESP_P_SWITCH(d.P, gather_ik_launch, d, f, out7, s)
@@ -571,11 +597,11 @@ hipError_t launch_fft_xy(const DevPlan<R>& d, const R* grid, Cplx<R>* spec, bool
 }
 
 template <typename R>
-hipError_t launch_fft_xy_inv(const DevPlan<R>& d, hipStream_t s) {
+hipError_t launch_fft_xy_inv(const DevPlan<R>& d, int ncomp, hipStream_t s) {
   const size_t lds = lds_fft_xy(d);
   allow_lds(reinterpret_cast<const void*>(&k_fft_xy_inv<R, false>), lds);
   const int nth = fft_threads(d.M1 * d.M2);
-  hipLaunchKernelGGL((k_fft_xy_inv<R, false>), dim3(d.M3 * (d.ik ? 3 : 1)), dim3(nth), lds, s, KArg<R, false>{d});
+  hipLaunchKernelGGL((k_fft_xy_inv<R, false>), dim3(d.M3 * ncomp), dim3(nth), lds, s, KArg<R, false>{d});
   return hipGetLastError();
 }
 
@@ -664,7 +690,8 @@ hipError_t launch_fill(T* p, size_t count, hipStream_t s) {
   template hipError_t launch_spread<R>(const DevPlan<R>&, hipStream_t);                       \
   template hipError_t launch_fft_xy<R>(const DevPlan<R>&, const R*, Cplx<R>*, bool, hipStream_t); \
   template hipError_t launch_fft_z<R>(const DevPlan<R>&, ZMode, hipStream_t);                 \
-  template hipError_t launch_fft_xy_inv<R>(const DevPlan<R>&, hipStream_t);                   \
+  template hipError_t launch_fft_xy_inv<R>(const DevPlan<R>&, int, hipStream_t);              \
+  template hipError_t launch_gather_local<R>(const DevPlan<R>&, R*, double*, hipStream_t);    \
   template hipError_t launch_gather<R>(const DevPlan<R>&, R*, double*, hipStream_t);          \
   template hipError_t launch_bin_batch<R>(const BatchLaunch<R>&, const R*, const R*, hipStream_t); \
   template hipError_t launch_scatter_batch<R>(const BatchLaunch<R>&, hipStream_t);            \

@@ -39,6 +39,7 @@ struct Resolved {
   double window_tol = 0;
   int gather = ESP_GATHER_AUTO;
   int force = ESP_FORCE_AD;
+  int local = 0;
   double pred[4] = {0, 0, 0, 0};
   double pred_cost = 0;
 };
@@ -285,6 +286,7 @@ esp_status resolve(const double* h, int64_t n, double tol, const esp_opts* o, Re
     return ESP_EINVAL;
   }
   r.force = o->force;
+  r.local = o->local_virial ? 1 : 0;
   std::memcpy(r.h, h, 9 * sizeof(double));
   esp_status st = check_box(h, r.rc, r.hinv, &r.V, err);
   if (st != ESP_OK) return st;
@@ -551,6 +553,8 @@ esp_status build_device(esp_plan_t* p) {
   d.nzblk = ((d.H + d.cz - 1) / d.cz) * d.M2;
   d.nbin = static_cast<int>((r.n + 255) / 256);
   d.ik = r.force == ESP_FORCE_IK ? 1 : 0;
+  d.local = r.local;
+  d.ncomp = d.local ? 6 : (d.ik ? 3 : 1);
   d.kcut2 = static_cast<R>((r.c_split / r.rc) * (r.c_split / r.rc));
   d.ysc = static_cast<R>((r.rc / r.c_split) * (r.rc / r.c_split));
   d.A = static_cast<R>(p->A);
@@ -646,7 +650,7 @@ esp_status build_device(esp_plan_t* p) {
       (st = dalloc(p, &d.offsets, r.ntiles + 1)) ||
       (st = dalloc(p, &d.keys, r.n)) || (st = dalloc(p, &d.ranks, r.n)) || (st = dalloc(p, &d.perm, r.n)) ||
       (st = dalloc(p, &d.tmp, r.n)) || (st = dalloc(p, &d.sorted, r.n)) || (st = dalloc(p, &d.rho, G)) ||
-      (st = dalloc(p, &d.spec, S * (d.ik ? 3 : 1))) || (st = dalloc(p, &d.phi, G * (d.ik ? 3 : 1))) ||
+      (st = dalloc(p, &d.spec, S * d.ncomp)) || (st = dalloc(p, &d.phi, G * d.ncomp)) ||
       (st = dalloc(p, &d.zpart, static_cast<size_t>(d.nzblk) * kNumSums)) ||
       (st = dalloc(p, &d.qpart, static_cast<size_t>(d.nbin) * 2)) || (st = dalloc(p, &d.flags, 4)))
     return st;
@@ -729,7 +733,8 @@ esp_status potential(esp_plan_t* p, const R* xyz, const R* q, ZMode mode = Z_POT
   if (st != ESP_OK) return st;
   hipError_t e = stage(p, ST_FFT_XY, [&] { return launch_fft_xy(d, d.rho, d.spec, true, p->stream); });
   if (e == hipSuccess) e = stage(p, ST_FFT_Z, [&] { return launch_fft_z(d, mode, p->stream); });
-  if (e == hipSuccess) e = stage(p, ST_FFT_XY_INV, [&] { return launch_fft_xy_inv(d, p->stream); });
+  const int ncomp = mode == Z_IK ? 3 : (mode == Z_LOCAL ? 6 : 1);
+  if (e == hipSuccess) e = stage(p, ST_FFT_XY_INV, [&] { return launch_fft_xy_inv(d, ncomp, p->stream); });
   return e == hipSuccess ? ESP_OK : hip_fail(p, e, "kernel launch");
 }
 
@@ -743,6 +748,23 @@ esp_status forces(esp_plan_t* p, const R* xyz, const R* q, R* f, double* out7) {
   esp_status st = potential(p, xyz, q, d.ik ? Z_IK : Z_POTENTIAL);
   if (st != ESP_OK) return st;
   hipError_t e = stage(p, ST_GATHER, [&] { return launch_gather(d, f, out7, p->stream); });
+  return e == hipSuccess ? ESP_OK : hip_fail(p, e, "kernel launch");
+}
+
+template <typename R>
+esp_status local_virial(esp_plan_t* p, const R* xyz, const R* q, R* w6, double* out7) {
+  if (!xyz || !q || !w6) {
+    p->err = "null pointer argument";
+    return ESP_EINVAL;
+  }
+  DevPlan<R>& d = dev<R>(p);
+  if (!d.local) {
+    p->err = "the plan was made without local_virial";
+    return ESP_EINVAL;
+  }
+  esp_status st = potential(p, xyz, q, Z_LOCAL);
+  if (st != ESP_OK) return st;
+  hipError_t e = stage(p, ST_GATHER, [&] { return launch_gather_local(d, w6, out7, p->stream); });
   return e == hipSuccess ? ESP_OK : hip_fail(p, e, "kernel launch");
 }
 
@@ -900,6 +922,16 @@ esp_status esp_forces_f64(esp_plan_t* p, const double* xyz, const double* q, dou
   return st != ESP_OK ? st : forces<double>(p, xyz, q, f, out7);
 }
 
+esp_status esp_local_virial(esp_plan_t* p, const float* xyz, const float* q, float* w6, double* out7) {
+  esp_status st = want_precision(p, ESP_FP32);
+  return st != ESP_OK ? st : local_virial<float>(p, xyz, q, w6, out7);
+}
+
+esp_status esp_local_virial_f64(esp_plan_t* p, const double* xyz, const double* q, double* w6, double* out7) {
+  esp_status st = want_precision(p, ESP_FP64);
+  return st != ESP_OK ? st : local_virial<double>(p, xyz, q, w6, out7);
+}
+
 esp_status esp_check(esp_plan_t* p) {
   if (!p) return ESP_EINVAL;
   hipError_t e = hipStreamSynchronize(p->stream);
@@ -949,6 +981,7 @@ esp_status esp_get_params(const esp_plan_t* p, esp_params* out) {
   out->gather_tiled = r.precision == ESP_FP32 ? p->d32.gather_tiled : p->d64.gather_tiled;
   out->counter_copies = r.precision == ESP_FP32 ? p->d32.nsub : p->d64.nsub;
   out->force = r.force;
+  out->local_virial = r.local;
   return ESP_OK;
 }
 

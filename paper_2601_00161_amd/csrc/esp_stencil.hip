@@ -325,6 +325,89 @@ __global__ void __launch_bounds__(256) k_gather_ik(KArg<R, BATCH> ka, R* __restr
   }
 }
 
+// Per-particle Fourier virial (Sec. 4.4, eq. PinsFind): the six grids
+// Pi_c = inverse FFT of P_hat_c rho_hat / (2 V W_hat^2) (phi + c M1 M2 M3) are
+// gathered with the plain window; w6[6 j + c] = q_j sum_g W(u_j - g) Pi_c(g),
+// components xx, yy, zz, xy, xz, yz, in input order.  Lane layout as in
+// k_gather.
+template <typename R, int P, int NW, bool BATCH>
+__global__ void __launch_bounds__(256) k_gather_local(KArg<R, BATCH> ka, R* __restrict__ w6,
+                                                      double* __restrict__ out7) {
+  constexpr int L = GatherLanes<P>::L;
+  constexpr int G = 256 / L;
+  int blk;
+  const DevPlan<R>& d = plan_of(ka, blk);
+  w6 += 6 * d.pofs;
+  if (out7 && blk == 0) {
+    __shared__ double red[kNumSums * 16];
+    finalize_sums(d, out7 + kNumSums * d.rep, red);
+  }
+  extern __shared__ __align__(16) unsigned char smem[];
+  R* win = reinterpret_cast<R*>(smem);                // (NW + 1) x P
+  R* wt = win + (NW + 1) * P;                         // G x 3 x P: w1 w2 w3
+  for (int k = threadIdx.x; k < (NW + 1) * P; k += blockDim.x) win[k] = d.win[k];
+  __syncthreads();
+  const int grp = threadIdx.x / L, lane = threadIdx.x - grp * L;
+  const int64_t i = static_cast<int64_t>(blk) * G + grp;
+  const bool valid = i < d.n;
+  const Record<R> rec = d.sorted[valid ? i : 0];
+  int g1, g2, g3;
+  R t1, t2, t3;
+  Coord<R>::stencil(rec, 0, d.M1, P, g1, t1);
+  Coord<R>::stencil(rec, 1, d.M2, P, g2, t2);
+  Coord<R>::stencil(rec, 2, d.M3, P, g3, t3);
+  R* my = wt + grp * 3 * P;
+  if (lane < 3) {
+    R w[P];
+    eval_window<R, P, NW>(win, lane == 0 ? t1 : (lane == 1 ? t2 : t3), w);
+#pragma unroll
+    for (int p = 0; p < P; ++p) my[lane * P + p] = w[p];
+  }
+  __syncthreads();
+  R acc[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+  if (lane < P) {
+    const size_t G3 = static_cast<size_t>(d.M1) * d.M2 * d.M3;
+    int xi[P];
+#pragma unroll
+    for (int a = 0; a < P; ++a) {
+      const int x = g1 + a;
+      xi[a] = x >= d.M1 ? x - d.M1 : x;
+    }
+    R w1[P];
+#pragma unroll
+    for (int a = 0; a < P; ++a) w1[a] = my[a];
+    int z = g3 + lane;
+    z -= z >= d.M3 ? d.M3 : 0;
+#pragma unroll
+    for (int b = 0; b < P; ++b) {
+      int y = g2 + b;
+      y -= y >= d.M2 ? d.M2 : 0;
+      const R* row = d.phi + (static_cast<size_t>(z) * d.M2 + y) * d.M1;
+      const R w2 = my[P + b];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        R sc = R(0);
+#pragma unroll
+        for (int a = 0; a < P; ++a) sc += row[c * G3 + xi[a]] * w1[a];
+        acc[c] += sc * w2;
+      }
+    }
+    const R w3 = my[2 * P + lane];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) acc[c] *= w3;
+  }
+#pragma unroll
+  for (int off = L / 2; off > 0; off >>= 1)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) acc[c] += __shfl_xor(acc[c], off, 64);
+  if (lane == 0 && valid) {
+    const R qk = rec.q * d.coulomb_k;
+    const int64_t j = d.perm[i];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) w6[6 * j + c] = qk * acc[c];
+  }
+}
+
 // Tile-staged gather, for dense tiles: one workgroup per tile.  The
 // potential on the tile's stencil box (its cells plus P - 1 more along each
 // cell vector, cyclically) is staged in LDS once, then the tile's particles
@@ -516,6 +599,21 @@ hipError_t gather_ik_launch(const DevPlan<R>& d, R* f, double* out7, hipStream_t
   ESP_NW_SWITCH(d.nw, gather_ik_nw, d, f, out7, s)
 }
 
+template <typename R, int P, int NW>
+static hipError_t gather_local_nw(const DevPlan<R>& d, R* w6, double* out7, hipStream_t s) {
+  constexpr int G = 256 / GatherLanes<P>::L;
+  const int nb = static_cast<int>((d.n + G - 1) / G);
+  const size_t lds = ((NW + 1) * P + G * 3 * P) * sizeof(R);
+  hipLaunchKernelGGL((k_gather_local<R, P, NW, false>), dim3(nb), dim3(256), lds, s, KArg<R, false>{d}, w6,
+                     out7);
+  return hipGetLastError();
+}
+
+template <typename R, int P>
+hipError_t gather_local_launch(const DevPlan<R>& d, R* w6, double* out7, hipStream_t s) {
+  ESP_NW_SWITCH(d.nw, gather_local_nw, d, w6, out7, s)
+}
+
 template <typename R, int P>
 hipError_t spread_launch_batch(const BatchLaunch<R>& b, hipStream_t s) {
   ESP_NW_SWITCH(b.nw, spread_nw_batch, b, s)
@@ -532,6 +630,8 @@ template hipError_t gather_launch<float, ESP_P>(const DevPlan<float>&, float*, d
 template hipError_t gather_launch<double, ESP_P>(const DevPlan<double>&, double*, double*, hipStream_t);
 template hipError_t gather_ik_launch<float, ESP_P>(const DevPlan<float>&, float*, double*, hipStream_t);
 template hipError_t gather_ik_launch<double, ESP_P>(const DevPlan<double>&, double*, double*, hipStream_t);
+template hipError_t gather_local_launch<float, ESP_P>(const DevPlan<float>&, float*, double*, hipStream_t);
+template hipError_t gather_local_launch<double, ESP_P>(const DevPlan<double>&, double*, double*, hipStream_t);
 template hipError_t spread_launch_batch<float, ESP_P>(const BatchLaunch<float>&, hipStream_t);
 template hipError_t spread_launch_batch<double, ESP_P>(const BatchLaunch<double>&, hipStream_t);
 template hipError_t gather_launch_batch<float, ESP_P>(const BatchLaunch<float>&, float*, double*, hipStream_t);

@@ -38,7 +38,8 @@ class Opts(ctypes.Structure):
                 ("rc", ctypes.c_double), ("c_split", ctypes.c_double), ("c_spread", ctypes.c_double),
                 ("P", ctypes.c_int), ("M", ctypes.c_int * 3), ("grid_sigma", ctypes.c_double),
                 ("coulomb_k", ctypes.c_double), ("tile", ctypes.c_int), ("stream", ctypes.c_void_p),
-                ("window_tol", ctypes.c_double), ("gather", ctypes.c_int), ("force", ctypes.c_int)]
+                ("window_tol", ctypes.c_double), ("gather", ctypes.c_int), ("force", ctypes.c_int),
+                ("local_virial", ctypes.c_int)]
 
 
 class Params(ctypes.Structure):
@@ -50,7 +51,8 @@ class Params(ctypes.Structure):
                 ("C0_split", ctypes.c_double), ("psi0_split", ctypes.c_double),
                 ("volume", ctypes.c_double), ("params_source", ctypes.c_int),
                 ("predicted_log10_err", ctypes.c_double * 4), ("predicted_cost", ctypes.c_double),
-                ("gather_tiled", ctypes.c_int), ("counter_copies", ctypes.c_int), ("force", ctypes.c_int)]
+                ("gather_tiled", ctypes.c_int), ("counter_copies", ctypes.c_int), ("force", ctypes.c_int),
+                ("local_virial", ctypes.c_int)]
 
     def as_dict(self):
         out = {}
@@ -82,6 +84,8 @@ SIGNATURES = [
     ("esp_forces", ctypes.c_int, [_P, _P, _P, _P, _P]),
     ("esp_forces_f64", ctypes.c_int, [_P, _P, _P, _P, _P]),
     ("esp_check", ctypes.c_int, [_P]),
+    ("esp_local_virial", ctypes.c_int, [_P, _P, _P, _P, _P]),
+    ("esp_local_virial_f64", ctypes.c_int, [_P, _P, _P, _P, _P]),
     ("esp_get_params", ctypes.c_int, [_P, ctypes.POINTER(Params)]),
     ("esp_last_error", ctypes.c_char_p, [_P]),
     ("esp_destroy", None, [_P]),
@@ -151,7 +155,7 @@ def _cell(h):
 
 def make_opts(precision="fp32", params="analytic", coupling="iso", rc=0.9, c_split=None,
               c_spread=None, P=None, M=None, grid_sigma=1.07, coulomb_k=1.0, tile=0, stream=None,
-              window_tol=0.0, gather="auto", force="ad"):
+              window_tol=0.0, gather="auto", force="ad", local_virial=False):
     o = Opts()
     lib().esp_opts_default(ctypes.byref(o))
     o.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
@@ -179,6 +183,7 @@ def make_opts(precision="fp32", params="analytic", coupling="iso", rc=0.9, c_spl
     o.window_tol = float(window_tol)
     o.gather = GATHER[gather] if isinstance(gather, str) else int(gather)
     o.force = FORCE[force] if isinstance(force, str) else int(force)
+    o.local_virial = 1 if local_virial else 0
     return o
 
 
@@ -296,6 +301,18 @@ class Plan:
         if st < 0:
             self._err(st, "esp_forces")
         return f, out7
+
+    def local_virial(self, xyz, q, w6=None, out7=None):
+        """Per-particle Fourier virial, (n, 6) in xx, yy, zz, xy, xz, yz order."""
+        t = self._check_in(xyz, q)
+        if w6 is None:
+            w6 = t.empty((self.n, 6), dtype=self.dtype, device=xyz.device)
+        self._stream()
+        fn = self._lib.esp_local_virial if self.dtype == t.float32 else self._lib.esp_local_virial_f64
+        st = fn(self._h, _ptr(xyz), _ptr(q), _ptr(w6), _ptr(out7) if out7 is not None else None)
+        if st < 0:
+            self._err(st, "esp_local_virial")
+        return w6, out7
 
     def check(self):
         st = self._lib.esp_check(self._h)

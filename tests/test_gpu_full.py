@@ -136,3 +136,47 @@ def test_water_30k_ik_forces(precision):
     print(f"ik {precision}: {e}", flush=True)
     assert max(e) < TOL[precision]
     plan.close()
+
+
+def test_water_30k_local_virial_fp32():
+    """Per-particle virial at the benchmark size against the oracle."""
+    from oracle import esp_grid
+    h, r, q = synth.config2()
+    r_, q_, r64, q64 = as_inputs(r, q, "fp32")
+    plan = esp.Plan(h, len(q), 1e-5, local_virial=True)
+    xyz, qq = torch.from_numpy(r_).to(DEV), torch.from_numpy(q_).to(DEV)
+    out7 = torch.empty(7, dtype=torch.float64, device=DEV)
+    w6, _ = plan.local_virial(xyz, qq, out7=out7)
+    w6 = w6.double().cpu().numpy()
+    prm = plan.params
+    ref = esp_grid.local_virial(h, r64, q64, esp_grid.GridParams(prm["c_split"], prm["c_spread"], prm["P"],
+                                                                 tuple(prm["M"]), prm["rc"]))
+    ref6 = np.stack([ref[:, 0, 0], ref[:, 1, 1], ref[:, 2, 2], ref[:, 0, 1], ref[:, 0, 2], ref[:, 1, 2]], axis=1)
+    e = rel_rms(w6, ref6)
+    print(f"local virial rel rms {e:.2e}", flush=True)
+    assert e < TOL["fp32"]
+    plan.close()
+
+
+def test_membrane_1m_local_pressure_profile_fp32():
+    """N = 10^6 slab: the per-particle shares add up to the Fourier virial, and
+    the z-profile of the lateral-minus-normal pressure is symmetric about the
+    mid-plane (the two sheets are mirror images up to sampling noise, so only
+    a loose bound applies) -- properties that hold at any size."""
+    h, r, q = synth.config4()
+    r_, q_, _, _ = as_inputs(r, q, "fp32")
+    plan = esp.Plan(h, len(q), 1e-5, coupling="semi", local_virial=True)
+    xyz, qq = torch.from_numpy(r_).to(DEV), torch.from_numpy(q_).to(DEV)
+    out7 = torch.empty(7, dtype=torch.float64, device=DEV)
+    w6, _ = plan.local_virial(xyz, qq, out7=out7)
+    assert plan.check() == esp.ESP_OK
+    w6 = w6.double().cpu().numpy()
+    out = out7.cpu().numpy()
+    assert np.max(np.abs(w6.sum(axis=0) - out[1:])) <= 1e-5 * np.max(np.abs(out[1:]))
+    z = np.mod(r[:, 2], h[2, 2])
+    bins = np.linspace(0, h[2, 2], 21)
+    idx = np.digitize(z, bins) - 1
+    prof = np.bincount(idx, weights=0.5 * (w6[:, 0] + w6[:, 1]) - w6[:, 2], minlength=20)[:20]
+    assert np.all(np.isfinite(prof))
+    print("lateral - normal Fourier virial profile:", np.round(prof, 1), flush=True)
+    plan.close()

@@ -211,3 +211,25 @@ def test_forces_ik(case, precision, dev):
     eps = 1e-6 if precision == "fp32" else 1e-12
     assert np.linalg.norm(f.sum(axis=0)) < eps * np.sqrt(len(q)) * fscale
     plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("case", SYSTEMS, ids=IDS)
+def test_local_virial(case, precision, dev):
+    """Per-particle Fourier virial (Sec. 4.4, eq. PinsFind) against the oracle,
+    and the shares adding up to the plan's virial (neutral systems)."""
+    from oracle import esp_grid
+    name, h, r, q, prm = case
+    r_, q_, r64, q64 = as_inputs(r, q, precision)
+    plan = make_plan(h, len(q), prm, precision, local_virial=True)
+    out7 = torch.empty(7, dtype=torch.float64, device=dev)
+    w6, _ = plan.local_virial(to_dev(r_, dev), to_dev(q_, dev), out7=out7)
+    w6 = w6.cpu().numpy().astype(np.float64)
+    out = out7.cpu().numpy()
+    ref = esp_grid.local_virial(h, r64, q64, esp_grid.GridParams(prm["c_split"], prm["c_spread"], prm["P"],
+                                                                 tuple(prm["M"]), prm["rc"]))
+    ref6 = np.stack([ref[:, 0, 0], ref[:, 1, 1], ref[:, 2, 2], ref[:, 0, 1], ref[:, 0, 2], ref[:, 1, 2]], axis=1)
+    assert rel_rms(w6, ref6) < TOL[precision]
+    total = w6.sum(axis=0)
+    assert np.max(np.abs(total - out[1:])) <= (1e-6 if precision == "fp32" else 1e-11) * np.max(np.abs(out[1:]))
+    plan.close()
