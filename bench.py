@@ -292,6 +292,22 @@ def main():
     pik = Plan(h, N, args.tol, precision="fp32", params=args.params, force="ik", tile=p32.params["tile"][0])
     dtik, fik, oik = run_plan(pik, x32, c32, args.steps, args.warmup, torch)
 
+    # ---- FP32 per-particle virial (local pressure) ----------------------------------
+    ploc = Plan(h, N, args.tol, precision="fp32", params=args.params, local_virial=True,
+                tile=p32.params["tile"][0])
+    w6, o_loc = ploc.local_virial(x32, c32, out7=torch.empty(7, dtype=torch.float64, device=dev))
+    for _ in range(args.warmup):
+        ploc.local_virial(x32, c32, w6=w6, out7=o_loc)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ploc.local_virial(x32, c32, w6=w6, out7=o_loc)
+    torch.cuda.synchronize()
+    dtloc = time.perf_counter() - t0
+    loc_sum_err = float(np.max(np.abs(w6.double().sum(0).cpu().numpy() - o_loc.cpu().numpy()[1:]))
+                        / np.max(np.abs(o_loc.cpu().numpy()[1:])))
+    ploc.close()
+
     # ---- plain FP64 path, analytic parameters -------------------------------------
     p64, tuned_64 = make_plan("fp64", "analytic", x64, c64)
     dt64, f64, o64 = run_plan(p64, x64, c64, args.steps, args.warmup, torch)
@@ -347,6 +363,8 @@ def main():
         "fp32_analytic": {"value": round(va, 3), "ms_per_step": dta / args.steps * 1e3, **brief(pa)},
         "learned_gain_vs_analytic": value / va,
         "batch_64_replicas": batch,
+        "local_virial_fp32": {"value": round(N * args.steps / dtloc / 1e6, 3), "unit": "M particle-steps/s",
+                              "ms_per_step": dtloc / args.steps * 1e3, "shares_sum_rel_err": loc_sum_err},
         "ik_forces_fp32": {"value": round(N * args.steps / dtik / 1e6, 3), "ms_per_step": dtik / args.steps * 1e3,
                            "net_force_over_rms": float(np.linalg.norm(fik.double().sum(0).cpu().numpy())
                                                        / np.sqrt(np.sum(fik.double().cpu().numpy() ** 2)))},
