@@ -308,9 +308,36 @@ def main():
                         / np.max(np.abs(o_loc.cpu().numpy()[1:])))
     ploc.close()
 
+    # ---- real-space (near) part, and the total Coulomb step (Fourier forces plus
+    # near forces accumulated in place) on the headline plan --------------------------
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    f_near = torch.empty_like(f32)
+    o_near = torch.empty(7, dtype=torch.float64, device=dev)
+    dt_near = timed(lambda: p32.real_space(x32, c32, f=f_near, out7=o_near))
+    f_tot = torch.empty_like(f32)
+    o_tot = torch.empty(7, dtype=torch.float64, device=dev)
+
+    def total_step():
+        p32.forces(x32, c32, f=f_tot, out7=o_tot)
+        p32.real_space(x32, c32, f=f_tot, out7=o_near, accumulate=True)
+    dt_tot = timed(total_step)
+
     # ---- plain FP64 path, analytic parameters -------------------------------------
     p64, tuned_64 = make_plan("fp64", "analytic", x64, c64)
     dt64, f64, o64 = run_plan(p64, x64, c64, args.steps, args.warmup, torch)
+
+    f64_near = torch.empty_like(f64)
+    o64_near = torch.empty(7, dtype=torch.float64, device=dev)
+    dt64_near = timed(lambda: p64.real_space(x64, c64, f=f64_near, out7=o64_near))
 
     batch = None if args.no_batch else batch_throughput(torch, dev)
 
@@ -368,6 +395,13 @@ def main():
         "ik_forces_fp32": {"value": round(N * args.steps / dtik / 1e6, 3), "ms_per_step": dtik / args.steps * 1e3,
                            "net_force_over_rms": float(np.linalg.norm(fik.double().sum(0).cpu().numpy())
                                                        / np.sqrt(np.sum(fik.double().cpu().numpy() ** 2)))},
+        "real_space": {"unit": "M particle-steps/s", "cells": prm["real_cells"], "rc": prm["rc"],
+                       "fp32": {"value": round(N * args.steps / dt_near / 1e6, 3),
+                                "ms_per_step": dt_near / args.steps * 1e3},
+                       "fp64": {"value": round(N * args.steps / dt64_near / 1e6, 3),
+                                "ms_per_step": dt64_near / args.steps * 1e3},
+                       "total_coulomb_fp32": {"value": round(N * args.steps / dt_tot / 1e6, 3),
+                                              "ms_per_step": dt_tot / args.steps * 1e3}},
         **extra,
         "stage_ms_fp32": {k: v[0] / v[1] for k, v in stages.items()},
         "roofline": {"kernel": dominant, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,

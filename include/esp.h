@@ -136,6 +136,8 @@ typedef struct {
   int counter_copies;             /* tile-counter copies used by the cell sort */
   int force;                      /* ESP_FORCE_AD or ESP_FORCE_IK */
   int local_virial;               /* the plan supports esp_local_virial */
+  int real_cells[3];              /* esp_real_space cells per cell vector (current box) */
+  int real_segments;              /* segments of the near-kernel polynomials on [0, rc] */
 } esp_params;
 
 void esp_opts_default(esp_opts *o);
@@ -177,6 +179,25 @@ esp_status esp_forces_f64(esp_plan_t *p, const double *xyz, const double *q, dou
 esp_status esp_local_virial(esp_plan_t *p, const float *xyz, const float *q, float *w6, double *out7);
 esp_status esp_local_virial_f64(esp_plan_t *p, const double *xyz, const double *q, double *w6,
                                 double *out7);
+
+/* Real-space (near) part of the split (Sec. 3.1, eq. UN, eq. PinsN and
+ * eq. Fc with eq. mathFN): over the pairs closer than rc (minimum image),
+ *   out7 = { sum_{i<j} q_i q_j N^c(r_ij),
+ *            W_N = 1/2 sum_{i != j} q_i q_j F_N(r_ij) d_ij d_ij^T / r_ij^3 }
+ * (W_N as xx, yy, zz, xy, xz, yz), and the forces
+ *   f_i = sum_j q_i q_j F_N(r_ij) d_ij / r_ij^3,  d_ij = r_i - r_j,
+ * all times coulomb_k.  Adding out7 to the Fourier part's out7 gives the
+ * total Coulomb energy and virial; with accumulate != 0 the near forces are
+ * added to f (e.g. the Fourier forces of esp_forces), else f is overwritten.
+ * Device pointers: xyz 3n, q n, f 3n, out7 7 doubles.  The cell sort uses
+ * cells of perpendicular width >= rc (the plan's rc, below half the smallest
+ * cell width as esp_plan / esp_set_box require), so each call costs about
+ * 27 n^2 rc^3 / V pair tests.  A non-finite input is flagged for esp_check
+ * and the particle is treated as uncharged at the origin. */
+esp_status esp_real_space(esp_plan_t *p, const float *xyz, const float *q, float *f, int accumulate,
+                          double *out7);
+esp_status esp_real_space_f64(esp_plan_t *p, const double *xyz, const double *q, double *f,
+                              int accumulate, double *out7);
 
 /* Synchronise the plan's stream and report device-side errors
  * (ESP_ENONFINITE) seen since the last check; clears the flag. */
@@ -240,7 +261,7 @@ double esp_c_from_delta(double delta);
  * esp_profile_read: synchronise and return, per stage (ESP_NUM_STAGES
  *   entries, host arrays), the accumulated milliseconds and launch counts
  *   since profiling was enabled. */
-#define ESP_NUM_STAGES 7
+#define ESP_NUM_STAGES 8
 esp_status esp_profile_enable(esp_plan_t *p, unsigned stage_mask, int max_launches, int stride);
 esp_status esp_profile_read(esp_plan_t *p, double *total_ms, int64_t *launches);
 const char *esp_stage_name(int stage);

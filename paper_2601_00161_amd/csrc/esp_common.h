@@ -241,7 +241,11 @@ __device__ void block_sum(double* v, double* red) {
 }
 
 // ----------------------------------------------------------- coordinates
+// The error-free transformations below must not be contracted: a product
+// fused into the subtraction of two_sum would be rounded differently from the
+// product that fed the sum, and its rounding error would be counted twice.
 __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+#pragma clang fp contract(off)
   s = a + b;
   float bb = s - a;
   e = (a - (s - bb)) + (b - bb);
@@ -251,6 +255,7 @@ __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
 // 32-bit fixed point floor(frac(s_d) 2^32).
 __device__ __forceinline__ uint32_t fixed_reduced(const float* hi, const float* lo, float x, float y,
                                                   float z) {
+#pragma clang fp contract(off)
   const float r[3] = {x, y, z};
   float sh = 0.f, sl = 0.f;
 #pragma unroll
@@ -310,6 +315,18 @@ struct Coord<float> {
     const uint32_t S = dim == 0 ? rec.S[0] : (dim == 1 ? rec.S[1] : rec.S[2]);
     stencil_fixed(S, M, P, gm, tau);
   }
+  // real-space cell of s_dim among n equal cells: floor(n S / 2^32), exact
+  __device__ static int cell(const Record<float>& rec, int dim, int n) {
+    const uint32_t S = dim == 0 ? rec.S[0] : (dim == 1 ? rec.S[1] : rec.S[2]);
+    return static_cast<int>((static_cast<unsigned long long>(S) * static_cast<unsigned>(n)) >> 32);
+  }
+  // reduced displacement a - b, minimum image in [-1/2, 1/2): the 32-bit
+  // difference of the fixed-point coordinates wraps by itself
+  __device__ static void disp(const Record<float>& a, const Record<float>& b, float* ds) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      ds[k] = static_cast<float>(static_cast<int>(a.S[k] - b.S[k])) * 2.3283064365386963e-10f;
+  }
 };
 
 template <>
@@ -327,6 +344,17 @@ struct Coord<double> {
   __device__ static void stencil(const Record<double>& rec, int dim, int M, int P, int& gm, double& tau) {
     const double sd = dim == 0 ? rec.s[0] : (dim == 1 ? rec.s[1] : rec.s[2]);
     stencil_f64(sd, M, P, gm, tau);
+  }
+  __device__ static int cell(const Record<double>& rec, int dim, int n) {
+    const double sd = dim == 0 ? rec.s[0] : (dim == 1 ? rec.s[1] : rec.s[2]);
+    return min(n - 1, static_cast<int>(sd * n));
+  }
+  __device__ static void disp(const Record<double>& a, const Record<double>& b, double* ds) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double v = a.s[k] - b.s[k];
+      ds[k] = v - rint(v);
+    }
   }
 };
 

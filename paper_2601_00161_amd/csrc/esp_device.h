@@ -108,11 +108,26 @@ struct DevPlan {
   int local;                       // per-particle virial enabled (6 field components)
   int ncomp;                       // spectra / real grids allocated (1, 3 or 6)
   int nsub;                        // tile counters per tile: binning block b uses copy b % nsub
+  int cellsort;                    // binning keys are real-space cells (cn1 x cn2 x cn3), not tiles
   int* sbase;                      // nsub > 1: nsub x ntiles first rank of each copy in its tile
   FinalConsts fin;                 // final-sum constants (updated by esp_set_box)
+  // real-space (near) part: cells of perpendicular width >= rc along the cell vectors
+  int cn1, cn2, cn3;               // cells per dimension (current box)
+  int nrs;                         // segments of the near-kernel polynomials on x = r / rc in [0, 1]
+  const R* rsN;                    // nrs x 2 x (kRealDeg + 1) monomial coefficients in the segment's
+                                   // local t = nrs x - s - 1/2: first 1 - phi0(x), then
+                                   // F_N(x) = 1 - phi0(x) + x psi(x) / C0 (eq. mathFN)
+  R hmat[9];                       // h, row major: d = h ds
+  R rc2, inv_rc;
+  double* rpart;                   // cells x 7 partial sums of the near energy and virial
   int64_t pofs;                    // batched launches: first particle of this plan in the
   int rep;                         // concatenated inputs, and its index (0 for single plans)
 };
+
+// Degree of the near-kernel segment polynomials (FP32 / FP64 path).
+template <typename R>
+inline constexpr int kRealDeg = sizeof(R) == 8 ? 9 : 5;
+constexpr int kMaxCells = 32768;   // real-space cells (the scatter pass keeps their offsets in LDS)
 
 // Lanes per particle of the gather kernel (a power of two >= P).
 constexpr int gather_lanes(int P) { return P <= 4 ? 4 : (P <= 8 ? 8 : 16); }
@@ -200,6 +215,17 @@ template <typename R>
 hipError_t launch_finalize_batch(const BatchLaunch<R>& b, double* out7, hipStream_t s);
 template <typename T>
 hipError_t launch_fill(T* p, size_t count, hipStream_t s);
+
+// Real-space part (one workgroup per cell, after a cell sort with cellsort set):
+// f receives (accumulate) or is overwritten with the near forces in input
+// order; the partial sums go to rpart, which launch_real_finalize turns into
+// out7 = {U_N, W_N}.
+template <typename R>
+hipError_t launch_real_pairs(const DevPlan<R>& d, R* f, int accumulate, hipStream_t s);
+template <typename R>
+hipError_t launch_real_finalize(const DevPlan<R>& d, double* out7, hipStream_t s);
+template <typename R>
+size_t lds_real(const DevPlan<R>& d);
 
 // LDS bytes the kernels need for a plan (the host checks them against the
 // device limit before any launch).

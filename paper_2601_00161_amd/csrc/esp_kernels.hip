@@ -80,12 +80,17 @@ __global__ void __launch_bounds__(256) k_bin(KArg<R, BATCH> ka, const R* __restr
     Record<R> rec;
     Coord<R>::make(d, x, y, z, qi, rec);
     d.tmp[i] = rec;
-    int g1, g2, g3;
-    R t;
-    Coord<R>::stencil(rec, 0, d.M1, d.P, g1, t);
-    Coord<R>::stencil(rec, 1, d.M2, d.P, g2, t);
-    Coord<R>::stencil(rec, 2, d.M3, d.P, g3, t);
-    key = ((g3 / d.T3) * d.nt2 + g2 / d.T2) * d.nt1 + g1 / d.T1;
+    if (d.cellsort) {
+      key = (Coord<R>::cell(rec, 2, d.cn3) * d.cn2 + Coord<R>::cell(rec, 1, d.cn2)) * d.cn1 +
+            Coord<R>::cell(rec, 0, d.cn1);
+    } else {
+      int g1, g2, g3;
+      R t;
+      Coord<R>::stencil(rec, 0, d.M1, d.P, g1, t);
+      Coord<R>::stencil(rec, 1, d.M2, d.P, g2, t);
+      Coord<R>::stencil(rec, 2, d.M3, d.P, g3, t);
+      key = ((g3 / d.T3) * d.nt2 + g2 / d.T2) * d.nt1 + g1 / d.T1;
+    }
     lr = lh ? atomicAdd(hist + key, 1)
             : atomicAdd(d.counts + static_cast<size_t>(blk % d.nsub) * d.ntiles + key, 1);
     v[0] = static_cast<double>(qi);

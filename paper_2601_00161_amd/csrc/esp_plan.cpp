@@ -368,8 +368,9 @@ void factor(int n, FftLen& f) {
 
 }  // namespace
 
-enum StageId { ST_BIN, ST_SCATTER, ST_SPREAD, ST_FFT_XY, ST_FFT_Z, ST_FFT_XY_INV, ST_GATHER, ST_COUNT };
-const char* kStageNames[ST_COUNT] = {"bin", "scatter", "spread", "fft_xy", "fft_z", "fft_xy_inv", "gather"};
+enum StageId { ST_BIN, ST_SCATTER, ST_SPREAD, ST_FFT_XY, ST_FFT_Z, ST_FFT_XY_INV, ST_GATHER, ST_REAL, ST_COUNT };
+const char* kStageNames[ST_COUNT] = {"bin", "scatter", "spread", "fft_xy", "fft_z", "fft_xy_inv", "gather",
+                                     "real"};
 
 // Optional per-stage timing with HIP events recorded on the plan's stream.
 struct Profiler {
@@ -393,7 +394,7 @@ struct esp_plan_s {
   Resolved r;
   Profiler prof;
   std::unique_ptr<Pswf> split, spread;
-  int nw = 0, nw_fitted = 0, nker = 0;
+  int nw = 0, nw_fitted = 0, nker = 0, nseg = 0;
   double A = 0, self_coef = 0, Ic = 0;
   hipStream_t stream = nullptr;
   std::vector<void*> allocs;
@@ -455,6 +456,21 @@ void set_box_fields(esp_plan_t* p, DevPlan<R>& d) {
     }
   d.inv_vol = static_cast<R>(1.0 / r.V);
   d.fin = final_consts(p);
+  // real-space cells: floor(w_d / rc) per dimension (at least 2, since rc is
+  // below half of every width), merged along the most divided dimension while
+  // there are more than kMaxCells
+  int cn[3];
+  for (int k = 0; k < 3; ++k) cn[k] = std::max(2, static_cast<int>(perp_width(r.h, k, r.V) / r.rc));
+  while (static_cast<int64_t>(cn[0]) * cn[1] * cn[2] > kMaxCells) {
+    const int k = cn[0] >= cn[1] && cn[0] >= cn[2] ? 0 : (cn[1] >= cn[2] ? 1 : 2);
+    --cn[k];
+  }
+  d.cn1 = cn[0];
+  d.cn2 = cn[1];
+  d.cn3 = cn[2];
+  for (int i = 0; i < 9; ++i) d.hmat[i] = static_cast<R>(r.h[i]);
+  d.rc2 = static_cast<R>(r.rc * r.rc);
+  d.inv_rc = static_cast<R>(1.0 / r.rc);
 }
 
 // Per-subinterval window polynomials (Sec. 4.3): polynomial p approximates
@@ -528,6 +544,39 @@ int fit_kernel(esp_plan_t* p, std::vector<double>& cf, std::vector<double>& cg) 
     if (err <= 1e-13 * ps.psi0()) return deg;
   }
   return kMaxKerDeg;
+}
+
+// Near-part split functions (Sec. 3.1, eq. UN and eq. mathFN) of x = r / rc
+// as piecewise polynomials of degree kRealDeg on nseg equal segments of
+// [0, 1]: the fewest segments (a power of two) whose fits stay within eps of
+// both functions; layout seg x {1 - phi0, F_N} x (deg + 1) coefficients of
+// t = nseg x - seg - 1/2 in [-1/2, 1/2].
+int fit_near(esp_plan_t* p, int deg, double eps, int max_seg, std::vector<double>& coef) {
+  const Pswf& ps = *p->split;
+  const double C0 = ps.C0();
+  auto gN = [&](double x) { return 1.0 - ps.int_psi(x) / C0; };
+  auto gF = [&](double x) { return 1.0 - ps.int_psi(x) / C0 + x * ps.psi(x) / C0; };
+  int nseg = 8;
+  for (;; nseg *= 2) {
+    coef.assign(static_cast<size_t>(nseg) * 2 * (deg + 1), 0.0);
+    double err = 0;
+    for (int sgm = 0; sgm < nseg && (err <= eps || nseg >= max_seg); ++sgm)
+      for (int fn = 0; fn < 2; ++fn) {
+        auto g = [&](double t) {
+          const double x = std::min(1.0, std::max(0.0, (sgm + 0.5 + t) / nseg));
+          return fn == 0 ? gN(x) : gF(x);
+        };
+        const std::vector<double> m = fit_monomial(g, -0.5, 0.5, deg);
+        for (int k = 0; k <= deg; ++k) coef[(static_cast<size_t>(sgm) * 2 + fn) * (deg + 1) + k] = m[k];
+        for (int s2 = 0; s2 <= 16; ++s2) {
+          const double t = -0.5 + s2 / 16.0;
+          double v = 0;
+          for (int k = deg; k >= 0; --k) v = v * t + m[k];
+          err = std::max(err, std::fabs(v - g(t)));
+        }
+      }
+    if (err <= eps || nseg >= max_seg) return nseg;
+  }
 }
 
 template <typename R>
@@ -604,8 +653,13 @@ esp_status build_device(esp_plan_t* p) {
     while (tab.size() % 4) tab.push_back(R(0));
     return off;
   };
+  std::vector<double> near;
+  int max_seg = 8;                  // segment tables of at most 40 KiB of LDS
+  while (2 * max_seg * 2 * (kRealDeg<R> + 1) * static_cast<int>(sizeof(R)) <= 40 * 1024) max_seg *= 2;
+  p->nseg = fit_near(p, kRealDeg<R>, r.precision == ESP_FP32 ? 2e-8 : 1e-14, max_seg, near);
+  d.nrs = p->nseg;
   const size_t o_win = push(win), o_kf = push(cf), o_kg = push(cg);
-  const size_t o_i1 = push(iw[0]), o_i2 = push(iw[1]), o_i3 = push(iw[2]);
+  const size_t o_i1 = push(iw[0]), o_i2 = push(iw[1]), o_i3 = push(iw[2]), o_near = push(near);
   R* dtab;
   Cplx<R>* dtw;
   esp_status st;
@@ -620,6 +674,7 @@ esp_status build_device(esp_plan_t* p) {
   d.iw1 = dtab + o_i1;
   d.iw2 = dtab + o_i2;
   d.iw3 = dtab + o_i3;
+  d.rsN = dtab + o_near;
   d.tw = dtw;
 
   // ---- LDS limits --------------------------------------------------------
@@ -645,9 +700,11 @@ esp_status build_device(esp_plan_t* p) {
     const double per = static_cast<double>(d.nbin) * std::min(256, r.ntiles) / r.ntiles;
     d.nsub = std::max(1, std::min(kMaxCounterCopies, static_cast<int>(std::ceil(per / kBinContention))));
   }
-  const size_t ncount = static_cast<size_t>(r.ntiles) * d.nsub;
+  // the counters and offsets also serve the real-space cell sort (at most kMaxCells cells)
+  const size_t ncount = std::max(static_cast<size_t>(r.ntiles) * d.nsub, static_cast<size_t>(kMaxCells));
   if ((st = dalloc(p, &d.counts, ncount)) || (st = dalloc(p, &d.sbase, d.nsub > 1 ? ncount : 1)) ||
-      (st = dalloc(p, &d.offsets, r.ntiles + 1)) ||
+      (st = dalloc(p, &d.offsets, std::max(r.ntiles, kMaxCells) + 1)) ||
+      (st = dalloc(p, &d.rpart, static_cast<size_t>(kMaxCells) * kNumSums)) ||
       (st = dalloc(p, &d.keys, r.n)) || (st = dalloc(p, &d.ranks, r.n)) || (st = dalloc(p, &d.perm, r.n)) ||
       (st = dalloc(p, &d.tmp, r.n)) || (st = dalloc(p, &d.sorted, r.n)) || (st = dalloc(p, &d.rho, G)) ||
       (st = dalloc(p, &d.spec, S * d.ncomp)) || (st = dalloc(p, &d.phi, G * d.ncomp)) ||
@@ -765,6 +822,30 @@ esp_status local_virial(esp_plan_t* p, const R* xyz, const R* q, R* w6, double* 
   esp_status st = potential(p, xyz, q, Z_LOCAL);
   if (st != ESP_OK) return st;
   hipError_t e = stage(p, ST_GATHER, [&] { return launch_gather_local(d, w6, out7, p->stream); });
+  return e == hipSuccess ? ESP_OK : hip_fail(p, e, "kernel launch");
+}
+
+// Real-space part: cell sort with the real-space cells, the pair kernel and
+// the final sums.  Shares the sort buffers with the reciprocal path (each
+// call sorts again); the pair kernel clears the cell counters.
+template <typename R>
+esp_status real_space(esp_plan_t* p, const R* xyz, const R* q, R* f, int accumulate, double* out7) {
+  if (!xyz || !q || !f || !out7) {
+    p->err = "null pointer argument";
+    return ESP_EINVAL;
+  }
+  DevPlan<R> c = dev<R>(p);
+  c.cellsort = 1;
+  c.ntiles = c.cn1 * c.cn2 * c.cn3;
+  c.nsub = 1;
+  c.bin_lds = c.ntiles <= 8192 ? 1 : 0;
+  hipError_t e = stage(p, ST_REAL, [&] {
+    hipError_t eb = launch_bin(c, xyz, q, p->stream);
+    if (eb == hipSuccess) eb = launch_scatter(c, p->stream);
+    if (eb == hipSuccess) eb = launch_real_pairs(c, f, accumulate, p->stream);
+    if (eb == hipSuccess) eb = launch_real_finalize(c, out7, p->stream);
+    return eb;
+  });
   return e == hipSuccess ? ESP_OK : hip_fail(p, e, "kernel launch");
 }
 
@@ -932,6 +1013,18 @@ esp_status esp_local_virial_f64(esp_plan_t* p, const double* xyz, const double* 
   return st != ESP_OK ? st : local_virial<double>(p, xyz, q, w6, out7);
 }
 
+esp_status esp_real_space(esp_plan_t* p, const float* xyz, const float* q, float* f, int accumulate,
+                          double* out7) {
+  esp_status st = want_precision(p, ESP_FP32);
+  return st != ESP_OK ? st : real_space<float>(p, xyz, q, f, accumulate, out7);
+}
+
+esp_status esp_real_space_f64(esp_plan_t* p, const double* xyz, const double* q, double* f, int accumulate,
+                              double* out7) {
+  esp_status st = want_precision(p, ESP_FP64);
+  return st != ESP_OK ? st : real_space<double>(p, xyz, q, f, accumulate, out7);
+}
+
 esp_status esp_check(esp_plan_t* p) {
   if (!p) return ESP_EINVAL;
   hipError_t e = hipStreamSynchronize(p->stream);
@@ -982,6 +1075,13 @@ esp_status esp_get_params(const esp_plan_t* p, esp_params* out) {
   out->counter_copies = r.precision == ESP_FP32 ? p->d32.nsub : p->d64.nsub;
   out->force = r.force;
   out->local_virial = r.local;
+  {
+    const bool f32 = r.precision == ESP_FP32;
+    out->real_cells[0] = f32 ? p->d32.cn1 : p->d64.cn1;
+    out->real_cells[1] = f32 ? p->d32.cn2 : p->d64.cn2;
+    out->real_cells[2] = f32 ? p->d32.cn3 : p->d64.cn3;
+    out->real_segments = p->nseg;
+  }
   return ESP_OK;
 }
 

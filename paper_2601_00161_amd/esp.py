@@ -52,7 +52,8 @@ class Params(ctypes.Structure):
                 ("volume", ctypes.c_double), ("params_source", ctypes.c_int),
                 ("predicted_log10_err", ctypes.c_double * 4), ("predicted_cost", ctypes.c_double),
                 ("gather_tiled", ctypes.c_int), ("counter_copies", ctypes.c_int), ("force", ctypes.c_int),
-                ("local_virial", ctypes.c_int)]
+                ("local_virial", ctypes.c_int), ("real_cells", ctypes.c_int * 3),
+                ("real_segments", ctypes.c_int)]
 
     def as_dict(self):
         out = {}
@@ -86,6 +87,8 @@ SIGNATURES = [
     ("esp_check", ctypes.c_int, [_P]),
     ("esp_local_virial", ctypes.c_int, [_P, _P, _P, _P, _P]),
     ("esp_local_virial_f64", ctypes.c_int, [_P, _P, _P, _P, _P]),
+    ("esp_real_space", ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, _P]),
+    ("esp_real_space_f64", ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, _P]),
     ("esp_get_params", ctypes.c_int, [_P, ctypes.POINTER(Params)]),
     ("esp_last_error", ctypes.c_char_p, [_P]),
     ("esp_destroy", None, [_P]),
@@ -127,7 +130,7 @@ SIGNATURES = [
     ("esp_batch_destroy", None, [_P]),
     ("esp_version", ctypes.c_char_p, []),
 ]
-NUM_STAGES = 7
+NUM_STAGES = 8
 
 _lib_handle = None
 
@@ -276,6 +279,9 @@ class Plan:
         st = self._lib.esp_set_box(self._h, hp)
         if st < 0:
             self._err(st, "esp_set_box")
+        prm = Params()
+        self._lib.esp_get_params(self._h, ctypes.byref(prm))
+        self.params = prm.as_dict()
         return st
 
     def energy_virial(self, xyz, q, out7=None):
@@ -313,6 +319,23 @@ class Plan:
         if st < 0:
             self._err(st, "esp_local_virial")
         return w6, out7
+
+    def real_space(self, xyz, q, f=None, out7=None, accumulate=False):
+        """Near part over pairs within rc: forces (n, 3) (added to f when
+        accumulate) and out7 = (U_N, W_N) in the Fourier part's layout."""
+        t = self._check_in(xyz, q)
+        if f is None:
+            if accumulate:
+                raise ValueError("accumulate needs an f to add to")
+            f = t.empty((self.n, 3), dtype=self.dtype, device=xyz.device)
+        if out7 is None:
+            out7 = t.empty(7, dtype=t.float64, device=xyz.device)
+        self._stream()
+        fn = self._lib.esp_real_space if self.dtype == t.float32 else self._lib.esp_real_space_f64
+        st = fn(self._h, _ptr(xyz), _ptr(q), _ptr(f), 1 if accumulate else 0, _ptr(out7))
+        if st < 0:
+            self._err(st, "esp_real_space")
+        return f, out7
 
     def check(self):
         st = self._lib.esp_check(self._h)
