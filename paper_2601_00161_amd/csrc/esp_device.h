@@ -119,7 +119,9 @@ struct DevPlan {
                                    // F_N(x) = 1 - phi0(x) + x psi(x) / C0 (eq. mathFN)
   R hmat[9];                       // h, row major: d = h ds
   R rc2, inv_rc;
-  double* rpart;                   // cells x 7 partial sums of the near energy and virial
+  int rsplit;                      // workgroups per cell, each with a share of the candidates
+  R* fpart;                        // rsplit x n x 3 near-force shares (sorted order)
+  double* rpart;                   // cells x rsplit x 7 partial sums of the near energy and virial
   int64_t pofs;                    // batched launches: first particle of this plan in the
   int rep;                         // concatenated inputs, and its index (0 for single plans)
 };
@@ -128,6 +130,8 @@ struct DevPlan {
 template <typename R>
 inline constexpr int kRealDeg = sizeof(R) == 8 ? 9 : 5;
 constexpr int kMaxCells = 32768;   // real-space cells (the scatter pass keeps their offsets in LDS)
+constexpr int kMaxRealSplit = 8;   // workgroups per real-space cell
+constexpr int kRealBlocks = 2048;  // target workgroups of the pair kernel (rsplit up to kMaxRealSplit)
 
 // Lanes per particle of the gather kernel (a power of two >= P).
 constexpr int gather_lanes(int P) { return P <= 4 ? 4 : (P <= 8 ? 8 : 16); }

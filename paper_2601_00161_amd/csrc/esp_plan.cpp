@@ -704,7 +704,8 @@ esp_status build_device(esp_plan_t* p) {
   const size_t ncount = std::max(static_cast<size_t>(r.ntiles) * d.nsub, static_cast<size_t>(kMaxCells));
   if ((st = dalloc(p, &d.counts, ncount)) || (st = dalloc(p, &d.sbase, d.nsub > 1 ? ncount : 1)) ||
       (st = dalloc(p, &d.offsets, std::max(r.ntiles, kMaxCells) + 1)) ||
-      (st = dalloc(p, &d.rpart, static_cast<size_t>(kMaxCells) * kNumSums)) ||
+      (st = dalloc(p, &d.rpart, static_cast<size_t>(std::max(kMaxCells, 2 * kRealBlocks)) * kNumSums)) ||
+      (st = dalloc(p, &d.fpart, static_cast<size_t>(kMaxRealSplit) * r.n * 3)) ||
       (st = dalloc(p, &d.keys, r.n)) || (st = dalloc(p, &d.ranks, r.n)) || (st = dalloc(p, &d.perm, r.n)) ||
       (st = dalloc(p, &d.tmp, r.n)) || (st = dalloc(p, &d.sorted, r.n)) || (st = dalloc(p, &d.rho, G)) ||
       (st = dalloc(p, &d.spec, S * d.ncomp)) || (st = dalloc(p, &d.phi, G * d.ncomp)) ||
@@ -839,6 +840,8 @@ esp_status real_space(esp_plan_t* p, const R* xyz, const R* q, R* f, int accumul
   c.ntiles = c.cn1 * c.cn2 * c.cn3;
   c.nsub = 1;
   c.bin_lds = c.ntiles <= 8192 ? 1 : 0;
+  // enough workgroups to fill the chip: rsplit x cells <= max(cells, 2 kRealBlocks)
+  c.rsplit = std::max(1, std::min(kMaxRealSplit, (kRealBlocks + c.ntiles / 2) / c.ntiles));
   hipError_t e = stage(p, ST_REAL, [&] {
     hipError_t eb = launch_bin(c, xyz, q, p->stream);
     if (eb == hipSuccess) eb = launch_scatter(c, p->stream);

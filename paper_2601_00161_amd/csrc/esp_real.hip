@@ -5,13 +5,16 @@
 // and, with rc below half the smallest width, its separation is the minimum
 // image in reduced coordinates.
 //
-// One workgroup of 256 threads per home cell.  The candidates (the particles
-// of the distinct neighbouring cells, the home cell included) are staged
-// through LDS in chunks; thread t works on home particle t % HC against every
-// (256 / HC)-th candidate, HC in {16, 32, 64} chosen per cell to waste the
-// fewest lanes, and the partial forces of a home particle are summed over its
-// thread group in LDS.  Every ordered pair is visited once, so the forces need
-// no atomics; energy and virial take the factor 1/2 at the end.  The split
+// Workgroups of 256 threads: rsplit per home cell, each taking an equal share
+// of the cell's candidate list (the particles of the distinct neighbouring
+// cells, the home cell included), so that small systems still fill the chip.
+// Candidates are staged through LDS in chunks; thread t works on home
+// particle t % HC against every (256 / HC)-th candidate, HC in {16, 32, 64}
+// chosen per cell to waste the fewest lanes, and the partial forces of a home
+// particle are summed over its thread group in LDS and stored per share; a
+// second kernel adds the shares in a fixed order.  Every ordered pair is
+// visited once, so no atomics are needed and the results are reproducible;
+// energy and virial take the factor 1/2 at the end.  The split
 // functions of x = r / rc, 1 - phi0(x) (N^c = that / r) and
 // F_N(x) = 1 - phi0(x) + x psi(x) / C0 (pair force q_i q_j F_N d / r^3), are
 // piecewise polynomials on nseg equal segments of [0, 1].
@@ -24,6 +27,11 @@ namespace espx {
 constexpr int kRealThreads = 256;
 constexpr int kRealStage = 1024;     // candidate records staged per round
 
+// 1 / sqrt(x): the hardware reciprocal square root (1 ulp) in FP32, the
+// correctly rounded quotient in FP64.
+__device__ __forceinline__ float inv_sqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double inv_sqrt(double x) { return 1.0 / sqrt(x); }
+
 template <typename R, int NC>
 __device__ __forceinline__ R horner(const R* __restrict__ c, R t) {
   R v = c[NC - 1];
@@ -33,49 +41,57 @@ __device__ __forceinline__ R horner(const R* __restrict__ c, R t) {
 }
 
 template <typename R>
-__global__ void __launch_bounds__(kRealThreads) k_real_pairs(DevPlan<R> d, R* __restrict__ f, int accumulate) {
+__global__ void __launch_bounds__(kRealThreads) k_real_pairs(DevPlan<R> d) {
   constexpr int NC = kRealDeg<R> + 1;
   __shared__ Record<R> stage[kRealStage];
-  __shared__ R fred[3 * kRealThreads];
+  __shared__ Record<R> home[kRealThreads];       // each thread's home particle
+  __shared__ double fsh[3 * kRealThreads];       // each thread's home-particle force (FP64: the
+                                                 // LDS float add is slow on this chip)
+  __shared__ int wqueue[2 * kRealThreads];       // per wave: pairs within rc awaiting evaluation
   __shared__ double red[kNumSums * 16];
-  __shared__ int nstart[27], ncum[28], nnb;
+  __shared__ int nstart[27], ncnt[27], ncum[28];
   extern __shared__ __align__(16) unsigned char smem[];
   R* tab = reinterpret_cast<R*>(smem);          // nseg x {N, F} x NC coefficients
-  const int cell = blockIdx.x, tid = threadIdx.x;
+  const int ncells = d.cn1 * d.cn2 * d.cn3;
+  const int cell = blockIdx.x % ncells, ks = blockIdx.x / ncells, tid = threadIdx.x;
   const int nseg = d.nrs;
   for (int k = tid; k < nseg * 2 * NC; k += kRealThreads) tab[k] = d.rsN[k];
-  if (tid == 0) {
-    // distinct neighbour cells (27, fewer along dimensions with 2 cells)
-    const int n[3] = {d.cn1, d.cn2, d.cn3};
-    const int c[3] = {cell % d.cn1, (cell / d.cn1) % d.cn2, cell / (d.cn1 * d.cn2)};
-    int nb[3][3], cnt[3];
-    for (int a = 0; a < 3; ++a) {
-      cnt[a] = 0;
-      for (int o = -1; o <= 1; ++o) {
-        const int v = (c[a] + o + n[a]) % n[a];
-        bool seen = false;
-        for (int j = 0; j < cnt[a]; ++j) seen = seen || nb[a][j] == v;
-        if (!seen) nb[a][cnt[a]++] = v;
+  {
+    // neighbour cell at offset (o1, o2, o3) in {-1, 0, 1}^3; along a dimension
+    // with only 2 cells the offsets -1 and +1 name the same cell, so -1 is
+    // left out (its slot stays empty)
+    if (tid < 27) {
+      const int o1 = tid % 3 - 1, o2 = (tid / 3) % 3 - 1, o3 = tid / 9 - 1;
+      const bool ok = (d.cn1 > 2 || o1 >= 0) && (d.cn2 > 2 || o2 >= 0) && (d.cn3 > 2 || o3 >= 0);
+      int st = 0, en = 0;
+      if (ok) {
+        const int c1 = (cell % d.cn1 + o1 + d.cn1) % d.cn1;
+        const int c2 = ((cell / d.cn1) % d.cn2 + o2 + d.cn2) % d.cn2;
+        const int c3 = (cell / (d.cn1 * d.cn2) + o3 + d.cn3) % d.cn3;
+        const int nc = (c3 * d.cn2 + c2) * d.cn1 + c1;
+        st = d.offsets[nc];
+        en = d.offsets[nc + 1];
       }
+      nstart[tid] = st;
+      ncnt[tid] = en - st;
     }
-    int m = 0, run = 0;
-    for (int z = 0; z < cnt[2]; ++z)
-      for (int y = 0; y < cnt[1]; ++y)
-        for (int x = 0; x < cnt[0]; ++x) {
-          const int nc = (nb[2][z] * d.cn2 + nb[1][y]) * d.cn1 + nb[0][x];
-          const int s = d.offsets[nc], e = d.offsets[nc + 1];
-          nstart[m] = s;
-          ncum[m] = run;
-          run += e - s;
-          ++m;
-        }
-    ncum[m] = run;
-    nnb = m;
-    d.counts[cell] = 0;                         // ready for the next binning pass
+    __syncthreads();
+    if (tid == 0) {
+      int run = 0;
+      for (int m = 0; m < 27; ++m) {
+        ncum[m] = run;
+        run += ncnt[m];
+      }
+      ncum[27] = run;
+      if (ks == 0) d.counts[cell] = 0;          // ready for the next binning pass
+    }
   }
   __syncthreads();
   const int hs = d.offsets[cell], he = d.offsets[cell + 1], nh = he - hs;
-  const int total = ncum[nnb];
+  // this block's share of the candidate list
+  const int total = ncum[27];
+  const int clo = static_cast<int>(static_cast<int64_t>(total) * ks / d.rsplit);
+  const int chi = static_cast<int>(static_cast<int64_t>(total) * (ks + 1) / d.rsplit);
   // home-particle group size with the fewest idle lanes (ties: the larger)
   int HC = 64;
   {
@@ -90,17 +106,60 @@ __global__ void __launch_bounds__(kRealThreads) k_real_pairs(DevPlan<R> d, R* __
   }
   const int G = kRealThreads / HC, hi = tid % HC, g = tid / HC;
   const R nsegr = static_cast<R>(nseg);
+  R* fpart = d.fpart + static_cast<size_t>(ks) * d.n * 3;
+  const int lane = tid & 63, wbase = tid & ~63;
+  int* queue = wqueue + 2 * wbase;              // this wave's 128 entries
   double part[kNumSums];
 #pragma unroll
   for (int k = 0; k < kNumSums; ++k) part[k] = 0.0;
+  // energy and virial of the pairs this lane evaluates, folded into FP64 per chunk
+  R u = R(0), w0 = R(0), w1 = R(0), w2 = R(0), w3 = R(0), w4 = R(0), w5 = R(0);
+  // Evaluate queue entries [0, cnt) of this wave, one per lane (cnt <= 64):
+  // entry = (lane of the home particle << 16) | candidate slot.
+  auto evaluate = [&](int cnt) {
+    if (lane < cnt) {
+      const int e = queue[lane];
+      const int src = wbase + (e >> 16);
+      const Record<R> ri = home[src];
+      const Record<R> rj = stage[e & 0xffff];
+      R ds[3];
+      Coord<R>::disp(ri, rj, ds);
+      const R dx = d.hmat[0] * ds[0] + d.hmat[1] * ds[1] + d.hmat[2] * ds[2];
+      const R dy = d.hmat[3] * ds[0] + d.hmat[4] * ds[1] + d.hmat[5] * ds[2];
+      const R dz = d.hmat[6] * ds[0] + d.hmat[7] * ds[1] + d.hmat[8] * ds[2];
+      const R r2 = dx * dx + dy * dy + dz * dz;
+      const R ir = inv_sqrt(r2);
+      const R xs = r2 * ir * d.inv_rc * nsegr;
+      const int sg = min(nseg - 1, static_cast<int>(xs));
+      const R t = xs - static_cast<R>(sg) - R(0.5);
+      const R* cf = tab + sg * 2 * NC;
+      const R qq = ri.q * rj.q;
+      const R gn = horner<R, NC>(cf, t), gf = horner<R, NC>(cf + NC, t);
+      const R fw = qq * gf * ir * ir * ir;
+      const R wx = fw * dx, wy = fw * dy, wz = fw * dz;
+      atomicAdd(fsh + 3 * src + 0, static_cast<double>(wx));
+      atomicAdd(fsh + 3 * src + 1, static_cast<double>(wy));
+      atomicAdd(fsh + 3 * src + 2, static_cast<double>(wz));
+      u += qq * gn * ir;
+      w0 += wx * dx;
+      w1 += wy * dy;
+      w2 += wz * dz;
+      w3 += wx * dy;
+      w4 += wx * dz;
+      w5 += wy * dz;
+    }
+  };
   for (int h0 = hs; h0 < he; h0 += HC) {
     const int i = h0 + hi;
     const bool own = i < he;
     const Record<R> ri = d.sorted[own ? i : hs];
-    R fx = R(0), fy = R(0), fz = R(0);
-    for (int c0 = 0; c0 < total; c0 += kRealStage) {
-      const int nc = min(kRealStage, total - c0);
-      __syncthreads();                          // previous chunk consumed
+    home[tid] = ri;
+    fsh[3 * tid + 0] = 0.0;
+    fsh[3 * tid + 1] = 0.0;
+    fsh[3 * tid + 2] = 0.0;
+    for (int c0 = clo; c0 < chi; c0 += kRealStage) {
+      const int nc = min(kRealStage, chi - c0);
+      __syncthreads();                          // previous chunk consumed; home and fsh set
       for (int k = tid; k < nc; k += kRealThreads) {
         const int cand = c0 + k;
         int m = 0;
@@ -108,8 +167,15 @@ __global__ void __launch_bounds__(kRealThreads) k_real_pairs(DevPlan<R> d, R* __
         stage[k] = d.sorted[nstart[m] + cand - ncum[m]];
       }
       __syncthreads();
-      if (own) {
-        for (int jj = g; jj < nc; jj += G) {
+      // test phase: every lane takes the same number of steps, so the wave
+      // stays converged; pairs within rc are appended to the wave's queue and
+      // evaluated 64 at a time
+      int count = 0;
+      const int steps = (nc + G - 1) / G;
+      for (int st = 0; st < steps; ++st) {
+        const int jj = g + st * G;
+        bool hit = false;
+        if (own && jj < nc) {
           const Record<R> rj = stage[jj];
           R ds[3];
           Coord<R>::disp(ri, rj, ds);
@@ -117,71 +183,91 @@ __global__ void __launch_bounds__(kRealThreads) k_real_pairs(DevPlan<R> d, R* __
           const R dy = d.hmat[3] * ds[0] + d.hmat[4] * ds[1] + d.hmat[5] * ds[2];
           const R dz = d.hmat[6] * ds[0] + d.hmat[7] * ds[1] + d.hmat[8] * ds[2];
           const R r2 = dx * dx + dy * dy + dz * dz;
-          if (r2 < d.rc2 && r2 > R(0)) {
-            const R r = sqrt(r2);
-            const R ir = R(1) / r;
-            const R xs = r * d.inv_rc * nsegr;
-            const int sg = min(nseg - 1, static_cast<int>(xs));
-            const R t = xs - static_cast<R>(sg) - R(0.5);
-            const R* cf = tab + sg * 2 * NC;
-            const R qq = ri.q * rj.q;
-            const R gn = horner<R, NC>(cf, t), gf = horner<R, NC>(cf + NC, t);
-            const R fw = qq * gf * ir * ir * ir;
-            const R wx = fw * dx, wy = fw * dy, wz = fw * dz;
-            fx += wx;
-            fy += wy;
-            fz += wz;
-            part[0] += static_cast<double>(qq * gn * ir);
-            part[1] += static_cast<double>(wx * dx);
-            part[2] += static_cast<double>(wy * dy);
-            part[3] += static_cast<double>(wz * dz);
-            part[4] += static_cast<double>(wx * dy);
-            part[5] += static_cast<double>(wx * dz);
-            part[6] += static_cast<double>(wy * dz);
-          }
+          hit = r2 < d.rc2 && r2 > R(0);
+        }
+        const unsigned long long mask = __ballot(hit);
+        if (hit) {
+          const int below = __builtin_amdgcn_mbcnt_hi(static_cast<unsigned>(mask >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo(static_cast<unsigned>(mask), 0u));
+          queue[count + below] = (lane << 16) | jj;
+        }
+        count += __popcll(mask);
+        if (count >= 64) {
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          evaluate(64);
+          count -= 64;
+          // move the remaining entries to the front (read all, then write)
+          const int rest = lane < count ? queue[64 + lane] : 0;
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          if (lane < count) queue[lane] = rest;
         }
       }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      evaluate(count);                          // the chunk's remaining pairs
+      part[0] += static_cast<double>(u);
+      part[1] += static_cast<double>(w0);
+      part[2] += static_cast<double>(w1);
+      part[3] += static_cast<double>(w2);
+      part[4] += static_cast<double>(w3);
+      part[5] += static_cast<double>(w4);
+      part[6] += static_cast<double>(w5);
+      u = w0 = w1 = w2 = w3 = w4 = w5 = R(0);
     }
     // sum each home particle's forces over its thread group
-    fred[3 * tid + 0] = fx;
-    fred[3 * tid + 1] = fy;
-    fred[3 * tid + 2] = fz;
     __syncthreads();
     if (tid < HC && h0 + tid < he) {
-      R s0 = R(0), s1 = R(0), s2 = R(0);
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
       for (int k = 0; k < G; ++k) {
         const int t = k * HC + tid;
-        s0 += fred[3 * t + 0];
-        s1 += fred[3 * t + 1];
-        s2 += fred[3 * t + 2];
+        s0 += fsh[3 * t + 0];
+        s1 += fsh[3 * t + 1];
+        s2 += fsh[3 * t + 2];
       }
-      const int64_t j = d.perm[h0 + tid];
-      const R kc = d.coulomb_k;
-      if (accumulate) {
-        f[3 * j + 0] += kc * s0;
-        f[3 * j + 1] += kc * s1;
-        f[3 * j + 2] += kc * s2;
-      } else {
-        f[3 * j + 0] = kc * s0;
-        f[3 * j + 1] = kc * s1;
-        f[3 * j + 2] = kc * s2;
-      }
+      const size_t o = static_cast<size_t>(h0 + tid) * 3;
+      fpart[o + 0] = static_cast<R>(s0);
+      fpart[o + 1] = static_cast<R>(s1);
+      fpart[o + 2] = static_cast<R>(s2);
     }
+    __syncthreads();                            // fsh read before it is cleared again
   }
   block_sum<kNumSums>(part, red);
   if (tid == 0)
 #pragma unroll
-    for (int k = 0; k < kNumSums; ++k) d.rpart[static_cast<size_t>(cell) * kNumSums + k] = part[k];
+    for (int k = 0; k < kNumSums; ++k) d.rpart[static_cast<size_t>(blockIdx.x) * kNumSums + k] = part[k];
+}
+
+// Near forces in input order: the candidate shares summed, times coulomb_k,
+// written to f or added to it.
+template <typename R>
+__global__ void __launch_bounds__(256) k_real_forces(DevPlan<R> d, R* __restrict__ f, int accumulate) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= d.n) return;
+  R s[3] = {R(0), R(0), R(0)};
+  for (int k = 0; k < d.rsplit; ++k)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) s[a] += d.fpart[(static_cast<size_t>(k) * d.n + i) * 3 + a];
+  const int64_t j = d.perm[i];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const R v = d.coulomb_k * s[a];
+    f[3 * j + a] = accumulate ? f[3 * j + a] + v : v;
+  }
 }
 
 template <typename R>
 __global__ void __launch_bounds__(256) k_real_finalize(DevPlan<R> d, double* __restrict__ out7) {
   __shared__ double red[kNumSums * 16];
-  const int ncell = d.cn1 * d.cn2 * d.cn3;
+  const int nblk = d.cn1 * d.cn2 * d.cn3 * d.rsplit;
   double v[kNumSums];
 #pragma unroll
   for (int k = 0; k < kNumSums; ++k) v[k] = 0.0;
-  for (int c = threadIdx.x; c < ncell; c += blockDim.x)
+  for (int c = threadIdx.x; c < nblk; c += blockDim.x)
 #pragma unroll
     for (int k = 0; k < kNumSums; ++k) v[k] += d.rpart[static_cast<size_t>(c) * kNumSums + k];
   block_sum<kNumSums>(v, red);
@@ -198,7 +284,12 @@ size_t lds_real(const DevPlan<R>& d) {
 template <typename R>
 hipError_t launch_real_pairs(const DevPlan<R>& d, R* f, int accumulate, hipStream_t s) {
   const size_t lds = lds_real(d);     // at most 40 KiB (segment count capped on the host)
-  hipLaunchKernelGGL(k_real_pairs<R>, dim3(d.cn1 * d.cn2 * d.cn3), dim3(kRealThreads), lds, s, d, f, accumulate);
+  const int nblk = d.cn1 * d.cn2 * d.cn3 * d.rsplit;
+  hipLaunchKernelGGL(k_real_pairs<R>, dim3(nblk), dim3(kRealThreads), lds, s, d);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_real_forces<R>, dim3(static_cast<unsigned>((d.n + 255) / 256)), dim3(256), 0, s, d, f,
+                     accumulate);
   return hipGetLastError();
 }
 

@@ -111,7 +111,10 @@ def test_accumulate_and_total_coulomb_against_ewald(precision):
     f_near, o_near2 = plan.real_space(xyz, qq)
     assert plan.check() == esp.ESP_OK
     f_near = f_near.double().cpu().numpy()
-    assert np.allclose(o_near.cpu().numpy(), o_near2.cpu().numpy(), rtol=1e-12, atol=0)
+    # the order of particles within a cell follows the binning atomics, so FP32
+    # sums repeat only to their rounding
+    same = 1e-12 if precision == "fp64" else 1e-6
+    assert np.allclose(o_near.cpu().numpy(), o_near2.cpu().numpy(), rtol=same, atol=0)
     assert rel_rms(f_tot, f_far + f_near) < 1e-6
     o = o_far.cpu().numpy() + o_near.cpu().numpy()
     assert abs(o[0] - exact.energy) <= 1e-5 * abs(exact.energy)
