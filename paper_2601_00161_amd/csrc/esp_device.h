@@ -121,6 +121,7 @@ struct DevPlan {
   R rc2, inv_rc;
   int rsplit;                      // workgroups per cell, each with a share of the candidates
   R* fpart;                        // rsplit x n x 3 near-force shares (sorted order)
+  double* facc;                    // n x 3 reaction forces (sorted order; kept zero between calls)
   double* rpart;                   // cells x rsplit x 7 partial sums of the near energy and virial
   int64_t pofs;                    // batched launches: first particle of this plan in the
   int rep;                         // concatenated inputs, and its index (0 for single plans)

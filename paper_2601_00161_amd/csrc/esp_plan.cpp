@@ -706,6 +706,7 @@ esp_status build_device(esp_plan_t* p) {
       (st = dalloc(p, &d.offsets, std::max(r.ntiles, kMaxCells) + 1)) ||
       (st = dalloc(p, &d.rpart, static_cast<size_t>(std::max(kMaxCells, 2 * kRealBlocks)) * kNumSums)) ||
       (st = dalloc(p, &d.fpart, static_cast<size_t>(kMaxRealSplit) * r.n * 3)) ||
+      (st = dalloc(p, &d.facc, static_cast<size_t>(r.n) * 3)) ||
       (st = dalloc(p, &d.keys, r.n)) || (st = dalloc(p, &d.ranks, r.n)) || (st = dalloc(p, &d.perm, r.n)) ||
       (st = dalloc(p, &d.tmp, r.n)) || (st = dalloc(p, &d.sorted, r.n)) || (st = dalloc(p, &d.rho, G)) ||
       (st = dalloc(p, &d.spec, S * d.ncomp)) || (st = dalloc(p, &d.phi, G * d.ncomp)) ||
@@ -725,6 +726,7 @@ esp_status build_device(esp_plan_t* p) {
                     r.n >= static_cast<int64_t>(kTiledGatherMin) * r.ntiles);
   e = hipMemset(d.counts, 0, ncount * sizeof(int));
   if (e == hipSuccess) e = hipMemset(d.rho, 0, G * sizeof(R));
+  if (e == hipSuccess) e = hipMemset(d.facc, 0, static_cast<size_t>(r.n) * 3 * sizeof(double));
   if (e == hipSuccess) e = hipMemset(d.flags, 0, 4 * sizeof(int));
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(p, e, "buffer initialisation");

@@ -5,17 +5,22 @@
 // and, with rc below half the smallest width, its separation is the minimum
 // image in reduced coordinates.
 //
-// Workgroups of 256 threads: rsplit per home cell, each taking an equal share
-// of the cell's candidate list (the particles of the distinct neighbouring
-// cells, the home cell included), so that small systems still fill the chip.
-// Candidates are staged through LDS in chunks; thread t works on home
-// particle t % HC against every (256 / HC)-th candidate, HC in {16, 32, 64}
-// chosen per cell to waste the fewest lanes, and the partial forces of a home
-// particle are summed over its thread group in LDS and stored per share; a
-// second kernel adds the shares in a fixed order.  Every ordered pair is
-// visited once, so no atomics are needed and the results are reproducible;
-// energy and virial take the factor 1/2 at the end.  The split
-// functions of x = r / rc, 1 - phi0(x) (N^c = that / r) and
+// Each unordered pair within rc is evaluated once (Newton's third law): the
+// cell with the lower index handles a pair of neighbouring cells, and within
+// a cell a particle pairs with the ones sorted after it.  Workgroups of 256
+// threads, rsplit per home cell, each take an equal share of the cell's
+// candidate list (the particles of the neighbouring cells kept for it, the
+// home cell included), so that small systems still fill the chip.
+// Candidates are staged through LDS in chunks; thread t tests home particle
+// t % HC against every (256 / HC)-th candidate (a residue class that differs
+// between the lanes of a group), HC in {16, 32, 64} chosen per cell to waste
+// the fewest lanes.  Pairs within rc go to a per-wave queue and
+// are evaluated 64 at a time on full waves.  The force on the home particle
+// accumulates in LDS per thread and is summed over its thread group into a
+// per-share array that a second kernel adds in a fixed order; the reaction
+// on the candidate accumulates in LDS per staged record and is added to an
+// FP64 array with one atomic per record and chunk.  The split functions of
+// x = r / rc, 1 - phi0(x) (N^c = that / r) and
 // F_N(x) = 1 - phi0(x) + x psi(x) / C0 (pair force q_i q_j F_N d / r^3), are
 // piecewise polynomials on nseg equal segments of [0, 1].
 #include <hip/hip_runtime.h>
@@ -25,7 +30,7 @@
 namespace espx {
 
 constexpr int kRealThreads = 256;
-constexpr int kRealStage = 1024;     // candidate records staged per round
+constexpr int kRealStage = 256;      // candidate records staged per round
 
 // 1 / sqrt(x): the hardware reciprocal square root (1 ulp) in FP32, the
 // correctly rounded quotient in FP64.
@@ -47,7 +52,9 @@ __global__ void __launch_bounds__(kRealThreads) k_real_pairs(DevPlan<R> d) {
   __shared__ Record<R> home[kRealThreads];       // each thread's home particle
   __shared__ double fsh[3 * kRealThreads];       // each thread's home-particle force (FP64: the
                                                  // LDS float add is slow on this chip)
-  __shared__ int wqueue[2 * kRealThreads];       // per wave: pairs within rc awaiting evaluation
+  __shared__ double jf[3 * kRealStage];          // reaction forces on the staged candidates
+  __shared__ int sidx[kRealStage];               // sorted index of each staged candidate
+  __shared__ int wqueue[3 * kRealThreads];       // per wave: pairs within rc awaiting evaluation
   __shared__ double red[kNumSums * 16];
   __shared__ int nstart[27], ncnt[27], ncum[28];
   extern __shared__ __align__(16) unsigned char smem[];
@@ -59,7 +66,9 @@ __global__ void __launch_bounds__(kRealThreads) k_real_pairs(DevPlan<R> d) {
   {
     // neighbour cell at offset (o1, o2, o3) in {-1, 0, 1}^3; along a dimension
     // with only 2 cells the offsets -1 and +1 name the same cell, so -1 is
-    // left out (its slot stays empty)
+    // left out.  Each unordered pair of cells is handled once, by the lower
+    // cell index (slot 13, the cell itself, holds the pairs within it).
+    // Empty slots stay in the list with no particles.
     if (tid < 27) {
       const int o1 = tid % 3 - 1, o2 = (tid / 3) % 3 - 1, o3 = tid / 9 - 1;
       const bool ok = (d.cn1 > 2 || o1 >= 0) && (d.cn2 > 2 || o2 >= 0) && (d.cn3 > 2 || o3 >= 0);
@@ -69,8 +78,10 @@ __global__ void __launch_bounds__(kRealThreads) k_real_pairs(DevPlan<R> d) {
         const int c2 = ((cell / d.cn1) % d.cn2 + o2 + d.cn2) % d.cn2;
         const int c3 = (cell / (d.cn1 * d.cn2) + o3 + d.cn3) % d.cn3;
         const int nc = (c3 * d.cn2 + c2) * d.cn1 + c1;
-        st = d.offsets[nc];
-        en = d.offsets[nc + 1];
+        if (nc >= cell) {
+          st = d.offsets[nc];
+          en = d.offsets[nc + 1];
+        }
       }
       nstart[tid] = st;
       ncnt[tid] = en - st;
@@ -107,8 +118,9 @@ __global__ void __launch_bounds__(kRealThreads) k_real_pairs(DevPlan<R> d) {
   const int G = kRealThreads / HC, hi = tid % HC, g = tid / HC;
   const R nsegr = static_cast<R>(nseg);
   R* fpart = d.fpart + static_cast<size_t>(ks) * d.n * 3;
+  const int self0 = ncum[13], self1 = ncum[14];   // candidates of the home cell itself
   const int lane = tid & 63, wbase = tid & ~63;
-  int* queue = wqueue + 2 * wbase;              // this wave's 128 entries
+  int* queue = wqueue + 3 * wbase;              // this wave's 192 entries
   double part[kNumSums];
 #pragma unroll
   for (int k = 0; k < kNumSums; ++k) part[k] = 0.0;
@@ -137,9 +149,13 @@ __global__ void __launch_bounds__(kRealThreads) k_real_pairs(DevPlan<R> d) {
       const R gn = horner<R, NC>(cf, t), gf = horner<R, NC>(cf + NC, t);
       const R fw = qq * gf * ir * ir * ir;
       const R wx = fw * dx, wy = fw * dy, wz = fw * dz;
+      const int js = e & 0xffff;
       atomicAdd(fsh + 3 * src + 0, static_cast<double>(wx));
       atomicAdd(fsh + 3 * src + 1, static_cast<double>(wy));
       atomicAdd(fsh + 3 * src + 2, static_cast<double>(wz));
+      atomicAdd(jf + 3 * js + 0, -static_cast<double>(wx));
+      atomicAdd(jf + 3 * js + 1, -static_cast<double>(wy));
+      atomicAdd(jf + 3 * js + 2, -static_cast<double>(wz));
       u += qq * gn * ir;
       w0 += wx * dx;
       w1 += wy * dy;
@@ -149,6 +165,38 @@ __global__ void __launch_bounds__(kRealThreads) k_real_pairs(DevPlan<R> d) {
       w5 += wy * dz;
     }
   };
+  // stage candidates [c0, c0 + nc) with their sorted indices and cleared reactions
+  auto stage_chunk = [&](int c0, int nc) {
+    for (int k = tid; k < nc; k += kRealThreads) {
+      const int cand = c0 + k;
+      int lo = 0, hi2 = 26;                     // slot m with ncum[m] <= cand < ncum[m + 1]
+      while (lo < hi2) {
+        const int mid = (lo + hi2 + 1) >> 1;
+        if (ncum[mid] <= cand) lo = mid; else hi2 = mid - 1;
+      }
+      const int idx = nstart[lo] + cand - ncum[lo];
+      stage[k] = d.sorted[idx];
+      sidx[k] = idx;
+      jf[3 * k + 0] = 0.0;
+      jf[3 * k + 1] = 0.0;
+      jf[3 * k + 2] = 0.0;
+    }
+  };
+  // add the staged reactions to the FP64 force array (after a barrier)
+  auto flush_reactions = [&](int nc) {
+    for (int k = tid; k < nc; k += kRealThreads) {
+      double* dst = d.facc + 3 * static_cast<size_t>(sidx[k]);
+      const double a = jf[3 * k + 0], b = jf[3 * k + 1], c = jf[3 * k + 2];
+      if (a != 0.0 || b != 0.0 || c != 0.0) {
+        atomicAdd(dst + 0, a);
+        atomicAdd(dst + 1, b);
+        atomicAdd(dst + 2, c);
+      }
+    }
+  };
+  // a share that fits in one chunk is staged once for all home passes
+  const bool once = chi - clo <= kRealStage;
+  if (once) stage_chunk(clo, chi - clo);
   for (int h0 = hs; h0 < he; h0 += HC) {
     const int i = h0 + hi;
     const bool own = i < he;
@@ -160,20 +208,17 @@ __global__ void __launch_bounds__(kRealThreads) k_real_pairs(DevPlan<R> d) {
     for (int c0 = clo; c0 < chi; c0 += kRealStage) {
       const int nc = min(kRealStage, chi - c0);
       __syncthreads();                          // previous chunk consumed; home and fsh set
-      for (int k = tid; k < nc; k += kRealThreads) {
-        const int cand = c0 + k;
-        int m = 0;
-        while (ncum[m + 1] <= cand) ++m;
-        stage[k] = d.sorted[nstart[m] + cand - ncum[m]];
+      if (!once) {
+        stage_chunk(c0, nc);
+        __syncthreads();
       }
-      __syncthreads();
       // test phase: every lane takes the same number of steps, so the wave
       // stays converged; pairs within rc are appended to the wave's queue and
       // evaluated 64 at a time
       int count = 0;
-      const int steps = (nc + G - 1) / G;
-      for (int st = 0; st < steps; ++st) {
-        const int jj = g + st * G;
+      // is candidate jj within rc of this lane's home particle (and, within
+      // the home cell, sorted after it)?
+      auto test = [&](int jj) {
         bool hit = false;
         if (own && jj < nc) {
           const Record<R> rj = stage[jj];
@@ -183,8 +228,12 @@ __global__ void __launch_bounds__(kRealThreads) k_real_pairs(DevPlan<R> d) {
           const R dy = d.hmat[3] * ds[0] + d.hmat[4] * ds[1] + d.hmat[5] * ds[2];
           const R dz = d.hmat[6] * ds[0] + d.hmat[7] * ds[1] + d.hmat[8] * ds[2];
           const R r2 = dx * dx + dy * dy + dz * dz;
-          hit = r2 < d.rc2 && r2 > R(0);
+          const int cand = c0 + jj;
+          hit = r2 < d.rc2 && r2 > R(0) && (cand < self0 || cand >= self1 || cand - self0 > i - hs);
         }
+        return hit;
+      };
+      auto append = [&](bool hit, int jj) {
         const unsigned long long mask = __ballot(hit);
         if (hit) {
           const int below = __builtin_amdgcn_mbcnt_hi(static_cast<unsigned>(mask >> 32),
@@ -192,24 +241,43 @@ __global__ void __launch_bounds__(kRealThreads) k_real_pairs(DevPlan<R> d) {
           queue[count + below] = (lane << 16) | jj;
         }
         count += __popcll(mask);
-        if (count >= 64) {
+      };
+      // Lane (g, hi) takes the candidates of residue class (g + hi) mod G, so
+      // a home particle still meets every candidate once over its G lanes
+      // while the lanes of one group read (and react on) different records.
+      // Two candidates per step; every lane takes the same number of steps,
+      // so the wave stays converged.
+      const int rcls = (g + hi) % G;
+      const int steps = (nc + 2 * G - 1) / (2 * G);
+      for (int st = 0; st < steps; ++st) {
+        const int ja = rcls + 2 * st * G, jb = ja + G;
+        const bool ha = test(ja), hb = test(jb);
+        append(ha, ja);
+        append(hb, jb);
+        while (count >= 64) {
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
           __builtin_amdgcn_wave_barrier();
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
           evaluate(64);
           count -= 64;
-          // move the remaining entries to the front (read all, then write)
-          const int rest = lane < count ? queue[64 + lane] : 0;
+          // move the remaining entries (at most 127) to the front: read all, then write
+          const int r0 = lane < count ? queue[64 + lane] : 0;
+          const int r1 = lane + 64 < count ? queue[128 + lane] : 0;
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
           __builtin_amdgcn_wave_barrier();
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-          if (lane < count) queue[lane] = rest;
+          if (lane < count) queue[lane] = r0;
+          if (lane + 64 < count) queue[64 + lane] = r1;
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       evaluate(count);                          // the chunk's remaining pairs
+      if (!once) {
+        __syncthreads();                        // every reaction force of the chunk is in jf
+        flush_reactions(nc);
+      }
       part[0] += static_cast<double>(u);
       part[1] += static_cast<double>(w0);
       part[2] += static_cast<double>(w1);
@@ -236,6 +304,8 @@ __global__ void __launch_bounds__(kRealThreads) k_real_pairs(DevPlan<R> d) {
     }
     __syncthreads();                            // fsh read before it is cleared again
   }
+  __syncthreads();
+  if (once) flush_reactions(chi - clo);
   block_sum<kNumSums>(part, red);
   if (tid == 0)
 #pragma unroll
@@ -248,14 +318,19 @@ template <typename R>
 __global__ void __launch_bounds__(256) k_real_forces(DevPlan<R> d, R* __restrict__ f, int accumulate) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= d.n) return;
-  R s[3] = {R(0), R(0), R(0)};
+  double s[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    s[a] = d.facc[3 * i + a];
+    d.facc[3 * i + a] = 0.0;                    // zero again for the next call
+  }
   for (int k = 0; k < d.rsplit; ++k)
 #pragma unroll
-    for (int a = 0; a < 3; ++a) s[a] += d.fpart[(static_cast<size_t>(k) * d.n + i) * 3 + a];
+    for (int a = 0; a < 3; ++a) s[a] += static_cast<double>(d.fpart[(static_cast<size_t>(k) * d.n + i) * 3 + a]);
   const int64_t j = d.perm[i];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const R v = d.coulomb_k * s[a];
+    const R v = static_cast<R>(d.fin.coulomb_k * s[a]);
     f[3 * j + a] = accumulate ? f[3 * j + a] + v : v;
   }
 }
@@ -273,7 +348,7 @@ __global__ void __launch_bounds__(256) k_real_finalize(DevPlan<R> d, double* __r
   block_sum<kNumSums>(v, red);
   if (threadIdx.x == 0)
 #pragma unroll
-    for (int k = 0; k < kNumSums; ++k) out7[k] = 0.5 * d.fin.coulomb_k * v[k];
+    for (int k = 0; k < kNumSums; ++k) out7[k] = d.fin.coulomb_k * v[k];   // each pair once
 }
 
 template <typename R>
