@@ -327,6 +327,11 @@ struct Coord<float> {
     for (int k = 0; k < 3; ++k)
       ds[k] = static_cast<float>(static_cast<int>(a.S[k] - b.S[k])) * 2.3283064365386963e-10f;
   }
+  // the same displacement in units of 2^-32 (unscaled)
+  __device__ static void disp_raw(const Record<float>& a, const Record<float>& b, float* n) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) n[k] = static_cast<float>(static_cast<int>(a.S[k] - b.S[k]));
+  }
 };
 
 template <>
@@ -356,6 +361,7 @@ struct Coord<double> {
       ds[k] = v - rint(v);
     }
   }
+  __device__ static void disp_raw(const Record<double>& a, const Record<double>& b, double* n) { disp(a, b, n); }
 };
 
 template <typename R>

@@ -118,6 +118,8 @@ struct DevPlan {
                                    // local t = nrs x - s - 1/2: first 1 - phi0(x), then
                                    // F_N(x) = 1 - phi0(x) + x psi(x) / C0 (eq. mathFN)
   R hmat[9];                       // h, row major: d = h ds
+  R gmet[6];                       // metric h^T h as (g00, g11, g22, 2 g01, 2 g02, 2 g12), scaled
+                                   // by 2^-64 for the FP32 path (raw fixed-point displacements)
   R rc2, inv_rc;
   int rsplit;                      // workgroups per cell, each with a share of the candidates
   R* fpart;                        // rsplit x n x 3 near-force shares (sorted order)
@@ -132,7 +134,7 @@ template <typename R>
 inline constexpr int kRealDeg = sizeof(R) == 8 ? 9 : 5;
 constexpr int kMaxCells = 32768;   // real-space cells (the scatter pass keeps their offsets in LDS)
 constexpr int kMaxRealSplit = 8;   // workgroups per real-space cell
-constexpr int kRealBlocks = 2048;  // target workgroups of the pair kernel (rsplit up to kMaxRealSplit)
+constexpr int kRealBlocks = 3072;  // target workgroups of the pair kernel (rsplit up to kMaxRealSplit)
 
 // Lanes per particle of the gather kernel (a power of two >= P).
 constexpr int gather_lanes(int P) { return P <= 4 ? 4 : (P <= 8 ? 8 : 16); }

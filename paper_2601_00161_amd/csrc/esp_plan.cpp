@@ -469,6 +469,12 @@ void set_box_fields(esp_plan_t* p, DevPlan<R>& d) {
   d.cn2 = cn[1];
   d.cn3 = cn[2];
   for (int i = 0; i < 9; ++i) d.hmat[i] = static_cast<R>(r.h[i]);
+  {
+    auto g = [&](int a, int b) { return r.h[a] * r.h[b] + r.h[3 + a] * r.h[3 + b] + r.h[6 + a] * r.h[6 + b]; };
+    const double sc = sizeof(R) == 4 ? std::ldexp(1.0, -64) : 1.0;
+    const double gm[6] = {g(0, 0), g(1, 1), g(2, 2), 2 * g(0, 1), 2 * g(0, 2), 2 * g(1, 2)};
+    for (int k = 0; k < 6; ++k) d.gmet[k] = static_cast<R>(gm[k] * sc);
+  }
   d.rc2 = static_cast<R>(r.rc * r.rc);
   d.inv_rc = static_cast<R>(1.0 / r.rc);
 }

@@ -46,7 +46,7 @@ __device__ __forceinline__ R horner(const R* __restrict__ c, R t) {
 }
 
 template <typename R>
-__global__ void __launch_bounds__(kRealThreads) k_real_pairs(DevPlan<R> d) {
+__global__ void __launch_bounds__(kRealThreads) __attribute__((amdgpu_waves_per_eu(6))) k_real_pairs(DevPlan<R> d) {
   constexpr int NC = kRealDeg<R> + 1;
   __shared__ Record<R> stage[kRealStage];
   __shared__ Record<R> home[kRealThreads];       // each thread's home particle
@@ -222,12 +222,12 @@ __global__ void __launch_bounds__(kRealThreads) k_real_pairs(DevPlan<R> d) {
         bool hit = false;
         if (own && jj < nc) {
           const Record<R> rj = stage[jj];
-          R ds[3];
-          Coord<R>::disp(ri, rj, ds);
-          const R dx = d.hmat[0] * ds[0] + d.hmat[1] * ds[1] + d.hmat[2] * ds[2];
-          const R dy = d.hmat[3] * ds[0] + d.hmat[4] * ds[1] + d.hmat[5] * ds[2];
-          const R dz = d.hmat[6] * ds[0] + d.hmat[7] * ds[1] + d.hmat[8] * ds[2];
-          const R r2 = dx * dx + dy * dy + dz * dz;
+          R n[3];
+          Coord<R>::disp_raw(ri, rj, n);
+          // r^2 from the metric h^T h (the evaluation recomputes d itself)
+          const R t0 = d.gmet[0] * n[0] + d.gmet[3] * n[1] + d.gmet[4] * n[2];
+          const R t1 = d.gmet[1] * n[1] + d.gmet[5] * n[2];
+          const R r2 = n[0] * t0 + n[1] * t1 + n[2] * (d.gmet[2] * n[2]);
           const int cand = c0 + jj;
           hit = r2 < d.rc2 && r2 > R(0) && (cand < self0 || cand >= self1 || cand - self0 > i - hs);
         }

@@ -31,7 +31,18 @@ SYSTEMS = {
                                           seed=24),
     # mixed: 2 cells along one vector, more along the others
     "slab_1.9x3.3x2.8": lambda: synth.water(580, np.diag([1.9, 3.3, 2.8]), seed=25),
+    # one dense cluster in a mostly empty box: crowded cells whose candidates
+    # need several staging rounds, and empty cells next to them
+    "cluster_4.5": lambda: _cluster(),
 }
+
+
+def _cluster():
+    rng = np.random.default_rng(28)
+    n = 2000
+    r = rng.uniform(0.3, 1.8, size=(n, 3))
+    q = np.where(np.arange(n) % 2 == 0, 0.6, -0.6)
+    return synth.cubic(4.5), r, q
 
 
 def _run(h, r, q, precision, tol=1e-5, **kw):
