@@ -225,6 +225,10 @@ def main():
     ap.add_argument("--params", default="learned", choices=["learned", "analytic"],
                     help="parameter source of the FP32 headline plan")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner (plan defaults)")
+    ap.add_argument("--gather", default="auto", choices=["auto", "particle", "tile"],
+                    help="gather variant when the launch shape is given (--tile or --no-tune)")
+    ap.add_argument("--counters-only", action="store_true",
+                    help="run only the headline plan (at --tile / --gather) and the near part, for counter passes")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-replica batch measurement")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="first run 5 plain device copies of MIB MiB (float32), the known-size "
@@ -256,6 +260,21 @@ def main():
     x32, c32 = torch.from_numpy(r32).to(dev), torch.from_numpy(q32).to(dev)
     x64, c64 = torch.from_numpy(r32.astype(np.float64)).to(dev), torch.from_numpy(q32.astype(np.float64)).to(dev)
 
+    if args.counters_only:
+        # one plan at a fixed launch shape, so that per-kernel counters are not
+        # mixed with the autotuner's trial shapes
+        p = Plan(h, N, args.tol, precision="fp32", params=args.params, tile=args.tile, gather=args.gather)
+        f, o = p.forces(x32, c32)
+        fn, on = p.real_space(x32, c32)
+        for _ in range(args.warmup + args.steps):
+            p.forces(x32, c32, f=f, out7=o)
+            p.real_space(x32, c32, f=fn, out7=on)
+        torch.cuda.synchronize()
+        print(json.dumps({"counters_run": True, "tile": p.params["tile"], "gather_tiled": p.params["gather_tiled"],
+                          "P": p.params["P"], "M": p.params["M"], "launches": args.warmup + args.steps}))
+        p.close()
+        return
+
     import tempfile
     from paper_2601_00161_amd import autotune
     tune_dir = tempfile.TemporaryDirectory()
@@ -263,7 +282,7 @@ def main():
     def make_plan(precision, params, xyz, q):
         """A plan with the autotuned launch shape (tile edge, gather variant)."""
         if args.no_tune or args.tile:
-            return Plan(h, N, args.tol, precision=precision, params=params, tile=args.tile), None
+            return Plan(h, N, args.tol, precision=precision, params=params, tile=args.tile, gather=args.gather), None
         return autotune.tuned_plan(h, N, args.tol, xyz, q, cache=os.path.join(tune_dir.name, "tune.json"),
                                    precision=precision, params=params)
 
@@ -355,7 +374,8 @@ def main():
     avg_s = dom_ms / dom_n / 1e3
     bytes_dom = stage_bytes(dominant, N, G, S, 4)
     achieved = bytes_dom / avg_s / 1e9
-    workload_key = f"water30k_tol{args.tol:g}_P{prm['P']}_M{prm['M'][0]}x{prm['M'][1]}x{prm['M'][2]}"
+    workload_key = (f"water30k_tol{args.tol:g}_P{prm['P']}_M{prm['M'][0]}x{prm['M'][1]}x{prm['M'][2]}"
+                    f"_T{prm['tile'][0]}_{'gtile' if prm['gather_tiled'] else 'gpart'}")
     traffic = measured_traffic(dominant, workload_key)
     value = N * args.steps / dt32 / 1e6
     v64 = N * args.steps / dt64 / 1e6
