@@ -98,11 +98,25 @@ __global__ void __launch_bounds__(256) k_bin(KArg<R, BATCH> ka, const R* __restr
   }
   __syncthreads();
   int* counts = d.counts + static_cast<size_t>(blk % d.nsub) * d.ntiles;
-  if (lh)
-    for (int k = threadIdx.x; k < d.ntiles; k += blockDim.x) {
-      const int c = hist[k];
-      if (c) hist[k] = atomicAdd(counts + k, c);
+  if (lh) {
+    // a thread issues all of its (returning) atomics before it uses a result,
+    // so their round trips overlap instead of adding up
+    constexpr int U = 4;
+    for (int k0 = threadIdx.x; k0 < d.ntiles; k0 += U * blockDim.x) {
+      int c[U], r[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = k0 + u * static_cast<int>(blockDim.x);
+        c[u] = k < d.ntiles ? hist[k] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        r[u] = c[u] ? atomicAdd(counts + k0 + u * static_cast<int>(blockDim.x), c[u]) : 0;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (c[u]) hist[k0 + u * static_cast<int>(blockDim.x)] = r[u];
     }
+  }
   __syncthreads();
   if (i < d.n) {
     d.keys[i] = key;

@@ -74,15 +74,21 @@ __global__ void __launch_bounds__(256) k_spread(KArg<R, BATCH> ka) {
   const int start = d.offsets[tile], end = d.offsets[tile + 1];
   if (threadIdx.x == 0) d.counts[tile] = 0;        // ready for the next binning pass
   if (start == end) return;
+  // one weight task per (particle, dimension) of a chunk: kSpreadChunk x 3 <=
+  // 256 threads, so thread t always takes task t, and its record is fetched
+  // one phase ahead (the first while the LDS tile is cleared)
+  static_assert(kSpreadChunk * 3 <= 256, "one weight task per thread");
+  const int tj = threadIdx.x / 3, tdim = threadIdx.x - 3 * (threadIdx.x / 3);
+  Record<R> rec;
+  if (threadIdx.x < min(kSpreadChunk, end - start) * 3) rec = d.sorted[start + tj];
   for (int k = threadIdx.x; k < ncell; k += blockDim.x) grid[k] = 0.0;
   for (int k = threadIdx.x; k < (NW + 1) * P; k += blockDim.x) win[k] = d.win[k];
   __syncthreads();
   for (int c0 = start; c0 < end; c0 += kSpreadChunk) {
     const int nc = min(kSpreadChunk, end - c0);
-    // weights: one task per (particle, dimension); q folded into x
-    for (int t = threadIdx.x; t < nc * 3; t += blockDim.x) {
-      const int j = t / 3, dim = t - 3 * j;
-      const Record<R> rec = d.sorted[c0 + j];
+    // weights: q folded into x
+    if (threadIdx.x < nc * 3) {
+      const int j = tj, dim = tdim;
       int gm;
       R tau;
       const int Md = dim == 0 ? d.M1 : (dim == 1 ? d.M2 : d.M3);
@@ -96,6 +102,10 @@ __global__ void __launch_bounds__(256) k_spread(KArg<R, BATCH> ka) {
       base[j * 3 + dim] = gm - od;
     }
     __syncthreads();
+    {
+      const int c1 = c0 + kSpreadChunk;
+      if (c1 < end && threadIdx.x < min(kSpreadChunk, end - c1) * 3) rec = d.sorted[c1 + tj];
+    }
     // accumulation: one task per (particle, z offset), the P x P block of that plane
     for (int t = threadIdx.x; t < nc * P; t += blockDim.x) {
       const int j = t / P, cz = t - j * P;
@@ -160,12 +170,15 @@ __global__ void __launch_bounds__(256) k_gather(KArg<R, BATCH> ka, R* __restrict
   extern __shared__ __align__(16) unsigned char smem[];
   R* win = reinterpret_cast<R*>(smem);                // (NW + 1) x P
   R* wt = win + (NW + 1) * P;                         // G x 6 x P: w1 d1 w2 d2 w3 d3
-  for (int k = threadIdx.x; k < (NW + 1) * P; k += blockDim.x) win[k] = d.win[k];
-  __syncthreads();
+  // the particle's record and destination are fetched before the table
+  // barrier, so the two global round trips overlap
   const int grp = threadIdx.x / L, lane = threadIdx.x - grp * L;
   const int64_t i = static_cast<int64_t>(blk) * G + grp;
   const bool valid = i < d.n;
   const Record<R> rec = d.sorted[valid ? i : 0];
+  const int64_t j = valid ? d.perm[i] : 0;
+  for (int k = threadIdx.x; k < (NW + 1) * P; k += blockDim.x) win[k] = d.win[k];
+  __syncthreads();
   int g1, g2, g3;
   R t1, t2, t3;
   Coord<R>::stencil(rec, 0, d.M1, P, g1, t1);
@@ -229,7 +242,6 @@ __global__ void __launch_bounds__(256) k_gather(KArg<R, BATCH> ka, R* __restrict
   }
   if (lane == 0 && valid) {
     const R qk = rec.q * d.coulomb_k;
-    const int64_t j = d.perm[i];
     f[3 * j + 0] = qk * (d.G[0] * gx + d.G[1] * gy + d.G[2] * gz);
     f[3 * j + 1] = qk * (d.G[3] * gx + d.G[4] * gy + d.G[5] * gz);
     f[3 * j + 2] = qk * (d.G[6] * gx + d.G[7] * gy + d.G[8] * gz);
@@ -255,12 +267,15 @@ __global__ void __launch_bounds__(256) k_gather_ik(KArg<R, BATCH> ka, R* __restr
   extern __shared__ __align__(16) unsigned char smem[];
   R* win = reinterpret_cast<R*>(smem);                // (NW + 1) x P
   R* wt = win + (NW + 1) * P;                         // G x 3 x P: w1 w2 w3
-  for (int k = threadIdx.x; k < (NW + 1) * P; k += blockDim.x) win[k] = d.win[k];
-  __syncthreads();
+  // the particle's record and destination are fetched before the table
+  // barrier, so the two global round trips overlap
   const int grp = threadIdx.x / L, lane = threadIdx.x - grp * L;
   const int64_t i = static_cast<int64_t>(blk) * G + grp;
   const bool valid = i < d.n;
   const Record<R> rec = d.sorted[valid ? i : 0];
+  const int64_t j = valid ? d.perm[i] : 0;
+  for (int k = threadIdx.x; k < (NW + 1) * P; k += blockDim.x) win[k] = d.win[k];
+  __syncthreads();
   int g1, g2, g3;
   R t1, t2, t3;
   Coord<R>::stencil(rec, 0, d.M1, P, g1, t1);
@@ -318,7 +333,6 @@ __global__ void __launch_bounds__(256) k_gather_ik(KArg<R, BATCH> ka, R* __restr
   }
   if (lane == 0 && valid) {
     const R qk = -rec.q * d.coulomb_k;
-    const int64_t j = d.perm[i];
     f[3 * j + 0] = qk * ex;
     f[3 * j + 1] = qk * ey;
     f[3 * j + 2] = qk * ez;
@@ -345,12 +359,15 @@ __global__ void __launch_bounds__(256) k_gather_local(KArg<R, BATCH> ka, R* __re
   extern __shared__ __align__(16) unsigned char smem[];
   R* win = reinterpret_cast<R*>(smem);                // (NW + 1) x P
   R* wt = win + (NW + 1) * P;                         // G x 3 x P: w1 w2 w3
-  for (int k = threadIdx.x; k < (NW + 1) * P; k += blockDim.x) win[k] = d.win[k];
-  __syncthreads();
+  // the particle's record and destination are fetched before the table
+  // barrier, so the two global round trips overlap
   const int grp = threadIdx.x / L, lane = threadIdx.x - grp * L;
   const int64_t i = static_cast<int64_t>(blk) * G + grp;
   const bool valid = i < d.n;
   const Record<R> rec = d.sorted[valid ? i : 0];
+  const int64_t j = valid ? d.perm[i] : 0;
+  for (int k = threadIdx.x; k < (NW + 1) * P; k += blockDim.x) win[k] = d.win[k];
+  __syncthreads();
   int g1, g2, g3;
   R t1, t2, t3;
   Coord<R>::stencil(rec, 0, d.M1, P, g1, t1);
@@ -402,7 +419,6 @@ __global__ void __launch_bounds__(256) k_gather_local(KArg<R, BATCH> ka, R* __re
     for (int c = 0; c < 6; ++c) acc[c] += __shfl_xor(acc[c], off, 64);
   if (lane == 0 && valid) {
     const R qk = rec.q * d.coulomb_k;
-    const int64_t j = d.perm[i];
 #pragma unroll
     for (int c = 0; c < 6; ++c) w6[6 * j + c] = qk * acc[c];
   }
@@ -452,6 +468,7 @@ __global__ void __launch_bounds__(256) k_gather_tile(KArg<R, BATCH> ka, R* __res
     const int i = base + grp;
     const bool valid = i < end;
     const Record<R> rec = d.sorted[valid ? i : start];
+    const int64_t j = valid ? d.perm[i] : 0;        // fetched early: used at the end
     int g1, g2, g3;
     R u1, u2, u3;
     Coord<R>::stencil(rec, 0, d.M1, P, g1, u1);
@@ -508,7 +525,6 @@ __global__ void __launch_bounds__(256) k_gather_tile(KArg<R, BATCH> ka, R* __res
     }
     if (lane == 0 && valid) {
       const R qk = rec.q * d.coulomb_k;
-      const int64_t j = d.perm[i];
       f[3 * j + 0] = qk * (d.G[0] * gx + d.G[1] * gy + d.G[2] * gz);
       f[3 * j + 1] = qk * (d.G[3] * gx + d.G[4] * gy + d.G[5] * gz);
       f[3 * j + 2] = qk * (d.G[6] * gx + d.G[7] * gy + d.G[8] * gz);
