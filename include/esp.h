@@ -113,6 +113,9 @@ typedef struct {
                           conserves momentum.  Energy and virial are the same. */
   int local_virial;    /* nonzero: allocate the six tensor-component grids used by
                           esp_local_virial */
+  int fft_split;       /* nonzero: run the x and y transforms as separate passes even
+                          when a grid plane fits one workgroup's LDS (planes that do
+                          not fit always take them) */
 } esp_opts;
 
 enum { ESP_GATHER_AUTO = 0, ESP_GATHER_PARTICLE = 1, ESP_GATHER_TILE = 2 };
@@ -138,6 +141,7 @@ typedef struct {
   int local_virial;               /* the plan supports esp_local_virial */
   int real_cells[3];              /* esp_real_space cells per cell vector (current box) */
   int real_segments;              /* segments of the near-kernel polynomials on [0, rc] */
+  int fft_split;                  /* the xy transforms run as separate x and y passes */
 } esp_params;
 
 void esp_opts_default(esp_opts *o);

@@ -109,6 +109,8 @@ struct DevPlan {
   int ncomp;                       // spectra / real grids allocated (1, 3 or 6)
   int nsub;                        // tile counters per tile: binning block b uses copy b % nsub
   int cellsort;                    // binning keys are real-space cells (cn1 x cn2 x cn3), not tiles
+  int xy_split;                    // xy transforms as separate x and y passes (plane beyond LDS)
+  int xpairs, ycols;               // split passes: row pairs / half-spectrum columns per workgroup
   int* sbase;                      // nsub > 1: nsub x ntiles first rank of each copy in its tile
   FinalConsts fin;                 // final-sum constants (updated by esp_set_box)
   // real-space (near) part: cells of perpendicular width >= rc along the cell vectors
@@ -240,6 +242,11 @@ template <typename R>
 size_t lds_fft_xy(const DevPlan<R>& d);
 template <typename R>
 size_t lds_fft_z(const DevPlan<R>& d);
+// Split xy passes: x pass with npb row pairs, y pass with ncol columns per workgroup.
+template <typename R>
+size_t lds_fft_x(const DevPlan<R>& d, int npb);
+template <typename R>
+size_t lds_fft_y(const DevPlan<R>& d, int ncol);
 template <typename R>
 size_t lds_spread(const DevPlan<R>& d);
 // Potential box of the tile-staged gather: (T_d + P - 1) cells per dimension.

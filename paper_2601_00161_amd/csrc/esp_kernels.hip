@@ -320,6 +320,119 @@ __global__ void __launch_bounds__(1024) k_fft_xy_inv(KArg<R, BATCH> ka) {
   }
 }
 
+// ------------------------------------------------- FFT xy, split passes
+// For planes that do not fit one workgroup's LDS the x and y transforms run
+// as separate passes: the x pass on groups of npb row pairs (two real rows as
+// one complex transform, as above), the y pass on groups of ncol adjacent
+// half-spectrum columns of one plane, transformed in place.
+template <typename R>
+__global__ void __launch_bounds__(256) k_fft_x(DevPlan<R> d, const R* __restrict__ grid_in,
+                                              Cplx<R>* __restrict__ spec_in, int clear, int npb) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const R* grid = grid_in ? grid_in : d.rho;
+  Cplx<R>* spec = spec_in ? spec_in : d.spec;
+  const int M1 = d.M1, M2 = d.M2, H = d.H;
+  const int npairs = (M2 + 1) / 2, total = npairs * d.M3;
+  const int q0 = blockIdx.x * npb, np = min(npb, total - q0);
+  Cplx<R>* A = reinterpret_cast<Cplx<R>*>(smem);
+  Cplx<R>* B = A + static_cast<size_t>(npb) * M1;
+  Cplx<R>* tw1 = B + static_cast<size_t>(npb) * M1;
+  const int nth = blockDim.x, tid = threadIdx.x;
+  for (int k = tid; k < M1; k += nth) tw1[k] = d.tw[d.f1.tw + k];
+  R* wgrid = const_cast<R*>(grid);
+  for (int k = tid; k < np * M1; k += nth) {
+    const int j = k / M1, x = k - j * M1;
+    const int q = q0 + j, z = q / npairs, y0 = 2 * (q - z * npairs);
+    const size_t r0 = (static_cast<size_t>(z) * M2 + y0) * M1 + x;
+    const R re = grid[r0];
+    const R im = y0 + 1 < M2 ? grid[r0 + M1] : R(0);
+    A[k] = {re, im};
+    if (clear) {
+      wgrid[r0] = R(0);
+      if (y0 + 1 < M2) wgrid[r0 + M1] = R(0);
+    }
+  }
+  __syncthreads();
+  const Cplx<R>* res = fft_lines(A, B, d.f1, np, M1, 1, tw1, false);
+  for (int k = tid; k < np * H; k += nth) {
+    const int j = k / H, m = k - j * H;
+    const int q = q0 + j, z = q / npairs, y0 = 2 * (q - z * npairs);
+    const Cplx<R> Z = res[j * M1 + m];
+    const Cplx<R> Zm = res[j * M1 + (m == 0 ? 0 : M1 - m)];
+    Cplx<R>* row = spec + (static_cast<size_t>(z) * M2 + y0) * H;
+    row[m] = {R(0.5) * (Z.x + Zm.x), R(0.5) * (Z.y - Zm.y)};
+    if (y0 + 1 < M2) row[H + m] = {R(0.5) * (Z.y + Zm.y), R(0.5) * (Zm.x - Z.x)};
+  }
+}
+
+// block = (component x M3 + plane) x column groups + group
+template <typename R>
+__global__ void __launch_bounds__(256) k_fft_y(DevPlan<R> d, Cplx<R>* __restrict__ spec_in, int ncol, int inverse) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  Cplx<R>* spec = spec_in ? spec_in : d.spec;
+  const int M2 = d.M2, H = d.H;
+  const int ngrp = (H + ncol - 1) / ncol;
+  const int plane = blockIdx.x / ngrp, grp = blockIdx.x - plane * ngrp;
+  const int m0 = grp * ncol, nc = min(ncol, H - m0);
+  Cplx<R>* A = reinterpret_cast<Cplx<R>*>(smem);
+  Cplx<R>* B = A + static_cast<size_t>(ncol) * M2;
+  Cplx<R>* tw2 = B + static_cast<size_t>(ncol) * M2;
+  const int nth = blockDim.x, tid = threadIdx.x;
+  for (int k = tid; k < M2; k += nth) tw2[k] = d.tw[d.f2.tw + k];
+  Cplx<R>* base = spec + static_cast<size_t>(plane) * M2 * H + m0;
+  for (int k = tid; k < M2 * nc; k += nth) {
+    const int y = k / nc, c = k - y * nc;
+    A[k] = base[static_cast<size_t>(y) * H + c];
+  }
+  __syncthreads();
+  const Cplx<R>* res = fft_lines(A, B, d.f2, nc, 1, nc, tw2, inverse != 0);
+  for (int k = tid; k < M2 * nc; k += nth) {
+    const int y = k / nc, c = k - y * nc;
+    base[static_cast<size_t>(y) * H + c] = res[k];
+  }
+}
+
+// inverse x pass (complex-to-real) of component comp = blockIdx.y
+template <typename R>
+__global__ void __launch_bounds__(256) k_fft_x_inv(DevPlan<R> d, int npb) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int M1 = d.M1, M2 = d.M2, H = d.H;
+  const int npairs = (M2 + 1) / 2, total = npairs * d.M3;
+  const int q0 = blockIdx.x * npb, np = min(npb, total - q0);
+  const int comp = blockIdx.y;
+  Cplx<R>* A = reinterpret_cast<Cplx<R>*>(smem);
+  Cplx<R>* B = A + static_cast<size_t>(npb) * M1;
+  Cplx<R>* tw1 = B + static_cast<size_t>(npb) * M1;
+  const int nth = blockDim.x, tid = threadIdx.x;
+  for (int k = tid; k < M1; k += nth) tw1[k] = d.tw[d.f1.tw + k];
+  const Cplx<R>* spec = d.spec + static_cast<size_t>(comp) * d.M3 * M2 * H;
+  R* phi = d.phi + static_cast<size_t>(comp) * d.M3 * M2 * M1;
+  // Hermitian rows a (= row y0) and b (= row y0 + 1): Z[x] = X_a[x] + i X_b[x]
+  for (int k = tid; k < np * M1; k += nth) {
+    const int j = k / M1, x = k - j * M1;
+    const int q = q0 + j, z = q / npairs, y0 = 2 * (q - z * npairs);
+    const bool lo = x < H;
+    const int xs = lo ? x : M1 - x;
+    const Cplx<R>* row = spec + (static_cast<size_t>(z) * M2 + y0) * H;
+    Cplx<R> a = row[xs];
+    Cplx<R> b = y0 + 1 < M2 ? row[H + xs] : Cplx<R>{R(0), R(0)};
+    if (!lo) {
+      a.y = -a.y;
+      b.y = -b.y;
+    }
+    A[k] = {a.x - b.y, a.y + b.x};
+  }
+  __syncthreads();
+  const Cplx<R>* res = fft_lines(A, B, d.f1, np, M1, 1, tw1, true);
+  for (int k = tid; k < np * M1; k += nth) {
+    const int j = k / M1, x = k - j * M1;
+    const int q = q0 + j, z = q / npairs, y0 = 2 * (q - z * npairs);
+    const size_t r0 = (static_cast<size_t>(z) * M2 + y0) * M1 + x;
+    phi[r0] = res[k].x;
+    if (y0 + 1 < M2) phi[r0 + M1] = res[k].y;
+  }
+}
+
 // ------------------------------------------------------------------- FFT z
 template <typename R>
 __device__ __forceinline__ R chebyshev(const R* __restrict__ c, int deg, R z) {
@@ -605,8 +718,32 @@ hipError_t launch_gather(const DevPlan<R>& d, R* f, double* out7, hipStream_t s)
 }
 
 template <typename R>
+size_t lds_fft_x(const DevPlan<R>& d, int npb) {
+  return (2 * static_cast<size_t>(npb) + 1) * d.M1 * sizeof(Cplx<R>);
+}
+
+template <typename R>
+size_t lds_fft_y(const DevPlan<R>& d, int ncol) {
+  return (2 * static_cast<size_t>(ncol) + 1) * d.M2 * sizeof(Cplx<R>);
+}
+
+template <typename R>
 hipError_t launch_fft_xy(const DevPlan<R>& d, const R* grid, Cplx<R>* spec, bool clear_input,
                          hipStream_t s) {
+  if (d.xy_split) {
+    const int total = (d.M2 + 1) / 2 * d.M3;
+    size_t lds = lds_fft_x(d, d.xpairs);
+    allow_lds(reinterpret_cast<const void*>(&k_fft_x<R>), lds);
+    hipLaunchKernelGGL(k_fft_x<R>, dim3((total + d.xpairs - 1) / d.xpairs), dim3(256), lds, s, d, grid, spec,
+                       clear_input ? 1 : 0, d.xpairs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    lds = lds_fft_y(d, d.ycols);
+    allow_lds(reinterpret_cast<const void*>(&k_fft_y<R>), lds);
+    hipLaunchKernelGGL(k_fft_y<R>, dim3(d.M3 * ((d.H + d.ycols - 1) / d.ycols)), dim3(256), lds, s, d, spec,
+                       d.ycols, 0);
+    return hipGetLastError();
+  }
   const size_t lds = lds_fft_xy(d);
   allow_lds(reinterpret_cast<const void*>(&k_fft_xy<R, false>), lds);
   const int nth = fft_threads(d.M1 * d.M2);
@@ -617,6 +754,20 @@ hipError_t launch_fft_xy(const DevPlan<R>& d, const R* grid, Cplx<R>* spec, bool
 
 template <typename R>
 hipError_t launch_fft_xy_inv(const DevPlan<R>& d, int ncomp, hipStream_t s) {
+  if (d.xy_split) {
+    size_t lds = lds_fft_y(d, d.ycols);
+    allow_lds(reinterpret_cast<const void*>(&k_fft_y<R>), lds);
+    hipLaunchKernelGGL(k_fft_y<R>, dim3(ncomp * d.M3 * ((d.H + d.ycols - 1) / d.ycols)), dim3(256), lds, s, d,
+                       static_cast<Cplx<R>*>(nullptr), d.ycols, 1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int total = (d.M2 + 1) / 2 * d.M3;
+    lds = lds_fft_x(d, d.xpairs);
+    allow_lds(reinterpret_cast<const void*>(&k_fft_x_inv<R>), lds);
+    hipLaunchKernelGGL(k_fft_x_inv<R>, dim3((total + d.xpairs - 1) / d.xpairs, ncomp), dim3(256), lds, s, d,
+                       d.xpairs);
+    return hipGetLastError();
+  }
   const size_t lds = lds_fft_xy(d);
   allow_lds(reinterpret_cast<const void*>(&k_fft_xy_inv<R, false>), lds);
   const int nth = fft_threads(d.M1 * d.M2);
@@ -722,6 +873,8 @@ hipError_t launch_fill(T* p, size_t count, hipStream_t s) {
   template hipError_t launch_finalize_batch<R>(const BatchLaunch<R>&, double*, hipStream_t);  \
   template hipError_t launch_fill<R>(R*, size_t, hipStream_t);                                \
   template size_t lds_fft_xy<R>(const DevPlan<R>&);                                           \
+  template size_t lds_fft_x<R>(const DevPlan<R>&, int);                                       \
+  template size_t lds_fft_y<R>(const DevPlan<R>&, int);                                       \
   template size_t lds_fft_z<R>(const DevPlan<R>&);                                            \
   template size_t lds_spread<R>(const DevPlan<R>&);                                           \
   template size_t lds_gather_box<R>(const DevPlan<R>&);

@@ -40,6 +40,7 @@ struct Resolved {
   int gather = ESP_GATHER_AUTO;
   int force = ESP_FORCE_AD;
   int local = 0;
+  int fft_split = 0;
   double pred[4] = {0, 0, 0, 0};
   double pred_cost = 0;
 };
@@ -287,6 +288,7 @@ esp_status resolve(const double* h, int64_t n, double tol, const esp_opts* o, Re
   }
   r.force = o->force;
   r.local = o->local_virial ? 1 : 0;
+  r.fft_split = o->fft_split ? 1 : 0;
   std::memcpy(r.h, h, 9 * sizeof(double));
   esp_status st = check_box(h, r.rc, r.hinv, &r.V, err);
   if (st != ESP_OK) return st;
@@ -687,7 +689,15 @@ esp_status build_device(esp_plan_t* p) {
   int dev_id = 0, maxlds = 65536;
   if (hipGetDevice(&dev_id) == hipSuccess)
     (void)hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev_id);
-  const size_t need[3] = {lds_fft_xy(d), lds_fft_z(d), lds_spread(d)};
+  // xy transforms: one workgroup per plane when the plane fits in LDS, else
+  // separate x and y passes with as many row pairs / columns per workgroup
+  // (up to 16) as fit
+  d.xy_split = r.fft_split || lds_fft_xy(d) > static_cast<size_t>(maxlds) ? 1 : 0;
+  d.xpairs = d.ycols = 16;
+  while (d.xpairs > 1 && lds_fft_x(d, d.xpairs) > static_cast<size_t>(maxlds)) d.xpairs /= 2;
+  while (d.ycols > 1 && lds_fft_y(d, d.ycols) > static_cast<size_t>(maxlds)) d.ycols /= 2;
+  const size_t need_xy = d.xy_split ? std::max(lds_fft_x(d, d.xpairs), lds_fft_y(d, d.ycols)) : lds_fft_xy(d);
+  const size_t need[3] = {need_xy, lds_fft_z(d), lds_spread(d)};
   const char* what[3] = {"xy-plane FFT", "z-column FFT", "spreading tile"};
   for (int k = 0; k < 3; ++k)
     if (need[k] > static_cast<size_t>(maxlds)) {
@@ -1092,6 +1102,7 @@ esp_status esp_get_params(const esp_plan_t* p, esp_params* out) {
     out->real_cells[1] = f32 ? p->d32.cn2 : p->d64.cn2;
     out->real_cells[2] = f32 ? p->d32.cn3 : p->d64.cn3;
     out->real_segments = p->nseg;
+    out->fft_split = f32 ? p->d32.xy_split : p->d64.xy_split;
   }
   return ESP_OK;
 }
@@ -1371,6 +1382,11 @@ esp_status batch_build(esp_batch_t* b) {
   const int nrep = b->nrep;
   std::vector<DevPlan<R>> hp(nrep);
   for (int k = 0; k < nrep; ++k) hp[k] = batch_entry<R>(b, b->order[k]);
+  for (int k = 0; k < nrep; ++k)
+    if (hp[k].xy_split) {
+      b->err = "a replica's grid plane exceeds one workgroup's LDS; batched launches need the one-pass xy transform";
+      return ESP_EINVAL;
+    }
   std::vector<int> offs;
   auto make = [&](BatchStage& st, int first, int count, auto nblk_of, auto lds_of, int nth) {
     st.first = first;

@@ -150,9 +150,10 @@ def test_set_box_equals_a_new_plan():
 
 
 def test_grid_beyond_lds_is_rejected():
-    """A plane too large for one workgroup's LDS is an error at plan time (FP64
-    plane of 135 x 135), not a failed launch."""
+    """A z column too long for one workgroup's LDS is an error at plan time
+    (FP64, 12,000 points), not a failed launch.  (Planes too large for LDS
+    take the split x / y passes instead; see test_gpu_fft_split.py.)"""
     h = np.diag([25.0, 25.0, 20.0])
     with pytest.raises(esp.EspError) as ei:
-        esp.Plan(h, 1000, 1e-5, precision="fp64", c_split=14.0, P=6, M=(135, 135, 108))
+        esp.Plan(h, 1000, 1e-5, precision="fp64", c_split=14.0, P=6, M=(8, 8, 12000))
     assert ei.value.status == esp.ESP_EINVAL
