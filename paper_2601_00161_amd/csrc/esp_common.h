@@ -149,17 +149,19 @@ __device__ __forceinline__ int fast_div(int a, int b, float rb, int& rem) {
 // threads take adjacent elements of a line when elements are contiguous
 // (estride 1), else adjacent lines (lstride 1), so LDS accesses stay
 // unit-stride and free of bank conflicts either way.
+// nth: threads of the workgroup (passed in, so that no stage re-reads the
+// workgroup size from the dispatch packet).
 template <typename R, int RAD>
 __device__ void fft_stage(const Cplx<R>* __restrict__ in, Cplx<R>* __restrict__ out, int n, int Ns,
                           int nlines, int lstride, int estride, const Cplx<R>* __restrict__ tw,
-                          R sgn) {
+                          R sgn, int nth) {
   const int nb = n / RAD;
   const int total = nlines * nb;
   const int tunit = n / (Ns * RAD);
   const bool by_line = estride != 1;
   const int inner = by_line ? nlines : nb;
   const float rin = 1.0f / static_cast<float>(inner), rns = 1.0f / static_cast<float>(Ns);
-  for (int id = threadIdx.x; id < total; id += blockDim.x) {
+  for (int id = threadIdx.x; id < total; id += nth) {
     int rem, j;
     const int q = fast_div(id, inner, rin, rem);
     const int line = by_line ? rem : q;
@@ -189,19 +191,19 @@ __device__ void fft_stage(const Cplx<R>* __restrict__ in, Cplx<R>* __restrict__ 
 // All stages; ping-pongs between a and b and returns the buffer holding the result.
 template <typename R>
 __device__ Cplx<R>* fft_lines(Cplx<R>* a, Cplx<R>* b, const FftLen& f, int nlines, int lstride,
-                              int estride, const Cplx<R>* tw, bool inverse) {
+                              int estride, const Cplx<R>* tw, bool inverse, int nth) {
   const R sgn = inverse ? R(1) : R(-1);
   int Ns = 1;
   Cplx<R>* in = a;
   Cplx<R>* out = b;
   for (int s = 0; s < f.nstage; ++s) {
     switch (f.rad[s]) {
-      case 2: fft_stage<R, 2>(in, out, f.n, Ns, nlines, lstride, estride, tw, sgn); break;
-      case 3: fft_stage<R, 3>(in, out, f.n, Ns, nlines, lstride, estride, tw, sgn); break;
-      case 4: fft_stage<R, 4>(in, out, f.n, Ns, nlines, lstride, estride, tw, sgn); break;
-      case 5: fft_stage<R, 5>(in, out, f.n, Ns, nlines, lstride, estride, tw, sgn); break;
-      case 6: fft_stage<R, 6>(in, out, f.n, Ns, nlines, lstride, estride, tw, sgn); break;
-      default: fft_stage<R, 8>(in, out, f.n, Ns, nlines, lstride, estride, tw, sgn); break;
+      case 2: fft_stage<R, 2>(in, out, f.n, Ns, nlines, lstride, estride, tw, sgn, nth); break;
+      case 3: fft_stage<R, 3>(in, out, f.n, Ns, nlines, lstride, estride, tw, sgn, nth); break;
+      case 4: fft_stage<R, 4>(in, out, f.n, Ns, nlines, lstride, estride, tw, sgn, nth); break;
+      case 5: fft_stage<R, 5>(in, out, f.n, Ns, nlines, lstride, estride, tw, sgn, nth); break;
+      case 6: fft_stage<R, 6>(in, out, f.n, Ns, nlines, lstride, estride, tw, sgn, nth); break;
+      default: fft_stage<R, 8>(in, out, f.n, Ns, nlines, lstride, estride, tw, sgn, nth); break;
     }
     Ns *= f.rad[s];
     Cplx<R>* t = in;

@@ -241,24 +241,47 @@ __global__ void __launch_bounds__(1024) k_fft_xy(KArg<R, BATCH> ka, const R* __r
   Cplx<R>* tw1 = B + L;
   Cplx<R>* tw2 = tw1 + M1;
   const int nth = blockDim.x, tid = threadIdx.x;
-  for (int k = tid; k < M1; k += nth) tw1[k] = d.tw[d.f1.tw + k];
-  for (int k = tid; k < M2; k += nth) tw2[k] = d.tw[d.f2.tw + k];
   const size_t zoff = static_cast<size_t>(blk) * M2 * M1;
   const R* plane = grid + zoff;
   R* wplane = const_cast<R*>(grid) + zoff;
-  for (int k = tid; k < npairs * M1; k += nth) {
-    const int p = k / M1, x = k - p * M1;
-    const int y0 = 2 * p;
-    const R re = plane[y0 * M1 + x];
-    const R im = y0 + 1 < M2 ? plane[(y0 + 1) * M1 + x] : R(0);
-    A[k] = {re, im};
-    if (clear) {
-      wplane[y0 * M1 + x] = R(0);
-      if (y0 + 1 < M2) wplane[(y0 + 1) * M1 + x] = R(0);
+  // The plane in rounds of U loads per thread, issued before their stores;
+  // the first round is straight-line code together with the twiddle loads,
+  // so that all of them are in flight at once (indices clamped: no branches).
+  constexpr int U = 4;
+  auto round = [&](int k0) {
+    R re[U], im[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = min(k0 + u * nth, npairs * M1 - 1);
+      const int p = k / M1, x = k - p * M1;
+      const int y0 = 2 * p;
+      re[u] = plane[y0 * M1 + x];
+      im[u] = plane[min(y0 + 1, M2 - 1) * M1 + x];
     }
-  }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + u * nth;
+      if (k < npairs * M1) {
+        const int p = k / M1, x = k - p * M1;
+        const int y0 = 2 * p;
+        A[k] = {re[u], y0 + 1 < M2 ? im[u] : R(0)};
+        if (clear) {
+          wplane[y0 * M1 + x] = R(0);
+          if (y0 + 1 < M2) wplane[(y0 + 1) * M1 + x] = R(0);
+        }
+      }
+    }
+  };
+  const Cplx<R> tv1 = d.tw[d.f1.tw + min(tid, M1 - 1)];
+  const Cplx<R> tv2 = d.tw[d.f2.tw + min(tid, M2 - 1)];
+  round(tid);
+  for (int k0 = tid + U * nth; k0 < npairs * M1; k0 += U * nth) round(k0);
+  if (tid < M1) tw1[tid] = tv1;
+  if (tid < M2) tw2[tid] = tv2;
+  for (int k = tid + nth; k < M1; k += nth) tw1[k] = d.tw[d.f1.tw + k];
+  for (int k = tid + nth; k < M2; k += nth) tw2[k] = d.tw[d.f2.tw + k];
   __syncthreads();
-  Cplx<R>* res = fft_lines(A, B, d.f1, npairs, M1, 1, tw1, false);
+  Cplx<R>* res = fft_lines(A, B, d.f1, npairs, M1, 1, tw1, false, nth);
   Cplx<R>* oth = res == A ? B : A;
   // rows 2p (real part) and 2p+1 (imaginary part) were transformed together:
   // X_a[k] = (Z[k] + conj Z[-k]) / 2,  X_b[k] = (Z[k] - conj Z[-k]) / (2 i)
@@ -270,7 +293,7 @@ __global__ void __launch_bounds__(1024) k_fft_xy(KArg<R, BATCH> ka, const R* __r
     if (2 * p + 1 < M2) oth[(2 * p + 1) * H + m] = {R(0.5) * (Z.y + Zm.y), R(0.5) * (Zm.x - Z.x)};
   }
   __syncthreads();
-  res = fft_lines(oth, res, d.f2, H, 1, H, tw2, false);
+  res = fft_lines(oth, res, d.f2, H, 1, H, tw2, false, nth);
   Cplx<R>* out = spec + static_cast<size_t>(blk) * M2 * H;
   for (int k = tid; k < M2 * H; k += nth) out[k] = res[k];
 }
@@ -288,14 +311,31 @@ __global__ void __launch_bounds__(1024) k_fft_xy_inv(KArg<R, BATCH> ka) {
   Cplx<R>* tw1 = B + L;
   Cplx<R>* tw2 = tw1 + M1;
   const int nth = blockDim.x, tid = threadIdx.x;
-  for (int k = tid; k < M1; k += nth) tw1[k] = d.tw[d.f1.tw + k];
-  for (int k = tid; k < M2; k += nth) tw2[k] = d.tw[d.f2.tw + k];
+  const Cplx<R> tv1 = d.tw[d.f1.tw + min(tid, M1 - 1)];
+  const Cplx<R> tv2 = d.tw[d.f2.tw + min(tid, M2 - 1)];
   // block = component * M3 + plane
   const int comp = blk / d.M3, zp = blk - comp * d.M3;
   const Cplx<R>* in = d.spec + static_cast<size_t>(comp) * d.M3 * M2 * H + static_cast<size_t>(zp) * M2 * H;
-  for (int k = tid; k < M2 * H; k += nth) A[k] = in[k];
+  {
+    // as in the forward pass: the first round straight-line with the twiddle loads
+    constexpr int U = 4;
+    auto round = [&](int k0) {
+      Cplx<R> v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = in[min(k0 + u * nth, M2 * H - 1)];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (k0 + u * nth < M2 * H) A[k0 + u * nth] = v[u];
+    };
+    round(tid);
+    for (int k0 = tid + U * nth; k0 < M2 * H; k0 += U * nth) round(k0);
+  }
+  if (tid < M1) tw1[tid] = tv1;
+  if (tid < M2) tw2[tid] = tv2;
+  for (int k = tid + nth; k < M1; k += nth) tw1[k] = d.tw[d.f1.tw + k];
+  for (int k = tid + nth; k < M2; k += nth) tw2[k] = d.tw[d.f2.tw + k];
   __syncthreads();
-  Cplx<R>* res = fft_lines(A, B, d.f2, H, 1, H, tw2, true);
+  Cplx<R>* res = fft_lines(A, B, d.f2, H, 1, H, tw2, true, nth);
   Cplx<R>* oth = res == A ? B : A;
   // Hermitian rows a (= row 2p) and b (= row 2p+1): Z[x] = X_a[x] + i X_b[x]
   for (int k = tid; k < npairs * M1; k += nth) {
@@ -311,7 +351,7 @@ __global__ void __launch_bounds__(1024) k_fft_xy_inv(KArg<R, BATCH> ka) {
     oth[k] = {a.x - b.y, a.y + b.x};
   }
   __syncthreads();
-  res = fft_lines(oth, res, d.f1, npairs, M1, 1, tw1, true);
+  res = fft_lines(oth, res, d.f1, npairs, M1, 1, tw1, true, nth);
   R* plane = d.phi + static_cast<size_t>(comp) * d.M3 * M2 * M1 + static_cast<size_t>(zp) * M2 * M1;
   for (int k = tid; k < npairs * M1; k += nth) {
     const int p = k / M1, x = k - p * M1;
@@ -353,7 +393,7 @@ __global__ void __launch_bounds__(256) k_fft_x(DevPlan<R> d, const R* __restrict
     }
   }
   __syncthreads();
-  const Cplx<R>* res = fft_lines(A, B, d.f1, np, M1, 1, tw1, false);
+  const Cplx<R>* res = fft_lines(A, B, d.f1, np, M1, 1, tw1, false, nth);
   for (int k = tid; k < np * H; k += nth) {
     const int j = k / H, m = k - j * H;
     const int q = q0 + j, z = q / npairs, y0 = 2 * (q - z * npairs);
@@ -385,7 +425,7 @@ __global__ void __launch_bounds__(256) k_fft_y(DevPlan<R> d, Cplx<R>* __restrict
     A[k] = base[static_cast<size_t>(y) * H + c];
   }
   __syncthreads();
-  const Cplx<R>* res = fft_lines(A, B, d.f2, nc, 1, nc, tw2, inverse != 0);
+  const Cplx<R>* res = fft_lines(A, B, d.f2, nc, 1, nc, tw2, inverse != 0, nth);
   for (int k = tid; k < M2 * nc; k += nth) {
     const int y = k / nc, c = k - y * nc;
     base[static_cast<size_t>(y) * H + c] = res[k];
@@ -423,7 +463,7 @@ __global__ void __launch_bounds__(256) k_fft_x_inv(DevPlan<R> d, int npb) {
     A[k] = {a.x - b.y, a.y + b.x};
   }
   __syncthreads();
-  const Cplx<R>* res = fft_lines(A, B, d.f1, np, M1, 1, tw1, true);
+  const Cplx<R>* res = fft_lines(A, B, d.f1, np, M1, 1, tw1, true, nth);
   for (int k = tid; k < np * M1; k += nth) {
     const int j = k / M1, x = k - j * M1;
     const int q = q0 + j, z = q / npairs, y0 = 2 * (q - z * npairs);
@@ -481,19 +521,40 @@ __global__ void __launch_bounds__(256) k_fft_z(KArg<R, BATCH> ka, int mode) {
   R* fw = kg + d.nker + 1;                                         // Z_LOCAL: F_hat / (2 V W_hat^2)
   R* bw = fw + (mode == Z_LOCAL ? cz * M3 : 0);                    //          beta / (2 V W_hat^2)
   const int nth = blockDim.x, tid = threadIdx.x;
-  for (int k = tid; k < M3; k += nth) tw3[k] = d.tw[d.f3.tw + k];
-  for (int k = tid; k <= d.nker; k += nth) {
+  const size_t colstride = static_cast<size_t>(M2) * H;
+  Cplx<R>* col = d.spec + static_cast<size_t>(y) * H + k0;
+  // prologue: the column, twiddle and kernel-table loads are all issued
+  // before the first LDS store, so their round trips overlap
+  // (indices are clamped so that the loads need no branches)
+  constexpr int U = 4;
+  Cplx<R> cv[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int k = min(tid + u * nth, nc * M3 - 1);
+    const int z = k / nc, c = k - z * nc;
+    cv[u] = col[z * colstride + c];
+  }
+  const Cplx<R> twv = d.tw[d.f3.tw + min(tid, M3 - 1)];
+  const R kfv = d.kerf[min(tid, d.nker)], kgv = d.kerg[min(tid, d.nker)];
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (tid + u * nth < nc * M3) A[tid + u * nth] = cv[u];
+  if (tid < M3) tw3[tid] = twv;
+  if (tid <= d.nker) {
+    kf[tid] = kfv;
+    kg[tid] = kgv;
+  }
+  for (int k = tid + nth; k < M3; k += nth) tw3[k] = d.tw[d.f3.tw + k];
+  for (int k = tid + nth; k <= d.nker; k += nth) {
     kf[k] = d.kerf[k];
     kg[k] = d.kerg[k];
   }
-  const size_t colstride = static_cast<size_t>(M2) * H;
-  Cplx<R>* col = d.spec + static_cast<size_t>(y) * H + k0;
-  for (int k = tid; k < nc * M3; k += nth) {
+  for (int k = tid + U * nth; k < nc * M3; k += nth) {
     const int z = k / nc, c = k - z * nc;
     A[k] = col[z * colstride + c];
   }
   __syncthreads();
-  Cplx<R>* res = fft_lines(A, B, d.f3, nc, 1, nc, tw3, false);
+  Cplx<R>* res = fft_lines(A, B, d.f3, nc, 1, nc, tw3, false, nth);
   if (mode == Z_FFT_ONLY) {
     for (int k = tid; k < nc * M3; k += nth) {
       const int z = k / nc, c = k - z * nc;
@@ -555,7 +616,7 @@ __global__ void __launch_bounds__(256) k_fft_z(KArg<R, BATCH> ka, int mode) {
   __syncthreads();
   Cplx<R>* oth = res == A ? B : A;
   if (mode == Z_POTENTIAL) {
-    res = fft_lines(res, oth, d.f3, nc, 1, nc, tw3, true);
+    res = fft_lines(res, oth, d.f3, nc, 1, nc, tw3, true, nth);
     for (int k = tid; k < nc * M3; k += nth) {
       const int z = k / nc, c = k - z * nc;
       col[z * colstride + c] = res[k];
@@ -592,7 +653,7 @@ __global__ void __launch_bounds__(256) k_fft_z(KArg<R, BATCH> ka, int mode) {
       }
     }
     __syncthreads();
-    Cplx<R>* out = fft_lines(C, oth, d.f3, nc, 1, nc, tw3, true);
+    Cplx<R>* out = fft_lines(C, oth, d.f3, nc, 1, nc, tw3, true, nth);
     Cplx<R>* dst = col + a * S;
     for (int k = tid; k < nc * M3; k += nth) {
       const int z = k / nc, c = k - z * nc;
