@@ -65,14 +65,16 @@ __global__ void __launch_bounds__(256) k_bin(KArg<R, BATCH> ka, const R* __restr
   xyz += 3 * d.pofs;
   q += d.pofs;
   const bool lh = d.bin_lds != 0;
+  const int64_t i = static_cast<int64_t>(blk) * blockDim.x + threadIdx.x;
+  // inputs fetched first; the histogram is cleared while they arrive
+  const int64_t ii = i < d.n ? i : 0;
+  R x = xyz[3 * ii], y = xyz[3 * ii + 1], z = xyz[3 * ii + 2], qi = q[ii];
   if (lh)
     for (int k = threadIdx.x; k < d.ntiles; k += blockDim.x) hist[k] = 0;
   __syncthreads();
-  const int64_t i = static_cast<int64_t>(blk) * blockDim.x + threadIdx.x;
   double v[2] = {0.0, 0.0};
   int key = 0, lr = 0;
   if (i < d.n) {
-    R x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2], qi = q[i];
     if (!(finite_r(x) && finite_r(y) && finite_r(z) && finite_r(qi))) {
       atomicOr(d.flags, 1);
       x = y = z = qi = R(0);
@@ -200,11 +202,16 @@ __global__ void __launch_bounds__(1024) k_scatter(KArg<R, BATCH> ka) {
     }
     return;
   }
+  // the particle's key, rank and record are fetched before the scan, so
+  // their round trip overlaps it
+  const int64_t ii = i < d.n ? i : 0;
+  const int key = d.keys[ii], rank = d.ranks[ii];
+  const Record<R> rec = d.tmp[ii];
   block_scan(d.counts, offs, d.ntiles, part);
   if (i < d.n) {
-    const int pos = offs[d.keys[i]] + d.ranks[i];
+    const int pos = offs[key] + rank;
     if (pos >= 0 && pos < d.n) {
-      d.sorted[pos] = d.tmp[i];
+      d.sorted[pos] = rec;
       d.perm[pos] = static_cast<int>(i);
     } else {
       atomicOr(d.flags, 2);                 // inconsistent tile counts

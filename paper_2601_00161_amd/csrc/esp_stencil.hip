@@ -72,6 +72,7 @@ __global__ void __launch_bounds__(256) k_spread(KArg<R, BATCH> ka) {
   R* win = wts + kSpreadChunk * 3 * P;               // (NW + 1) x P
   int* base = reinterpret_cast<int*>(win + (NW + 1) * P);   // kSpreadChunk x 3
   const int start = d.offsets[tile], end = d.offsets[tile + 1];
+  const R wv = d.win[min(static_cast<int>(threadIdx.x), (NW + 1) * P - 1)];   // in flight with the offsets
   if (threadIdx.x == 0) d.counts[tile] = 0;        // ready for the next binning pass
   if (start == end) return;
   // one weight task per (particle, dimension) of a chunk: kSpreadChunk x 3 <=
@@ -82,7 +83,8 @@ __global__ void __launch_bounds__(256) k_spread(KArg<R, BATCH> ka) {
   Record<R> rec;
   if (threadIdx.x < min(kSpreadChunk, end - start) * 3) rec = d.sorted[start + tj];
   for (int k = threadIdx.x; k < ncell; k += blockDim.x) grid[k] = 0.0;
-  for (int k = threadIdx.x; k < (NW + 1) * P; k += blockDim.x) win[k] = d.win[k];
+  if (static_cast<int>(threadIdx.x) < (NW + 1) * P) win[threadIdx.x] = wv;
+  for (int k = threadIdx.x + blockDim.x; k < (NW + 1) * P; k += blockDim.x) win[k] = d.win[k];
   __syncthreads();
   for (int c0 = start; c0 < end; c0 += kSpreadChunk) {
     const int nc = min(kSpreadChunk, end - c0);
@@ -445,23 +447,40 @@ __global__ void __launch_bounds__(256) k_gather_tile(KArg<R, BATCH> ka, R* __res
   R* win = reinterpret_cast<R*>(smem);                // (NW + 1) x P
   R* wt = win + (NW + 1) * P;                         // G x 6 x P: w1 d1 w2 d2 w3 d3
   R* box = wt + G * 6 * P;                            // E1 x E2 x E3 potential values
-  const int start = d.offsets[tile], end = d.offsets[tile + 1];
-  if (start == end) return;
   const int tid = threadIdx.x, nth = blockDim.x;
   const int t1 = tile % d.nt1, t2 = (tile / d.nt1) % d.nt2, t3 = tile / (d.nt1 * d.nt2);
   const int o1 = t1 * d.T1, o2 = t2 * d.T2, o3 = t3 * d.T3;
   const int E1 = min(d.T1, d.M1 - o1) + P - 1;
   const int E2 = min(d.T2, d.M2 - o2) + P - 1;
   const int E3 = min(d.T3, d.M3 - o3) + P - 1;
-  for (int k = tid; k < (NW + 1) * P; k += nth) win[k] = d.win[k];
-  for (int k = tid; k < E1 * E2 * E3; k += nth) {
+  const int nbox = E1 * E2 * E3;
+  // the offsets, the window table and the potential box are fetched in rounds
+  // of U loads per thread, the first together with the offsets (clamped
+  // indices: no branches)
+  constexpr int U = 4;
+  auto box_at = [&](int k) {
     const int x = k % E1, y = (k / E1) % E2, z = k / (E1 * E2);
     int gx = o1 + x, gy = o2 + y, gz = o3 + z;
     gx -= gx >= d.M1 ? d.M1 : 0;
     gy -= gy >= d.M2 ? d.M2 : 0;
     gz -= gz >= d.M3 ? d.M3 : 0;
-    box[k] = d.phi[(static_cast<size_t>(gz) * d.M2 + gy) * d.M1 + gx];
-  }
+    return d.phi[(static_cast<size_t>(gz) * d.M2 + gy) * d.M1 + gx];
+  };
+  auto round = [&](int k0) {
+    R v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = box_at(min(k0 + u * nth, nbox - 1));
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (k0 + u * nth < nbox) box[k0 + u * nth] = v[u];
+  };
+  const int start = d.offsets[tile], end = d.offsets[tile + 1];
+  const R wv = d.win[min(tid, (NW + 1) * P - 1)];
+  round(tid);
+  if (start == end) return;
+  if (tid < (NW + 1) * P) win[tid] = wv;
+  for (int k = tid + nth; k < (NW + 1) * P; k += nth) win[k] = d.win[k];
+  for (int k0 = tid + U * nth; k0 < nbox; k0 += U * nth) round(k0);
   const int grp = tid / L, lane = tid - grp * L;
   R* my = wt + grp * 6 * P;
   for (int base = start; base < end; base += G) {
