@@ -14,7 +14,11 @@ beside it on the same input.  The CPU leg runs the oracle: the baseline
 timing, parity at identical parameters, and the error of every GPU result
 against an exact reference.
 
-Prints ONE JSON line.  See DESIGN.md for the byte model behind "roofline".
+Prints ONE JSON line.  Its "roofline" object rates the dominant kernel by
+algorithmic bytes per launch (stage_bytes below: e.g. spreading reads 16 B
+per particle record and writes 4 B per grid point) over its live launch
+time, against the 8 TB/s HBM peak, next to the HBM traffic measured by the
+FETCH_SIZE / WRITE_SIZE counter passes recorded under profiles/.
 """
 from __future__ import annotations
 
@@ -235,8 +239,8 @@ def main():
                          "kernel that calibrates the FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU decomposition is described in DESIGN.md but not built.", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); the slab decomposition "
+              "over several GPUs is designed but not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch
