@@ -28,21 +28,27 @@ __device__ __forceinline__ void eval_window(const R* __restrict__ win, R tau, R*
     for (int p = 0; p < P; ++p) w[p] = w[p] * tau + win[j * P + p];
 }
 
-// Values and tau-derivatives (= derivatives in grid units).
-template <typename R, int P, int NW>
-__device__ __forceinline__ void eval_window_d(const R* __restrict__ win, R tau, R* w, R* dw) {
+// The 3 P window values and derivatives of one particle, shared out over its
+// L lanes (polynomial k = lane, lane + L, ...: dimension k / P, point k % P),
+// stored as my[2 d P + p] (value) and my[(2 d + 1) P + p] (derivative).
+template <typename R, int P, int NW, int L>
+__device__ __forceinline__ void window_d_lanes(const R* __restrict__ win, R t1, R t2, R t3, int lane, R* my) {
 #pragma unroll
-  for (int p = 0; p < P; ++p) {
-    w[p] = win[NW * P + p];
-    dw[p] = R(0);
-  }
+  for (int r = 0; r < (3 * P + L - 1) / L; ++r) {
+    const int k = lane + r * L;
+    if (k < 3 * P) {
+      const int dim = k / P, p = k - dim * P;
+      const R tau = dim == 0 ? t1 : (dim == 1 ? t2 : t3);
+      R v = win[NW * P + p], dv = R(0);
 #pragma unroll
-  for (int j = NW - 1; j >= 0; --j)
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-      dw[p] = dw[p] * tau + w[p];
-      w[p] = w[p] * tau + win[j * P + p];
+      for (int j = NW - 1; j >= 0; --j) {
+        dv = dv * tau + v;
+        v = v * tau + win[j * P + p];
+      }
+      my[2 * dim * P + p] = v;
+      my[(2 * dim + 1) * P + p] = dv;
     }
+  }
 }
 
 // ----------------------------------------------------------------- spread
@@ -187,16 +193,7 @@ __global__ void __launch_bounds__(256) k_gather(KArg<R, BATCH> ka, R* __restrict
   Coord<R>::stencil(rec, 1, d.M2, P, g2, t2);
   Coord<R>::stencil(rec, 2, d.M3, P, g3, t3);
   R* my = wt + grp * 6 * P;
-  if (lane < 3) {
-    const R tau = lane == 0 ? t1 : (lane == 1 ? t2 : t3);
-    R w[P], dw[P];
-    eval_window_d<R, P, NW>(win, tau, w, dw);
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-      my[2 * lane * P + p] = w[p];
-      my[(2 * lane + 1) * P + p] = dw[p];
-    }
-  }
+  window_d_lanes<R, P, NW, L>(win, t1, t2, t3, lane, my);
   __syncthreads();
   R gx = R(0), gy = R(0), gz = R(0);
   if (lane < P) {
@@ -494,16 +491,7 @@ __global__ void __launch_bounds__(256) k_gather_tile(KArg<R, BATCH> ka, R* __res
     Coord<R>::stencil(rec, 1, d.M2, P, g2, u2);
     Coord<R>::stencil(rec, 2, d.M3, P, g3, u3);
     __syncthreads();                                  // box staged / previous round done with wt
-    if (lane < 3) {
-      const R tau = lane == 0 ? u1 : (lane == 1 ? u2 : u3);
-      R w[P], dw[P];
-      eval_window_d<R, P, NW>(win, tau, w, dw);
-#pragma unroll
-      for (int p = 0; p < P; ++p) {
-        my[2 * lane * P + p] = w[p];
-        my[(2 * lane + 1) * P + p] = dw[p];
-      }
-    }
+    window_d_lanes<R, P, NW, L>(win, u1, u2, u3, lane, my);
     __syncthreads();
     // the base lies in this tile: box-local base = g0 - o (no wrap)
     const int b1 = g1 - o1, b2 = g2 - o2, b3 = g3 - o3;
