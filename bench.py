@@ -343,6 +343,10 @@ def main():
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
+    # pressure-only path (energy and virial from one forward FFT, no forces)
+    o_ev = torch.empty(7, dtype=torch.float64, device=dev)
+    dt_ev = timed(lambda: p32.energy_virial(x32, c32, out7=o_ev))
+
     f_near = torch.empty_like(f32)
     o_near = torch.empty(7, dtype=torch.float64, device=dev)
     dt_near = timed(lambda: p32.real_space(x32, c32, f=f_near, out7=o_near))
@@ -419,6 +423,8 @@ def main():
         "ik_forces_fp32": {"value": round(N * args.steps / dtik / 1e6, 3), "ms_per_step": dtik / args.steps * 1e3,
                            "net_force_over_rms": float(np.linalg.norm(fik.double().sum(0).cpu().numpy())
                                                        / np.sqrt(np.sum(fik.double().cpu().numpy() ** 2)))},
+        "energy_virial_fp32": {"value": round(N * args.steps / dt_ev / 1e6, 3), "unit": "M particle-steps/s",
+                               "ms_per_step": dt_ev / args.steps * 1e3},
         "real_space": {"unit": "M particle-steps/s", "cells": prm["real_cells"], "rc": prm["rc"],
                        "fp32": {"value": round(N * args.steps / dt_near / 1e6, 3),
                                 "ms_per_step": dt_near / args.steps * 1e3},
