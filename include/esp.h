@@ -203,6 +203,22 @@ esp_status esp_real_space(esp_plan_t *p, const float *xyz, const float *q, float
 esp_status esp_real_space_f64(esp_plan_t *p, const double *xyz, const double *q, double *f,
                               int accumulate, double *out7);
 
+/* Total Coulomb interaction of the split (Sec. 3.2, eq. splitting: near
+ * part plus Fourier part, whose out7 carries the self term; forces as in
+ * eq. Fc): f is overwritten with the esp_forces forces
+ * plus the esp_real_space forces, and out7 with the sum of the two parts'
+ * energy and virial, i.e. the result of esp_forces followed by
+ * esp_real_space with accumulate != 0, up to the rounding of the final
+ * additions.  The real-space part runs on a second stream of the plan
+ * (created on the first call, default priority, forked from and joined back
+ * to the plan's stream by events) at the same time as the Fourier part; it
+ * sorts into buffers of its own, so the two never write the same memory.
+ * The call is asynchronous like the others: later work on the plan's stream
+ * sees the complete result.  Device pointers: xyz 3n, q n, f 3n, out7 7
+ * doubles (neither may be NULL). */
+esp_status esp_coulomb(esp_plan_t *p, const float *xyz, const float *q, float *f, double *out7);
+esp_status esp_coulomb_f64(esp_plan_t *p, const double *xyz, const double *q, double *f, double *out7);
+
 /* Synchronise the plan's stream and report device-side errors
  * (ESP_ENONFINITE) seen since the last check; clears the flag. */
 esp_status esp_check(esp_plan_t *p);

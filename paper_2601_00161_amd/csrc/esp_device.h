@@ -127,6 +127,16 @@ struct DevPlan {
   R* fpart;                        // rsplit x n x 3 near-force shares (sorted order)
   double* facc;                    // n x 3 reaction forces (sorted order; kept zero between calls)
   double* rpart;                   // cells x rsplit x 7 partial sums of the near energy and virial
+  // cell-sort buffers of the real-space part, apart from the Fourier part's
+  // so that the two can run at once on two streams
+  int* nr_counts;                  // kMaxCells
+  int* nr_offsets;                 // kMaxCells + 1
+  int* nr_keys;                    // n
+  int* nr_ranks;                   // n
+  int* nr_perm;                    // n
+  Record<R>* nr_tmp;               // n
+  Record<R>* nr_sorted;            // n
+  double* nr_qpart;                // nbin x 2
   int64_t pofs;                    // batched launches: first particle of this plan in the
   int rep;                         // concatenated inputs, and its index (0 for single plans)
 };
@@ -225,14 +235,17 @@ hipError_t launch_finalize_batch(const BatchLaunch<R>& b, double* out7, hipStrea
 template <typename T>
 hipError_t launch_fill(T* p, size_t count, hipStream_t s);
 
-// Real-space part (one workgroup per cell, after a cell sort with cellsort set):
-// f receives (accumulate) or is overwritten with the near forces in input
-// order; the partial sums go to rpart, which launch_real_finalize turns into
+// Real-space part (one workgroup share per cell, after a cell sort with
+// cellsort set): launch_real_pairs leaves the force shares in fpart / facc and
+// the partial sums in rpart; launch_real_forces writes (accumulate: adds) the
+// near forces to f in input order; launch_real_finalize writes (add: adds)
 // out7 = {U_N, W_N}.
 template <typename R>
-hipError_t launch_real_pairs(const DevPlan<R>& d, R* f, int accumulate, hipStream_t s);
+hipError_t launch_real_pairs(const DevPlan<R>& d, hipStream_t s);
 template <typename R>
-hipError_t launch_real_finalize(const DevPlan<R>& d, double* out7, hipStream_t s);
+hipError_t launch_real_forces(const DevPlan<R>& d, R* f, int accumulate, hipStream_t s);
+template <typename R>
+hipError_t launch_real_finalize(const DevPlan<R>& d, double* out7, int add, hipStream_t s);
 template <typename R>
 size_t lds_real(const DevPlan<R>& d);
 

@@ -399,12 +399,20 @@ struct esp_plan_s {
   int nw = 0, nw_fitted = 0, nker = 0, nseg = 0;
   double A = 0, self_coef = 0, Ic = 0;
   hipStream_t stream = nullptr;
+  // esp_coulomb: the real-space part runs on its own stream (made on first
+  // use, default priority), forked from and joined back to `stream` by events
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::vector<void*> allocs;
   DevPlan<float> d32{};
   DevPlan<double> d64{};
   std::string err;
   ~esp_plan_s() {
     prof.release();
+    if (side) (void)hipStreamSynchronize(side);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (side) (void)hipStreamDestroy(side);
     for (void* p : allocs) (void)hipFree(p);
   }
 };
@@ -716,10 +724,13 @@ esp_status build_device(esp_plan_t* p) {
     const double per = static_cast<double>(d.nbin) * std::min(256, r.ntiles) / r.ntiles;
     d.nsub = std::max(1, std::min(kMaxCounterCopies, static_cast<int>(std::ceil(per / kBinContention))));
   }
-  // the counters and offsets also serve the real-space cell sort (at most kMaxCells cells)
-  const size_t ncount = std::max(static_cast<size_t>(r.ntiles) * d.nsub, static_cast<size_t>(kMaxCells));
+  const size_t ncount = static_cast<size_t>(r.ntiles) * d.nsub;
   if ((st = dalloc(p, &d.counts, ncount)) || (st = dalloc(p, &d.sbase, d.nsub > 1 ? ncount : 1)) ||
-      (st = dalloc(p, &d.offsets, std::max(r.ntiles, kMaxCells) + 1)) ||
+      (st = dalloc(p, &d.offsets, r.ntiles + 1)) ||
+      (st = dalloc(p, &d.nr_counts, kMaxCells)) || (st = dalloc(p, &d.nr_offsets, kMaxCells + 1)) ||
+      (st = dalloc(p, &d.nr_keys, r.n)) || (st = dalloc(p, &d.nr_ranks, r.n)) ||
+      (st = dalloc(p, &d.nr_perm, r.n)) || (st = dalloc(p, &d.nr_tmp, r.n)) ||
+      (st = dalloc(p, &d.nr_sorted, r.n)) || (st = dalloc(p, &d.nr_qpart, static_cast<size_t>(d.nbin) * 2)) ||
       (st = dalloc(p, &d.rpart, static_cast<size_t>(std::max(kMaxCells, 2 * kRealBlocks)) * kNumSums)) ||
       (st = dalloc(p, &d.fpart, static_cast<size_t>(kMaxRealSplit) * r.n * 3)) ||
       (st = dalloc(p, &d.facc, static_cast<size_t>(r.n) * 3)) ||
@@ -741,6 +752,7 @@ esp_status build_device(esp_plan_t* p) {
                    (r.gather == ESP_GATHER_AUTO && box_fits &&
                     r.n >= static_cast<int64_t>(kTiledGatherMin) * r.ntiles);
   e = hipMemset(d.counts, 0, ncount * sizeof(int));
+  if (e == hipSuccess) e = hipMemset(d.nr_counts, 0, kMaxCells * sizeof(int));
   if (e == hipSuccess) e = hipMemset(d.rho, 0, G * sizeof(R));
   if (e == hipSuccess) e = hipMemset(d.facc, 0, static_cast<size_t>(r.n) * 3 * sizeof(double));
   if (e == hipSuccess) e = hipMemset(d.flags, 0, 4 * sizeof(int));
@@ -751,16 +763,21 @@ esp_status build_device(esp_plan_t* p) {
 
 // Launch one stage, bracketed by profiling events when that stage is profiled.
 template <class F>
-hipError_t stage(esp_plan_t* p, int st, F&& launch) {
+hipError_t stage(esp_plan_t* p, int st, F&& launch, hipStream_t s) {
   Profiler& pr = p->prof;
   const bool on = ((pr.mask >> st) & 1u) && pr.used[st] < pr.cap && pr.seen[st]++ % pr.stride == 0;
-  if (on) (void)hipEventRecord(pr.ev[st][2 * pr.used[st]], p->stream);
+  if (on) (void)hipEventRecord(pr.ev[st][2 * pr.used[st]], s);
   hipError_t e = launch();
   if (on) {
-    (void)hipEventRecord(pr.ev[st][2 * pr.used[st] + 1], p->stream);
+    (void)hipEventRecord(pr.ev[st][2 * pr.used[st] + 1], s);
     ++pr.used[st];
   }
   return e;
+}
+
+template <class F>
+hipError_t stage(esp_plan_t* p, int st, F&& launch) {
+  return stage(p, st, launch, p->stream);
 }
 
 // Cell sort.  Leaves the tile counts set; the spreading pass clears them.
@@ -844,29 +861,85 @@ esp_status local_virial(esp_plan_t* p, const R* xyz, const R* q, R* w6, double* 
   return e == hipSuccess ? ESP_OK : hip_fail(p, e, "kernel launch");
 }
 
-// Real-space part: cell sort with the real-space cells, the pair kernel and
-// the final sums.  Shares the sort buffers with the reciprocal path (each
-// call sorts again); the pair kernel clears the cell counters.
+// The real-space part's launch description: the plan with the real-space
+// cells as sort keys and the real-space sort buffers.
+template <typename R>
+DevPlan<R> near_plan(esp_plan_t* p) {
+  DevPlan<R> c = dev<R>(p);
+  c.cellsort = 1;
+  c.ntiles = c.cn1 * c.cn2 * c.cn3;
+  c.nsub = 1;
+  c.bin_lds = c.ntiles <= 8192 ? 1 : 0;
+  c.counts = c.nr_counts;
+  c.offsets = c.nr_offsets;
+  c.keys = c.nr_keys;
+  c.ranks = c.nr_ranks;
+  c.perm = c.nr_perm;
+  c.tmp = c.nr_tmp;
+  c.sorted = c.nr_sorted;
+  c.qpart = c.nr_qpart;
+  // enough workgroups to fill the chip: rsplit x cells <= max(cells, 2 kRealBlocks)
+  c.rsplit = std::max(1, std::min(kMaxRealSplit, (kRealBlocks + c.ntiles / 2) / c.ntiles));
+  return c;
+}
+
+// Cell sort with the real-space cells and the pair kernel on stream s (the
+// pair kernel clears the cell counters); forces and sums stay in the plan.
+template <typename R>
+hipError_t launch_near(const DevPlan<R>& c, const R* xyz, const R* q, hipStream_t s) {
+  hipError_t e = launch_bin(c, xyz, q, s);
+  if (e == hipSuccess) e = launch_scatter(c, s);
+  if (e == hipSuccess) e = launch_real_pairs(c, s);
+  return e;
+}
+
+// Real-space part on the plan's stream.
 template <typename R>
 esp_status real_space(esp_plan_t* p, const R* xyz, const R* q, R* f, int accumulate, double* out7) {
   if (!xyz || !q || !f || !out7) {
     p->err = "null pointer argument";
     return ESP_EINVAL;
   }
-  DevPlan<R> c = dev<R>(p);
-  c.cellsort = 1;
-  c.ntiles = c.cn1 * c.cn2 * c.cn3;
-  c.nsub = 1;
-  c.bin_lds = c.ntiles <= 8192 ? 1 : 0;
-  // enough workgroups to fill the chip: rsplit x cells <= max(cells, 2 kRealBlocks)
-  c.rsplit = std::max(1, std::min(kMaxRealSplit, (kRealBlocks + c.ntiles / 2) / c.ntiles));
+  const DevPlan<R> c = near_plan<R>(p);
   hipError_t e = stage(p, ST_REAL, [&] {
-    hipError_t eb = launch_bin(c, xyz, q, p->stream);
-    if (eb == hipSuccess) eb = launch_scatter(c, p->stream);
-    if (eb == hipSuccess) eb = launch_real_pairs(c, f, accumulate, p->stream);
-    if (eb == hipSuccess) eb = launch_real_finalize(c, out7, p->stream);
+    hipError_t eb = launch_near(c, xyz, q, p->stream);
+    if (eb == hipSuccess) eb = launch_real_forces(c, f, accumulate, p->stream);
+    if (eb == hipSuccess) eb = launch_real_finalize(c, out7, 0, p->stream);
     return eb;
   });
+  return e == hipSuccess ? ESP_OK : hip_fail(p, e, "kernel launch");
+}
+
+// Total Coulomb: the real-space part on the side stream, the Fourier forces
+// on the plan's stream at the same time (they share only the read-only
+// inputs and the error flags), then, after the join, the near forces and
+// sums added to f and out7.
+template <typename R>
+esp_status coulomb(esp_plan_t* p, const R* xyz, const R* q, R* f, double* out7) {
+  if (!xyz || !q || !f || !out7) {
+    p->err = "null pointer argument";
+    return ESP_EINVAL;
+  }
+  hipError_t e = hipSuccess;
+  if (!p->side) {
+    e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(p, e, "side stream creation");
+  }
+  const DevPlan<R> c = near_plan<R>(p);
+  e = hipEventRecord(p->ev_fork, p->stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(p->side, p->ev_fork, 0);
+  if (e == hipSuccess) e = stage(p, ST_REAL, [&] { return launch_near(c, xyz, q, p->side); }, p->side);
+  if (e == hipSuccess) e = hipEventRecord(p->ev_join, p->side);
+  if (e != hipSuccess) return hip_fail(p, e, "real-space launch");
+  const esp_status st = forces<R>(p, xyz, q, f, out7);
+  // joined whatever the Fourier part returned, so that later work on the
+  // plan's stream stays ordered after the side stream's
+  e = hipStreamWaitEvent(p->stream, p->ev_join, 0);
+  if (st != ESP_OK) return st;
+  if (e == hipSuccess) e = launch_real_forces(c, f, 1, p->stream);
+  if (e == hipSuccess) e = launch_real_finalize(c, out7, 1, p->stream);
   return e == hipSuccess ? ESP_OK : hip_fail(p, e, "kernel launch");
 }
 
@@ -1046,9 +1119,20 @@ esp_status esp_real_space_f64(esp_plan_t* p, const double* xyz, const double* q,
   return st != ESP_OK ? st : real_space<double>(p, xyz, q, f, accumulate, out7);
 }
 
+esp_status esp_coulomb(esp_plan_t* p, const float* xyz, const float* q, float* f, double* out7) {
+  esp_status st = want_precision(p, ESP_FP32);
+  return st != ESP_OK ? st : coulomb<float>(p, xyz, q, f, out7);
+}
+
+esp_status esp_coulomb_f64(esp_plan_t* p, const double* xyz, const double* q, double* f, double* out7) {
+  esp_status st = want_precision(p, ESP_FP64);
+  return st != ESP_OK ? st : coulomb<double>(p, xyz, q, f, out7);
+}
+
 esp_status esp_check(esp_plan_t* p) {
   if (!p) return ESP_EINVAL;
   hipError_t e = hipStreamSynchronize(p->stream);
+  if (e == hipSuccess && p->side) e = hipStreamSynchronize(p->side);
   if (e != hipSuccess) return hip_fail(p, e, "stream synchronise");
   int* flags = p->r.precision == ESP_FP32 ? p->d32.flags : p->d64.flags;
   int h = 0;
@@ -1112,6 +1196,7 @@ const char* esp_last_error(const esp_plan_t* p) { return p ? p->err.c_str() : "n
 void esp_destroy(esp_plan_t* p) {
   if (!p) return;
   (void)hipStreamSynchronize(p->stream);
+  if (p->side) (void)hipStreamSynchronize(p->side);
   delete p;
 }
 

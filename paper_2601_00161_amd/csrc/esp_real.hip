@@ -336,7 +336,7 @@ __global__ void __launch_bounds__(256) k_real_forces(DevPlan<R> d, R* __restrict
 }
 
 template <typename R>
-__global__ void __launch_bounds__(256) k_real_finalize(DevPlan<R> d, double* __restrict__ out7) {
+__global__ void __launch_bounds__(256) k_real_finalize(DevPlan<R> d, double* __restrict__ out7, int add) {
   __shared__ double red[kNumSums * 16];
   const int nblk = d.cn1 * d.cn2 * d.cn3 * d.rsplit;
   double v[kNumSums];
@@ -348,7 +348,7 @@ __global__ void __launch_bounds__(256) k_real_finalize(DevPlan<R> d, double* __r
   block_sum<kNumSums>(v, red);
   if (threadIdx.x == 0)
 #pragma unroll
-    for (int k = 0; k < kNumSums; ++k) out7[k] = d.fin.coulomb_k * v[k];   // each pair once
+    for (int k = 0; k < kNumSums; ++k) out7[k] = (add ? out7[k] : 0.0) + d.fin.coulomb_k * v[k];   // each pair once
 }
 
 template <typename R>
@@ -357,28 +357,33 @@ size_t lds_real(const DevPlan<R>& d) {
 }
 
 template <typename R>
-hipError_t launch_real_pairs(const DevPlan<R>& d, R* f, int accumulate, hipStream_t s) {
+hipError_t launch_real_pairs(const DevPlan<R>& d, hipStream_t s) {
   const size_t lds = lds_real(d);     // at most 40 KiB (segment count capped on the host)
   const int nblk = d.cn1 * d.cn2 * d.cn3 * d.rsplit;
   hipLaunchKernelGGL(k_real_pairs<R>, dim3(nblk), dim3(kRealThreads), lds, s, d);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_real_forces(const DevPlan<R>& d, R* f, int accumulate, hipStream_t s) {
   hipLaunchKernelGGL(k_real_forces<R>, dim3(static_cast<unsigned>((d.n + 255) / 256)), dim3(256), 0, s, d, f,
                      accumulate);
   return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_real_finalize(const DevPlan<R>& d, double* out7, hipStream_t s) {
-  hipLaunchKernelGGL(k_real_finalize<R>, dim3(1), dim3(256), 0, s, d, out7);
+hipError_t launch_real_finalize(const DevPlan<R>& d, double* out7, int add, hipStream_t s) {
+  hipLaunchKernelGGL(k_real_finalize<R>, dim3(1), dim3(256), 0, s, d, out7, add);
   return hipGetLastError();
 }
 
 template size_t lds_real<float>(const DevPlan<float>&);
 template size_t lds_real<double>(const DevPlan<double>&);
-template hipError_t launch_real_pairs<float>(const DevPlan<float>&, float*, int, hipStream_t);
-template hipError_t launch_real_pairs<double>(const DevPlan<double>&, double*, int, hipStream_t);
-template hipError_t launch_real_finalize<float>(const DevPlan<float>&, double*, hipStream_t);
-template hipError_t launch_real_finalize<double>(const DevPlan<double>&, double*, hipStream_t);
+template hipError_t launch_real_pairs<float>(const DevPlan<float>&, hipStream_t);
+template hipError_t launch_real_pairs<double>(const DevPlan<double>&, hipStream_t);
+template hipError_t launch_real_forces<float>(const DevPlan<float>&, float*, int, hipStream_t);
+template hipError_t launch_real_forces<double>(const DevPlan<double>&, double*, int, hipStream_t);
+template hipError_t launch_real_finalize<float>(const DevPlan<float>&, double*, int, hipStream_t);
+template hipError_t launch_real_finalize<double>(const DevPlan<double>&, double*, int, hipStream_t);
 
 }  // namespace espx

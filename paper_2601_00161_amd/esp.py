@@ -89,6 +89,8 @@ SIGNATURES = [
     ("esp_local_virial_f64", ctypes.c_int, [_P, _P, _P, _P, _P]),
     ("esp_real_space", ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, _P]),
     ("esp_real_space_f64", ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, _P]),
+    ("esp_coulomb", ctypes.c_int, [_P, _P, _P, _P, _P]),
+    ("esp_coulomb_f64", ctypes.c_int, [_P, _P, _P, _P, _P]),
     ("esp_get_params", ctypes.c_int, [_P, ctypes.POINTER(Params)]),
     ("esp_last_error", ctypes.c_char_p, [_P]),
     ("esp_destroy", None, [_P]),
@@ -336,6 +338,22 @@ class Plan:
         st = fn(self._h, _ptr(xyz), _ptr(q), _ptr(f), 1 if accumulate else 0, _ptr(out7))
         if st < 0:
             self._err(st, "esp_real_space")
+        return f, out7
+
+    def coulomb(self, xyz, q, f=None, out7=None):
+        """Total Coulomb forces (n, 3) and out7 (near plus Fourier energy
+        and virial); the near part runs on a second stream beside the
+        Fourier part."""
+        t = self._check_in(xyz, q)
+        if f is None:
+            f = t.empty((self.n, 3), dtype=self.dtype, device=xyz.device)
+        if out7 is None:
+            out7 = t.empty(7, dtype=t.float64, device=xyz.device)
+        self._stream()
+        fn = self._lib.esp_coulomb if self.dtype == t.float32 else self._lib.esp_coulomb_f64
+        st = fn(self._h, _ptr(xyz), _ptr(q), _ptr(f), _ptr(out7))
+        if st < 0:
+            self._err(st, "esp_coulomb")
         return f, out7
 
     def check(self):

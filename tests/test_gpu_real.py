@@ -1,8 +1,8 @@
 """Real-space (near) part on the GPU (Sec. 3.1, eq. UN, eq. PinsN, eq. Fc with
 eq. mathFN) through the C ABI against the oracle's pair sum: small and
 triclinic boxes, boxes only two cells wide, the 30,000-particle water box,
-accumulation onto the Fourier forces, total Coulomb against Ewald, and
-non-finite input."""
+accumulation onto the Fourier forces, total Coulomb against Ewald (two calls,
+or one call with the two parts on two streams), and non-finite input."""
 import numpy as np
 import pytest
 
@@ -131,6 +131,66 @@ def test_accumulate_and_total_coulomb_against_ewald(precision):
     assert abs(o[0] - exact.energy) <= 1e-5 * abs(exact.energy)
     assert tensor_rel(o, exact.virial) < 1e-5
     assert rel_rms(f_tot, exact.forces) < 1e-5
+    plan.close()
+
+
+@pytest.mark.parametrize("force", ["ad", "ik"])
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_coulomb_overlapped_matches_the_two_calls(precision, force):
+    """esp_coulomb (the near part on a second stream beside the Fourier part)
+    against esp_forces followed by esp_real_space with accumulate, and the
+    total against classical Ewald.  Three calls in a row reuse the side
+    stream and the near part's counters; a Fourier-only call comes before the
+    third, which runs on another torch stream."""
+    from oracle import ewald
+    h, r, q = SYSTEMS["water_triclinic"]()
+    r_, q_, r64, q64 = as_inputs(r, q, precision)
+    exact = ewald.ewald(h, r64, q64)
+    prm = paper_params(h, 1e-5)
+    kw = {"window_tol": 1e-13} if precision == "fp64" else {}
+    plan = esp.Plan(h, len(q), 1e-5, precision=precision, c_split=prm["c_split"], P=prm["P"], M=prm["M"],
+                    force=force, **kw)
+    xyz, qq = torch.from_numpy(r_).to(DEV), torch.from_numpy(q_).to(DEV)
+    f_ref, o_far = plan.forces(xyz, qq)
+    _, o_near = plan.real_space(xyz, qq, f=f_ref, accumulate=True)
+    f_ref = f_ref.double().cpu().numpy()
+    o_ref = o_far.cpu().numpy() + o_near.cpu().numpy()
+    same = 1e-12 if precision == "fp64" else 1e-6
+    results = []
+    for call in range(3):
+        if call < 2:
+            f, o = plan.coulomb(xyz, qq)
+        else:
+            plan.forces(xyz, qq)
+            s = torch.cuda.Stream()
+            s.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(s):
+                f, o = plan.coulomb(xyz, qq)
+            s.synchronize()
+        assert plan.check() == esp.ESP_OK
+        results.append((f.double().cpu().numpy(), o.cpu().numpy()))
+    for f, o in results:
+        assert rel_rms(f, f_ref) < same
+        assert np.allclose(o, o_ref, rtol=same, atol=0)
+        assert abs(o[0] - exact.energy) <= 1e-5 * abs(exact.energy)
+        assert tensor_rel(o, exact.virial) < 1e-5
+        assert rel_rms(f, exact.forces) < 1e-5
+    plan.close()
+
+
+def test_coulomb_nonfinite_input_is_flagged():
+    """A non-finite input seen by both parts is reported once by esp_check."""
+    h, r, q = SYSTEMS["water_cubic_2.2"]()
+    r_bad = r.copy()
+    r_bad[3, 1] = np.nan
+    r_, q_, _, _ = as_inputs(r_bad, q, "fp32")
+    prm = paper_params(h, 1e-5)
+    plan = esp.Plan(h, len(q), 1e-5, c_split=prm["c_split"], P=prm["P"], M=prm["M"])
+    plan.coulomb(torch.from_numpy(r_).to(DEV), torch.from_numpy(q_).to(DEV))
+    with pytest.raises(esp.EspError) as ei:
+        plan.check()
+    assert ei.value.status == esp.ESP_ENONFINITE
+    assert plan.check() == esp.ESP_OK
     plan.close()
 
 
