@@ -385,7 +385,8 @@ def main():
     bytes_dom = stage_bytes(dominant, N, G, S, 4)
     achieved = bytes_dom / avg_s / 1e9
     workload_key = (f"water30k_tol{args.tol:g}_P{prm['P']}_M{prm['M'][0]}x{prm['M'][1]}x{prm['M'][2]}"
-                    f"_T{prm['tile'][0]}_{'gtile' if prm['gather_tiled'] else 'gpart'}")
+                    f"_T{prm['tile'][0]}_{'gtile' if prm['gather_tiled'] else 'gpart'}"
+                    f"{'_fixed' if prm['spread_fixed'] else ''}")
     traffic = measured_traffic(dominant, workload_key)
     value = N * args.steps / dt32 / 1e6
     v64 = N * args.steps / dt64 / 1e6

@@ -116,10 +116,18 @@ typedef struct {
   int fft_split;       /* nonzero: run the x and y transforms as separate passes even
                           when a grid plane fits one workgroup's LDS (planes that do
                           not fit always take them) */
+  int spread_accum;    /* accumulator of the spreading tile in LDS: ESP_SPREAD_AUTO (0,
+                          64-bit fixed point when there are 512+ tiles holding 128+
+                          particles on average, else FP64), ESP_SPREAD_FIXED (1) or
+                          ESP_SPREAD_FP64 (2).  Fixed point: per tile, scale 2^e with
+                          2^e wmax^3 sum|q| < 2^62, each contribution rounded once to
+                          2^-e, exact integer sums.  Single plans only; batched
+                          launches use FP64. */
 } esp_opts;
 
 enum { ESP_GATHER_AUTO = 0, ESP_GATHER_PARTICLE = 1, ESP_GATHER_TILE = 2 };
 enum { ESP_FORCE_AD = 0, ESP_FORCE_IK = 1 };
+enum { ESP_SPREAD_AUTO = 0, ESP_SPREAD_FIXED = 1, ESP_SPREAD_FP64 = 2 };
 
 /* Parameters a plan resolved to (returned by esp_get_params). */
 typedef struct {
@@ -142,6 +150,7 @@ typedef struct {
   int real_cells[3];              /* esp_real_space cells per cell vector (current box) */
   int real_segments;              /* segments of the near-kernel polynomials on [0, rc] */
   int fft_split;                  /* the xy transforms run as separate x and y passes */
+  int spread_fixed;               /* 1: the spreading tile accumulates in 64-bit fixed point */
 } esp_params;
 
 void esp_opts_default(esp_opts *o);

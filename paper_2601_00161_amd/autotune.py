@@ -1,12 +1,16 @@
-"""Autotuner for the launch shape of a plan: the spreading tile edge and the
-gather variant (per particle, or tile-staged potential in LDS).
+"""Autotuner for the launch shape of a plan: the spreading tile edge, the
+gather variant (per particle, or tile-staged potential in LDS) and the LDS
+accumulator of the spreading (FP64, or 64-bit fixed point where tiles hold
+128+ particles on average).
 
 Each admissible candidate is timed on the GPU with the caller's own
 particles (one esp_forces call = one step, HIP events over repeated calls)
 and the fastest is kept.  Results are cached in a JSON file keyed by what
 the choice depends on: precision, grid, window support, window degree class
 and particle count (two significant digits).  Tuning never changes results
-beyond FP32 reassociation: every candidate computes the same sums.
+beyond the rounding of the plan's precision: every candidate computes the
+same sums, reassociated (and, in fixed point, each term rounded to at most
+2^-61 of its tile's charge bound).
 
     plan, info = autotune.tuned_plan(h, n, tol, xyz, q, cache="tune.json", precision="fp32")
 """
@@ -20,6 +24,8 @@ from . import esp
 
 TILES = (4, 5, 6, 8, 10, 12)
 GATHERS = ("particle", "tile")
+ACCUMS = ("fp64", "fixed")
+FIXED_MIN_PER_TILE = 128          # fixed point is tried only from this many particles per tile
 DEFAULT_CACHE = os.environ.get("ESP_AUTOTUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache",
                                                                   "esp_mi355x_autotune.json"))
 
@@ -64,24 +70,30 @@ def time_step(plan, xyz, q, reps=20, warmup=3):
     return a.elapsed_time(b) * 1e3 / reps
 
 
-def tune(h, n, tol, xyz, q, reps=20, tiles=TILES, gathers=GATHERS, **opts):
-    """Time every admissible (tile, gather) pair; returns {"tile", "gather", "us", "table"}."""
+def tune(h, n, tol, xyz, q, reps=20, tiles=TILES, gathers=GATHERS, accums=ACCUMS, **opts):
+    """Time every admissible (tile, gather, accumulator) choice; returns
+    {"tile", "gather", "accum", "us", "table"} (table keys "tile:gather" for
+    the FP64 accumulator, "tile:gather:fixed" for fixed point)."""
     table = {}
     best = None
     for t in tiles:
         for g in gathers:
-            try:
-                plan = esp.Plan(h, n, tol, tile=t, gather=g, **opts)
-            except esp.EspError:
-                continue                      # not admissible for this grid (LDS, tile count)
-            us = time_step(plan, xyz, q, reps=reps)
-            plan.close()
-            table[f"{t}:{g}"] = round(us, 2)
-            if best is None or us < best[2]:
-                best = (t, g, us)
+            for a in accums:
+                try:
+                    plan = esp.Plan(h, n, tol, tile=t, gather=g, spread_accum=a, **opts)
+                except esp.EspError:
+                    continue                  # not admissible for this grid (LDS, tile count)
+                if a == "fixed" and n < FIXED_MIN_PER_TILE * plan.params["ntiles"]:
+                    plan.close()              # sparse tiles: fixed point is slower (measured)
+                    continue
+                us = time_step(plan, xyz, q, reps=reps)
+                plan.close()
+                table[f"{t}:{g}" + (":fixed" if a == "fixed" else "")] = round(us, 2)
+                if best is None or us < best[3]:
+                    best = (t, g, a, us)
     if best is None:
         raise RuntimeError("no admissible launch shape")
-    return {"tile": best[0], "gather": best[1], "us": round(best[2], 2), "table": table}
+    return {"tile": best[0], "gather": best[1], "accum": best[2], "us": round(best[3], 2), "table": table}
 
 
 def tuned_plan(h, n, tol, xyz, q, cache=DEFAULT_CACHE, retune=False, **opts):
@@ -94,7 +106,8 @@ def tuned_plan(h, n, tol, xyz, q, cache=DEFAULT_CACHE, retune=False, **opts):
         data[key] = tune(h, n, tol, xyz, q, **opts)
         _save(cache, data)
     rec = data[key]
-    plan = esp.Plan(h, n, tol, tile=rec["tile"], gather=rec["gather"], **opts)
+    plan = esp.Plan(h, n, tol, tile=rec["tile"], gather=rec["gather"], spread_accum=rec.get("accum", "fp64"),
+                    **opts)
     return plan, dict(rec, key=key)
 
 
@@ -113,7 +126,7 @@ def tuned_tiles(cells, ns, tols, positions, charges, cache=DEFAULT_CACHE, **opts
         if key not in data:
             xyz = torch.as_tensor(r, dtype=dt, device="cuda").contiguous()
             qt = torch.as_tensor(qq, dtype=dt, device="cuda").contiguous()
-            data[key] = tune(h, n, tol, xyz, qt, gathers=("particle",), **opts)
+            data[key] = tune(h, n, tol, xyz, qt, gathers=("particle",), accums=("fp64",), **opts)
             changed = True
         tiles.append(data[key]["tile"])
     if changed:

@@ -41,6 +41,7 @@ struct Resolved {
   int force = ESP_FORCE_AD;
   int local = 0;
   int fft_split = 0;
+  int spread_accum = ESP_SPREAD_AUTO;
   double pred[4] = {0, 0, 0, 0};
   double pred_cost = 0;
 };
@@ -289,6 +290,11 @@ esp_status resolve(const double* h, int64_t n, double tol, const esp_opts* o, Re
   r.force = o->force;
   r.local = o->local_virial ? 1 : 0;
   r.fft_split = o->fft_split ? 1 : 0;
+  if (o->spread_accum < ESP_SPREAD_AUTO || o->spread_accum > ESP_SPREAD_FP64) {
+    err = "spread_accum must be ESP_SPREAD_AUTO, ESP_SPREAD_FIXED or ESP_SPREAD_FP64";
+    return ESP_EINVAL;
+  }
+  r.spread_accum = o->spread_accum;
   std::memcpy(r.h, h, 9 * sizeof(double));
   esp_status st = check_box(h, r.rc, r.hinv, &r.V, err);
   if (st != ESP_OK) return st;
@@ -633,6 +639,20 @@ esp_status build_device(esp_plan_t* p) {
   int fitted = 0;
   p->nw = fit_window(p, std::min(eps, 1e-4), win, &fitted);
   p->nw_fitted = fitted;
+  {
+    // largest |w_q(tau)| of the fitted polynomials over tau in [-1/2, 1/2],
+    // sampled, with 1% added (the values lie below psi(0); the bound only
+    // sets the fixed-point scale, which keeps another factor of two spare)
+    double wm = 0;
+    for (int q = 0; q < r.P; ++q)
+      for (int s = 0; s <= 256; ++s) {
+        const double tau = -0.5 + s / 256.0;
+        double v = 0;
+        for (int j = p->nw; j >= 0; --j) v = v * tau + win[static_cast<size_t>(j) * r.P + q];
+        wm = std::max(wm, std::fabs(v));
+      }
+    d.wmax3 = static_cast<float>(1.01 * wm * wm * wm);
+  }
   std::vector<double> cf, cg;
   p->nker = fit_kernel(p, cf, cg);
   d.nw = p->nw;
@@ -701,6 +721,13 @@ esp_status build_device(esp_plan_t* p) {
   // separate x and y passes with as many row pairs / columns per workgroup
   // (up to 16) as fit
   d.xy_split = r.fft_split || lds_fft_xy(d) > static_cast<size_t>(maxlds) ? 1 : 0;
+  // fixed-point spreading pays for its pass over the charges and its longer
+  // conversions only where the LDS atomics bound the kernel: crowded tiles,
+  // and enough of them to keep every CU busy (measured: faster with 1,296
+  // tiles of ~770 particles, slower with 125 tiles of ~240 or 729 of ~40)
+  d.spread_fixed = r.spread_accum == ESP_SPREAD_FIXED ||
+                   (r.spread_accum == ESP_SPREAD_AUTO && r.ntiles >= kSpreadFixedMinTiles &&
+                    r.n >= static_cast<int64_t>(kSpreadFixedMin) * r.ntiles);
   d.xpairs = d.ycols = 16;
   while (d.xpairs > 1 && lds_fft_x(d, d.xpairs) > static_cast<size_t>(maxlds)) d.xpairs /= 2;
   while (d.ycols > 1 && lds_fft_y(d, d.ycols) > static_cast<size_t>(maxlds)) d.ycols /= 2;
@@ -1187,6 +1214,7 @@ esp_status esp_get_params(const esp_plan_t* p, esp_params* out) {
     out->real_cells[2] = f32 ? p->d32.cn3 : p->d64.cn3;
     out->real_segments = p->nseg;
     out->fft_split = f32 ? p->d32.xy_split : p->d64.xy_split;
+    out->spread_fixed = f32 ? p->d32.spread_fixed : p->d64.spread_fixed;
   }
   return ESP_OK;
 }

@@ -7,6 +7,8 @@
 // loops unroll completely and the coefficient reads are issued up front.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "esp_common.h"
 
 #ifndef ESP_P
@@ -55,12 +57,27 @@ __device__ __forceinline__ void window_d_lanes(const R* __restrict__ win, R t1, 
 // One workgroup per tile of T1 x T2 x T3 grid cells.  Its particles (those
 // whose stencil base lies in the tile, contiguous after the cell sort) are
 // spread into an LDS copy of the tile plus its (P - 1)-wide upper halo, which
-// is then added to the periodic grid.  The LDS tile accumulates in FP64 for
-// both precisions: products are formed in R, and ds_add_f64 is the fast LDS
-// atomic on gfx950 (ds_add_f32 is not).
-template <typename R, int P, int NW, bool BATCH>
+// is then added to the periodic grid.  Products are formed in R; the LDS tile
+// accumulates them in 8-byte cells (ds_add_f32 is several times slower on
+// gfx950 than the 8-byte LDS adds):
+//  * FIX = false: FP64 (ds_add_f64).
+//  * FIX = true: 64-bit fixed point (ds_add_u64, faster than ds_add_f64 on
+//    crowded tiles).  The scale 2^e is the tile's own: with
+//    b = wmax^3 sum |q_j| over its particles no cell can exceed b in
+//    magnitude, and 2^e b < 2^62 keeps a factor of two of the int64 range
+//    spare.  Each contribution is rounded once, to 2^-e (at most 2^-61 b);
+//    the integer sums are exact, so a cell does not depend on the order of
+//    the atomics.  The pass over the tile's charges that gives b costs more
+//    than the faster atomics save when a tile holds few particles.
+template <typename R>
+__device__ __forceinline__ long long to_fixed(R y) {
+  return static_cast<long long>(rint(y));
+}
+
+template <typename R, int P, int NW, bool BATCH, bool FIX>
 __global__ void __launch_bounds__(256) k_spread(KArg<R, BATCH> ka) {
   extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ float qabs[4];                          // FIX: per-wave sums of |q| (256 threads)
   int tile;
   const DevPlan<R>& d = plan_of(ka, tile);
   const int t1 = tile % d.nt1, t2 = (tile / d.nt1) % d.nt2, t3 = tile / (d.nt1 * d.nt2);
@@ -69,11 +86,12 @@ __global__ void __launch_bounds__(256) k_spread(KArg<R, BATCH> ka) {
   const int E2 = min(d.T2, d.M2 - o2) + P - 1;
   const int E3 = min(d.T3, d.M3 - o3) + P - 1;
   // plane stride made odd: the P z-planes of one particle are touched by P
-  // adjacent lanes, and an even stride of doubles maps them onto few banks
+  // adjacent lanes, and an even stride of 8-byte cells maps them onto few banks
   const int S = (E1 * E2) | 1;
   const int ncell = S * E3;
   const int maxcell = (((d.T1 + P - 1) * (d.T2 + P - 1)) | 1) * (d.T3 + P - 1);
-  double* grid = reinterpret_cast<double*>(smem);
+  using Cell = typename std::conditional<FIX, unsigned long long, double>::type;
+  Cell* grid = reinterpret_cast<Cell*>(smem);
   R* wts = reinterpret_cast<R*>(grid + maxcell);     // kSpreadChunk x 3 x P
   R* win = wts + kSpreadChunk * 3 * P;               // (NW + 1) x P
   int* base = reinterpret_cast<int*>(win + (NW + 1) * P);   // kSpreadChunk x 3
@@ -88,13 +106,31 @@ __global__ void __launch_bounds__(256) k_spread(KArg<R, BATCH> ka) {
   const int tj = threadIdx.x / 3, tdim = threadIdx.x - 3 * (threadIdx.x / 3);
   Record<R> rec;
   if (threadIdx.x < min(kSpreadChunk, end - start) * 3) rec = d.sorted[start + tj];
-  for (int k = threadIdx.x; k < ncell; k += blockDim.x) grid[k] = 0.0;
+  float qs = 0.f;
+  if constexpr (FIX)
+    for (int k = start + threadIdx.x; k < end; k += blockDim.x) qs += fabsf(static_cast<float>(d.sorted[k].q));
+  for (int k = threadIdx.x; k < ncell; k += blockDim.x) grid[k] = Cell(0);
   if (static_cast<int>(threadIdx.x) < (NW + 1) * P) win[threadIdx.x] = wv;
   for (int k = threadIdx.x + blockDim.x; k < (NW + 1) * P; k += blockDim.x) win[k] = d.win[k];
+  if constexpr (FIX) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) qs += __shfl_xor(qs, off);
+    if ((threadIdx.x & 63) == 0) qabs[threadIdx.x >> 6] = qs;
+  }
   __syncthreads();
+  R scale = R(1);
+  double unscale = 1.0;
+  if constexpr (FIX) {
+    // the float sum of |q| is within n 2^-24 (relative) of the exact one,
+    // far inside the spare factor of two for any tile
+    const float bnd = (qabs[0] + qabs[1] + qabs[2] + qabs[3]) * d.wmax3;
+    const int e = max(-100, min(120, 61 - ilogbf(fmaxf(bnd, 1e-30f))));
+    scale = static_cast<R>(ldexpf(1.f, e));
+    unscale = ldexp(1.0, -e);
+  }
   for (int c0 = start; c0 < end; c0 += kSpreadChunk) {
     const int nc = min(kSpreadChunk, end - c0);
-    // weights: q folded into x
+    // weights: q (and the fixed-point scale) folded into x
     if (threadIdx.x < nc * 3) {
       const int j = tj, dim = tdim;
       int gm;
@@ -104,7 +140,7 @@ __global__ void __launch_bounds__(256) k_spread(KArg<R, BATCH> ka) {
       Coord<R>::stencil(rec, dim, Md, P, gm, tau);
       R w[P];
       eval_window<R, P, NW>(win, tau, w);
-      const R sc = dim == 0 ? rec.q : R(1);
+      const R sc = dim == 0 ? (FIX ? rec.q * scale : rec.q) : R(1);
 #pragma unroll
       for (int p = 0; p < P; ++p) wts[(j * 3 + dim) * P + p] = w[p] * sc;
       base[j * 3 + dim] = gm - od;
@@ -125,12 +161,17 @@ __global__ void __launch_bounds__(256) k_spread(KArg<R, BATCH> ka) {
         wy[a] = wj[P + a];
       }
       const R wz = wj[2 * P + cz];
-      double* plane = grid + (base[j * 3 + 2] + cz) * S + base[j * 3 + 1] * E1 + base[j * 3];
+      Cell* plane = grid + (base[j * 3 + 2] + cz) * S + base[j * 3 + 1] * E1 + base[j * 3];
 #pragma unroll
       for (int by = 0; by < P; ++by) {
         const R v = wy[by] * wz;
 #pragma unroll
-        for (int a = 0; a < P; ++a) atomicAdd(plane + by * E1 + a, static_cast<double>(v * wx[a]));
+        for (int a = 0; a < P; ++a) {
+          if constexpr (FIX)
+            atomicAdd(plane + by * E1 + a, static_cast<unsigned long long>(to_fixed(v * wx[a])));
+          else
+            atomicAdd(plane + by * E1 + a, static_cast<double>(v * wx[a]));
+        }
       }
     }
     __syncthreads();
@@ -145,7 +186,11 @@ __global__ void __launch_bounds__(256) k_spread(KArg<R, BATCH> ka) {
     gy -= gy >= d.M2 ? d.M2 : 0;
     R* col = d.rho + static_cast<size_t>(gy) * d.M1 + gx;
     for (int z = 0; z < E3; ++z) {
-      const R val = static_cast<R>(grid[z * S + k0]);
+      R val;
+      if constexpr (FIX)
+        val = static_cast<R>(static_cast<double>(static_cast<long long>(grid[z * S + k0])) * unscale);
+      else
+        val = static_cast<R>(grid[z * S + k0]);
       int gz = o3 + z;
       gz -= gz >= d.M3 ? d.M3 : 0;
       if (val != R(0)) atomic_add_global(col + gz * planesz, val);
@@ -540,14 +585,19 @@ __global__ void __launch_bounds__(256) k_gather_tile(KArg<R, BATCH> ka, R* __res
 }
 
 // ---------------------------------------------------------------- launchers
-template <typename R, int P, int NW>
-static hipError_t spread_nw(const DevPlan<R>& d, hipStream_t s) {
+template <typename R, int P, int NW, bool FIX>
+static hipError_t spread_acc(const DevPlan<R>& d, hipStream_t s) {
   const size_t lds = lds_spread(d);
   if (lds > 65536)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spread<R, P, NW, false>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spread<R, P, NW, false, FIX>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-  hipLaunchKernelGGL((k_spread<R, P, NW, false>), dim3(d.ntiles), dim3(256), lds, s, KArg<R, false>{d});
+  hipLaunchKernelGGL((k_spread<R, P, NW, false, FIX>), dim3(d.ntiles), dim3(256), lds, s, KArg<R, false>{d});
   return hipGetLastError();
+}
+
+template <typename R, int P, int NW>
+static hipError_t spread_nw(const DevPlan<R>& d, hipStream_t s) {
+  return d.spread_fixed ? spread_acc<R, P, NW, true>(d, s) : spread_acc<R, P, NW, false>(d, s);
 }
 
 template <typename R, int P, int NW>
@@ -576,9 +626,9 @@ static hipError_t gather_nw(const DevPlan<R>& d, R* f, double* out7, hipStream_t
 template <typename R, int P, int NW>
 static hipError_t spread_nw_batch(const BatchLaunch<R>& b, hipStream_t s) {
   if (b.lds > 65536)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spread<R, P, NW, true>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spread<R, P, NW, true, false>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(b.lds));
-  hipLaunchKernelGGL((k_spread<R, P, NW, true>), dim3(b.nblk), dim3(256), b.lds, s,
+  hipLaunchKernelGGL((k_spread<R, P, NW, true, false>), dim3(b.nblk), dim3(256), b.lds, s,
                      KArg<R, true>{b.plans, b.boff, b.nrep});
   return hipGetLastError();
 }

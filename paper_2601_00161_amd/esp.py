@@ -25,6 +25,7 @@ PARAMS = {"analytic": 0, "explicit": 1, "learned": 2}
 COUPLING = {"iso": 0, "semi": 1, "aniso": 2, "flex": 3}
 GATHER = {"auto": 0, "particle": 1, "tile": 2}
 FORCE = {"ad": 0, "ik": 1}
+SPREAD_ACCUM = {"auto": 0, "fixed": 1, "fp64": 2}
 
 
 class EspError(RuntimeError):
@@ -39,7 +40,7 @@ class Opts(ctypes.Structure):
                 ("P", ctypes.c_int), ("M", ctypes.c_int * 3), ("grid_sigma", ctypes.c_double),
                 ("coulomb_k", ctypes.c_double), ("tile", ctypes.c_int), ("stream", ctypes.c_void_p),
                 ("window_tol", ctypes.c_double), ("gather", ctypes.c_int), ("force", ctypes.c_int),
-                ("local_virial", ctypes.c_int), ("fft_split", ctypes.c_int)]
+                ("local_virial", ctypes.c_int), ("fft_split", ctypes.c_int), ("spread_accum", ctypes.c_int)]
 
 
 class Params(ctypes.Structure):
@@ -53,7 +54,7 @@ class Params(ctypes.Structure):
                 ("predicted_log10_err", ctypes.c_double * 4), ("predicted_cost", ctypes.c_double),
                 ("gather_tiled", ctypes.c_int), ("counter_copies", ctypes.c_int), ("force", ctypes.c_int),
                 ("local_virial", ctypes.c_int), ("real_cells", ctypes.c_int * 3),
-                ("real_segments", ctypes.c_int), ("fft_split", ctypes.c_int)]
+                ("real_segments", ctypes.c_int), ("fft_split", ctypes.c_int), ("spread_fixed", ctypes.c_int)]
 
     def as_dict(self):
         out = {}
@@ -160,7 +161,8 @@ def _cell(h):
 
 def make_opts(precision="fp32", params="analytic", coupling="iso", rc=0.9, c_split=None,
               c_spread=None, P=None, M=None, grid_sigma=1.07, coulomb_k=1.0, tile=0, stream=None,
-              window_tol=0.0, gather="auto", force="ad", local_virial=False, fft_split=False):
+              window_tol=0.0, gather="auto", force="ad", local_virial=False, fft_split=False,
+              spread_accum="auto"):
     o = Opts()
     lib().esp_opts_default(ctypes.byref(o))
     o.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
@@ -190,6 +192,7 @@ def make_opts(precision="fp32", params="analytic", coupling="iso", rc=0.9, c_spl
     o.force = FORCE[force] if isinstance(force, str) else int(force)
     o.local_virial = 1 if local_virial else 0
     o.fft_split = 1 if fft_split else 0
+    o.spread_accum = SPREAD_ACCUM[spread_accum] if isinstance(spread_accum, str) else int(spread_accum)
     return o
 
 

@@ -22,7 +22,17 @@ def test_tuned_plan_matches_default_and_caches(tmp_path):
     cache = str(tmp_path / "tune.json")
     plan, info = autotune.tuned_plan(h, len(q), 1e-5, xyz, qq, cache=cache)
     assert info["tile"] in autotune.TILES and info["gather"] in autotune.GATHERS
-    assert f"{info['tile']}:{info['gather']}" in info["table"]
+    assert info["accum"] in autotune.ACCUMS
+    key = f"{info['tile']}:{info['gather']}" + (":fixed" if info["accum"] == "fixed" else "")
+    assert key in info["table"]
+    assert plan.params["spread_fixed"] == (1 if info["accum"] == "fixed" else 0)
+    # fixed point is tried exactly where tiles hold 128+ particles on average
+    for k in info["table"]:
+        t = int(k.split(":")[0])
+        if k.endswith(":fixed"):
+            probe = esp.Plan(h, len(q), 1e-5, tile=t)
+            assert len(q) >= autotune.FIXED_MIN_PER_TILE * probe.params["ntiles"]
+            probe.close()
     assert plan.params["tile"][0] == min(info["tile"], plan.params["M"][0])
     assert plan.params["gather_tiled"] == (1 if info["gather"] == "tile" else 0)
     data = json.load(open(cache))

@@ -80,6 +80,7 @@ def test_membrane_1m_semi_fp32():
     h, r, q = synth.config4()
     r_, q_, r64, q64 = as_inputs(r, q, "fp32")
     plan = esp.Plan(h, len(q), 1e-5, coupling="semi")
+    assert plan.params["spread_fixed"] == 1          # ~770 particles per tile: fixed-point spreading
     f, out = gpu(plan, r_, q_)
     compare(h, r64, q64, plan, f, out, "fp32")
     plan.close()

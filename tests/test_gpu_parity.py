@@ -102,13 +102,33 @@ def test_sort_is_a_valid_binning(case, precision, dev):
     plan.close()
 
 
+def test_spread_accumulator_rule(dev):
+    """The automatic choice takes 64-bit fixed point exactly when there are at
+    least 512 tiles holding at least 128 particles on average (the
+    10^6-particle slab of the full-size tests is such a case); explicit
+    choices are kept."""
+    for name, h, r, q, prm in SYSTEMS:
+        for tile in (0, 8):
+            plan = make_plan(h, len(q), prm, "fp32", tile=tile)
+            nt = plan.params["ntiles"]
+            want = nt >= 512 and len(q) >= 128 * nt
+            assert plan.params["spread_fixed"] == int(want), (name, tile)
+            plan.close()
+        for accum, want in (("fixed", 1), ("fp64", 0)):
+            plan = make_plan(h, len(q), prm, "fp32", spread_accum=accum)
+            assert plan.params["spread_fixed"] == want
+            plan.close()
+
+
+@pytest.mark.parametrize("accum", ["fixed", "fp64"])
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 @pytest.mark.parametrize("case", SYSTEMS, ids=IDS)
-def test_spread_grid(case, precision, dev):
-    """A2: the charge grid equals the oracle's Step-1 grid element by element."""
+def test_spread_grid(case, precision, accum, dev):
+    """A2: the charge grid equals the oracle's Step-1 grid element by element,
+    with either LDS accumulator."""
     name, h, r, q, prm = case
     r_, q_, r64, q64 = as_inputs(r, q, precision)
-    plan = make_plan(h, len(q), prm, precision)
+    plan = make_plan(h, len(q), prm, precision, spread_accum=accum)
     g = plan.stage_spread(to_dev(r_, dev), to_dev(q_, dev)).cpu().numpy().astype(np.float64)
     ref = oracle(h, r64, q64, prm, forces=False).rho_grid.transpose(2, 1, 0)
     # scale: the largest cell of the same grid spread with |q| (no cancellation).
@@ -140,6 +160,27 @@ def test_fft_against_numpy(M, precision, dev):
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("qscale", [1e-12, 1e12])
+def test_fixed_point_spread_follows_the_charge_scale(qscale, precision, dev):
+    """The fixed-point scale is chosen per tile from its charges: charges
+    multiplied by 1e-12 or 1e12 give the same grid times that factor (the
+    scale is a power of two, so up to the rounding of the factor itself), and
+    uncharged particles give an exactly zero grid."""
+    name, h, r, q, prm = SYSTEMS[0]
+    r_, q_, _, _ = as_inputs(r, q, precision)
+    plan = make_plan(h, len(q), prm, precision, spread_accum="fixed")
+    g1 = plan.stage_spread(to_dev(r_, dev), to_dev(q_, dev)).cpu().numpy().astype(np.float64)
+    qs = (q_.astype(np.float64) * qscale).astype(q_.dtype)
+    g2 = plan.stage_spread(to_dev(r_, dev), to_dev(qs, dev)).cpu().numpy().astype(np.float64)
+    g0 = plan.stage_spread(to_dev(r_, dev), to_dev(np.zeros_like(q_), dev)).cpu().numpy()
+    plan.close()
+    bar = 1e-6 if precision == "fp32" else 1e-12
+    assert np.all(np.isfinite(g2))
+    assert np.max(np.abs(g2 / qscale - g1)) <= bar * np.max(np.abs(g1))
+    assert not np.any(g0)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
 @pytest.mark.parametrize("case", SYSTEMS, ids=IDS)
 def test_energy_virial(case, precision, dev):
     """A4 + A7: energy and the six virial components from the single-FFT path."""
@@ -167,14 +208,15 @@ def test_potential_grid(case, precision, dev):
     plan.close()
 
 
+@pytest.mark.parametrize("accum", ["fixed", "fp64"])
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 @pytest.mark.parametrize("case", SYSTEMS, ids=IDS)
-def test_forces(case, precision, dev):
+def test_forces(case, precision, accum, dev):
     """A6: forces by analytic differentiation; E and W from the force path equal
-    those of the single-FFT path."""
+    those of the single-FFT path (either LDS accumulator of the spreading)."""
     name, h, r, q, prm = case
     r_, q_, r64, q64 = as_inputs(r, q, precision)
-    plan = make_plan(h, len(q), prm, precision)
+    plan = make_plan(h, len(q), prm, precision, spread_accum=accum)
     xyz, qq = to_dev(r_, dev), to_dev(q_, dev)
     f, out = plan.forces(xyz, qq)
     f = f.cpu().numpy().astype(np.float64)
