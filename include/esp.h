@@ -116,13 +116,15 @@ typedef struct {
   int fft_split;       /* nonzero: run the x and y transforms as separate passes even
                           when a grid plane fits one workgroup's LDS (planes that do
                           not fit always take them) */
-  int spread_accum;    /* accumulator of the spreading tile in LDS: ESP_SPREAD_AUTO (0,
-                          64-bit fixed point when there are 512+ tiles holding 128+
-                          particles on average, else FP64), ESP_SPREAD_FIXED (1) or
-                          ESP_SPREAD_FP64 (2).  Fixed point: per tile, scale 2^e with
-                          2^e wmax^3 sum|q| < 2^62, each contribution rounded once to
-                          2^-e, exact integer sums.  Single plans only; batched
-                          launches use FP64. */
+  int spread_accum;    /* accumulator of the spreading tile in LDS: ESP_SPREAD_AUTO (0:
+                          64-bit fixed point for FP32 plans; for FP64 plans when
+                          there are 512+ tiles holding 128+ particles on average,
+                          else FP64), ESP_SPREAD_FIXED (1) or ESP_SPREAD_FP64 (2).
+                          Fixed point: per tile, scale 2^e with 2^e wmax^3 sum|q|
+                          <= 2^59 (FP32) or < 2^62 (FP64), each term rounded once to
+                          2^-e, exact integer sums (FP32 terms: the int32-rounded
+                          factors q wx 2^eq and wy wz 2^ka multiplied exactly).
+                          Single plans only; batched launches use FP64. */
 } esp_opts;
 
 enum { ESP_GATHER_AUTO = 0, ESP_GATHER_PARTICLE = 1, ESP_GATHER_TILE = 2 };

@@ -1,7 +1,7 @@
 """Autotuner for the launch shape of a plan: the spreading tile edge, the
 gather variant (per particle, or tile-staged potential in LDS) and the LDS
-accumulator of the spreading (FP64, or 64-bit fixed point where tiles hold
-128+ particles on average).
+accumulator of the spreading (FP64, or 64-bit fixed point: always tried for
+FP32 plans, for FP64 plans where tiles hold 128+ particles on average).
 
 Each admissible candidate is timed on the GPU with the caller's own
 particles (one esp_forces call = one step, HIP events over repeated calls)
@@ -25,7 +25,7 @@ from . import esp
 TILES = (4, 5, 6, 8, 10, 12)
 GATHERS = ("particle", "tile")
 ACCUMS = ("fp64", "fixed")
-FIXED_MIN_PER_TILE = 128          # fixed point is tried only from this many particles per tile
+FIXED_MIN_PER_TILE = 128          # FP64 plans: fixed point is tried from this many particles per tile
 DEFAULT_CACHE = os.environ.get("ESP_AUTOTUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache",
                                                                   "esp_mi355x_autotune.json"))
 
@@ -83,8 +83,9 @@ def tune(h, n, tol, xyz, q, reps=20, tiles=TILES, gathers=GATHERS, accums=ACCUMS
                     plan = esp.Plan(h, n, tol, tile=t, gather=g, spread_accum=a, **opts)
                 except esp.EspError:
                     continue                  # not admissible for this grid (LDS, tile count)
-                if a == "fixed" and n < FIXED_MIN_PER_TILE * plan.params["ntiles"]:
-                    plan.close()              # sparse tiles: fixed point is slower (measured)
+                if (a == "fixed" and plan.params["precision"] == 1
+                        and n < FIXED_MIN_PER_TILE * plan.params["ntiles"]):
+                    plan.close()              # FP64, sparse tiles: fixed point is slower (measured)
                     continue
                 us = time_step(plan, xyz, q, reps=reps)
                 plan.close()

@@ -19,8 +19,8 @@ constexpr int kMaxRadix = 8;
 constexpr int kMaxStages = 16;
 constexpr int kNumSums = 7;        // energy + 6 virial components
 constexpr int kSpreadChunk = 64;   // particles staged per spreading round
-constexpr int kSpreadFixedMin = 128;  // automatic fixed-point spreading: mean particles per tile
-constexpr int kSpreadFixedMinTiles = 512;  // ... and tiles (two per CU) at least
+constexpr int kSpreadFixedMin = 128;  // automatic fixed-point spreading of FP64 plans: mean particles
+constexpr int kSpreadFixedMinTiles = 512;  // per tile, and tiles (two per CU), at least
 constexpr int kTiledGatherMin = 96;  // mean particles per tile above which the gather is tile-staged
 constexpr int kBinContention = 64;   // target same-address atomics per tile counter in binning
 constexpr int kMaxCounterCopies = 16;
@@ -81,7 +81,7 @@ struct DevPlan {
   R A;                             // 2 pi lam0 / C0 of the splitting PSWF
   R inv_vol;                       // 1 / V
   R coulomb_k;
-  float wmax3;                     // bound of |window value|^3 (sets the spreading's fixed-point scale)
+  float wmax, wmax3;               // bound of |window value| and its cube (fixed-point spreading scales)
   int spread_fixed;                // spreading tile in 64-bit fixed point (else FP64)
   // tables (device)
   const R* win;                    // (nw + 1) x P monomial coefficients in tau, coefficient-major

@@ -702,7 +702,7 @@ template <typename R>
 size_t lds_spread(const DevPlan<R>& d) {
   const size_t cells = ((static_cast<size_t>(d.T1 + d.P - 1) * (d.T2 + d.P - 1)) | 1) * (d.T3 + d.P - 1);
   return cells * sizeof(double) + (kSpreadChunk * 3 * d.P + d.P * (d.nw + 1)) * sizeof(R) +
-         kSpreadChunk * 3 * sizeof(int) + 16;
+         kSpreadChunk * 4 * sizeof(int) + 16;
 }
 
 // Raise the dynamic-LDS limit of a kernel when a launch needs more than 64 KiB.

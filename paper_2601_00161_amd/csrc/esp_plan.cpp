@@ -651,6 +651,7 @@ esp_status build_device(esp_plan_t* p) {
         for (int j = p->nw; j >= 0; --j) v = v * tau + win[static_cast<size_t>(j) * r.P + q];
         wm = std::max(wm, std::fabs(v));
       }
+    d.wmax = static_cast<float>(1.01 * wm);
     d.wmax3 = static_cast<float>(1.01 * wm * wm * wm);
   }
   std::vector<double> cf, cg;
@@ -721,13 +722,15 @@ esp_status build_device(esp_plan_t* p) {
   // separate x and y passes with as many row pairs / columns per workgroup
   // (up to 16) as fit
   d.xy_split = r.fft_split || lds_fft_xy(d) > static_cast<size_t>(maxlds) ? 1 : 0;
-  // fixed-point spreading pays for its pass over the charges and its longer
-  // conversions only where the LDS atomics bound the kernel: crowded tiles,
-  // and enough of them to keep every CU busy (measured: faster with 1,296
-  // tiles of ~770 particles, slower with 125 tiles of ~240 or 729 of ~40)
+  // fixed-point spreading: FP32 terms are integer products (two VALU
+  // instructions), faster than the FP64 adds on every shape measured (729
+  // tiles of ~40 particles to 1,296 of ~770).  FP64 terms need the long
+  // f64 -> i64 conversion, which pays only where the LDS atomics bound the
+  // kernel: crowded tiles, and enough of them to keep every CU busy.
   d.spread_fixed = r.spread_accum == ESP_SPREAD_FIXED ||
-                   (r.spread_accum == ESP_SPREAD_AUTO && r.ntiles >= kSpreadFixedMinTiles &&
-                    r.n >= static_cast<int64_t>(kSpreadFixedMin) * r.ntiles);
+                   (r.spread_accum == ESP_SPREAD_AUTO &&
+                    (r.precision == ESP_FP32 || (r.ntiles >= kSpreadFixedMinTiles &&
+                                                 r.n >= static_cast<int64_t>(kSpreadFixedMin) * r.ntiles)));
   d.xpairs = d.ycols = 16;
   while (d.xpairs > 1 && lds_fft_x(d, d.xpairs) > static_cast<size_t>(maxlds)) d.xpairs /= 2;
   while (d.ycols > 1 && lds_fft_y(d, d.ycols) > static_cast<size_t>(maxlds)) d.ycols /= 2;

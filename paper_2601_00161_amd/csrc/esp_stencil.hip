@@ -57,18 +57,23 @@ __device__ __forceinline__ void window_d_lanes(const R* __restrict__ win, R t1, 
 // One workgroup per tile of T1 x T2 x T3 grid cells.  Its particles (those
 // whose stencil base lies in the tile, contiguous after the cell sort) are
 // spread into an LDS copy of the tile plus its (P - 1)-wide upper halo, which
-// is then added to the periodic grid.  Products are formed in R; the LDS tile
-// accumulates them in 8-byte cells (ds_add_f32 is several times slower on
-// gfx950 than the 8-byte LDS adds):
-//  * FIX = false: FP64 (ds_add_f64).
+// is then added to the periodic grid.  The LDS tile accumulates in 8-byte
+// cells (ds_add_f32 is several times slower on gfx950 than the 8-byte LDS
+// adds):
+//  * FIX = false: FP64 (ds_add_f64) of products formed in R.
 //  * FIX = true: 64-bit fixed point (ds_add_u64, faster than ds_add_f64 on
 //    crowded tiles).  The scale 2^e is the tile's own: with
 //    b = wmax^3 sum |q_j| over its particles no cell can exceed b in
-//    magnitude, and 2^e b < 2^62 keeps a factor of two of the int64 range
-//    spare.  Each contribution is rounded once, to 2^-e (at most 2^-61 b);
-//    the integer sums are exact, so a cell does not depend on the order of
-//    the atomics.  The pass over the tile's charges that gives b costs more
-//    than the faster atomics save when a tile holds few particles.
+//    magnitude, and 2^e b <= 2^59 (FP32) or < 2^62 (FP64) keeps the int64
+//    sums in range.  The integer sums are exact, so a cell does not depend
+//    on the order of the atomics.  FP64 plans round each product q wx wy wz
+//    2^e to an integer.  FP32 plans form each term as an exact integer
+//    product: B_a = q wx_a 2^eq and A = wy wz 2^ka are rounded to int32
+//    (|B|, |A| < 2^31; the float products before the rounding are the same
+//    two roundings as the float path's), and A B 2^-s, s = eq + ka - e >= 1,
+//    is taken with one rounding shift: two VALU instructions per term.
+//    The pass over the tile's charges that gives b costs more than the faster
+//    atomics save when a tile holds few particles.
 template <typename R>
 __device__ __forceinline__ long long to_fixed(R y) {
   return static_cast<long long>(rint(y));
@@ -78,6 +83,7 @@ template <typename R, int P, int NW, bool BATCH, bool FIX>
 __global__ void __launch_bounds__(256) k_spread(KArg<R, BATCH> ka) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ float qabs[4];                          // FIX: per-wave sums of |q| (256 threads)
+  constexpr bool IPROD = FIX && sizeof(R) == 4;      // integer-product terms (FP32)
   int tile;
   const DevPlan<R>& d = plan_of(ka, tile);
   const int t1 = tile % d.nt1, t2 = (tile / d.nt1) % d.nt2, t3 = tile / (d.nt1 * d.nt2);
@@ -92,9 +98,10 @@ __global__ void __launch_bounds__(256) k_spread(KArg<R, BATCH> ka) {
   const int maxcell = (((d.T1 + P - 1) * (d.T2 + P - 1)) | 1) * (d.T3 + P - 1);
   using Cell = typename std::conditional<FIX, unsigned long long, double>::type;
   Cell* grid = reinterpret_cast<Cell*>(smem);
-  R* wts = reinterpret_cast<R*>(grid + maxcell);     // kSpreadChunk x 3 x P
+  R* wts = reinterpret_cast<R*>(grid + maxcell);     // kSpreadChunk x 3 x P (IPROD: x slots hold B)
   R* win = wts + kSpreadChunk * 3 * P;               // (NW + 1) x P
   int* base = reinterpret_cast<int*>(win + (NW + 1) * P);   // kSpreadChunk x 3
+  int* shf = base + kSpreadChunk * 3;                // IPROD: kSpreadChunk shifts s
   const int start = d.offsets[tile], end = d.offsets[tile + 1];
   const R wv = d.win[min(static_cast<int>(threadIdx.x), (NW + 1) * P - 1)];   // in flight with the offsets
   if (threadIdx.x == 0) d.counts[tile] = 0;        // ready for the next binning pass
@@ -120,13 +127,15 @@ __global__ void __launch_bounds__(256) k_spread(KArg<R, BATCH> ka) {
   __syncthreads();
   R scale = R(1);
   double unscale = 1.0;
+  int e = 0, kA = 0;
   if constexpr (FIX) {
     // the float sum of |q| is within n 2^-24 (relative) of the exact one,
-    // far inside the spare factor of two for any tile
+    // far inside the margins of the exponents below
     const float bnd = (qabs[0] + qabs[1] + qabs[2] + qabs[3]) * d.wmax3;
-    const int e = max(-100, min(120, 61 - ilogbf(fmaxf(bnd, 1e-30f))));
+    e = max(-100, min(120, (IPROD ? 58 : 61) - ilogbf(fmaxf(bnd, 1e-30f))));
     scale = static_cast<R>(ldexpf(1.f, e));
     unscale = ldexp(1.0, -e);
+    kA = 30 - ilogbf(d.wmax * d.wmax);               // |wy wz| 2^kA < 2^31
   }
   for (int c0 = start; c0 < end; c0 += kSpreadChunk) {
     const int nc = min(kSpreadChunk, end - c0);
@@ -140,9 +149,26 @@ __global__ void __launch_bounds__(256) k_spread(KArg<R, BATCH> ka) {
       Coord<R>::stencil(rec, dim, Md, P, gm, tau);
       R w[P];
       eval_window<R, P, NW>(win, tau, w);
-      const R sc = dim == 0 ? (FIX ? rec.q * scale : rec.q) : R(1);
+      if constexpr (IPROD) {
+        if (dim == 0) {
+          // B_p = q w_p 2^eq with |q| wmax 2^eq < 2^31; s = eq + kA - e
+          const float qa = fabsf(static_cast<float>(rec.q)) * d.wmax;
+          const int eq = qa > 0.f ? 30 - ilogbf(qa) : 0;
+          const float sq = ldexpf(static_cast<float>(rec.q), eq);
+          int* bw = reinterpret_cast<int*>(wts + j * 3 * P);
 #pragma unroll
-      for (int p = 0; p < P; ++p) wts[(j * 3 + dim) * P + p] = w[p] * sc;
+          for (int p = 0; p < P; ++p) bw[p] = __float2int_rn(static_cast<float>(w[p]) * sq);
+          shf[j] = qa > 0.f ? max(0, min(63, eq + kA - e)) : 0;
+        } else {
+          const R sc = dim == 2 ? static_cast<R>(ldexpf(1.f, kA)) : R(1);
+#pragma unroll
+          for (int p = 0; p < P; ++p) wts[(j * 3 + dim) * P + p] = w[p] * sc;
+        }
+      } else {
+        const R sc = dim == 0 ? (FIX ? rec.q * scale : rec.q) : R(1);
+#pragma unroll
+        for (int p = 0; p < P; ++p) wts[(j * 3 + dim) * P + p] = w[p] * sc;
+      }
       base[j * 3 + dim] = gm - od;
     }
     __syncthreads();
@@ -154,23 +180,39 @@ __global__ void __launch_bounds__(256) k_spread(KArg<R, BATCH> ka) {
     for (int t = threadIdx.x; t < nc * P; t += blockDim.x) {
       const int j = t / P, cz = t - j * P;
       const R* wj = wts + j * 3 * P;
-      R wx[P], wy[P];
+      R wy[P];
 #pragma unroll
-      for (int a = 0; a < P; ++a) {
-        wx[a] = wj[a];
-        wy[a] = wj[P + a];
-      }
+      for (int a = 0; a < P; ++a) wy[a] = wj[P + a];
       const R wz = wj[2 * P + cz];
       Cell* plane = grid + (base[j * 3 + 2] + cz) * S + base[j * 3 + 1] * E1 + base[j * 3];
+      if constexpr (IPROD) {
+        const int* bj = reinterpret_cast<const int*>(wj);
+        int bx[P];
 #pragma unroll
-      for (int by = 0; by < P; ++by) {
-        const R v = wy[by] * wz;
+        for (int a = 0; a < P; ++a) bx[a] = bj[a];
+        const int sh = shf[j];
+        const long long rnd = sh > 0 ? (1ll << (sh - 1)) : 0ll;
 #pragma unroll
-        for (int a = 0; a < P; ++a) {
-          if constexpr (FIX)
-            atomicAdd(plane + by * E1 + a, static_cast<unsigned long long>(to_fixed(v * wx[a])));
-          else
-            atomicAdd(plane + by * E1 + a, static_cast<double>(v * wx[a]));
+        for (int by = 0; by < P; ++by) {
+          const long long A = __float2int_rn(static_cast<float>(wy[by] * wz));
+#pragma unroll
+          for (int a = 0; a < P; ++a)
+            atomicAdd(plane + by * E1 + a, static_cast<unsigned long long>((A * bx[a] + rnd) >> sh));
+        }
+      } else {
+        R wx[P];
+#pragma unroll
+        for (int a = 0; a < P; ++a) wx[a] = wj[a];
+#pragma unroll
+        for (int by = 0; by < P; ++by) {
+          const R v = wy[by] * wz;
+#pragma unroll
+          for (int a = 0; a < P; ++a) {
+            if constexpr (FIX)
+              atomicAdd(plane + by * E1 + a, static_cast<unsigned long long>(to_fixed(v * wx[a])));
+            else
+              atomicAdd(plane + by * E1 + a, static_cast<double>(v * wx[a]));
+          }
         }
       }
     }

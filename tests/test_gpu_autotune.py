@@ -26,13 +26,10 @@ def test_tuned_plan_matches_default_and_caches(tmp_path):
     key = f"{info['tile']}:{info['gather']}" + (":fixed" if info["accum"] == "fixed" else "")
     assert key in info["table"]
     assert plan.params["spread_fixed"] == (1 if info["accum"] == "fixed" else 0)
-    # fixed point is tried exactly where tiles hold 128+ particles on average
-    for k in info["table"]:
-        t = int(k.split(":")[0])
-        if k.endswith(":fixed"):
-            probe = esp.Plan(h, len(q), 1e-5, tile=t)
-            assert len(q) >= autotune.FIXED_MIN_PER_TILE * probe.params["ntiles"]
-            probe.close()
+    # an FP32 plan tries both accumulators for every tile and gather variant
+    for k in list(info["table"]):
+        if not k.endswith(":fixed"):
+            assert k + ":fixed" in info["table"]
     assert plan.params["tile"][0] == min(info["tile"], plan.params["M"][0])
     assert plan.params["gather_tiled"] == (1 if info["gather"] == "tile" else 0)
     data = json.load(open(cache))

@@ -103,21 +103,24 @@ def test_sort_is_a_valid_binning(case, precision, dev):
 
 
 def test_spread_accumulator_rule(dev):
-    """The automatic choice takes 64-bit fixed point exactly when there are at
-    least 512 tiles holding at least 128 particles on average (the
-    10^6-particle slab of the full-size tests is such a case); explicit
-    choices are kept."""
+    """The automatic choice takes 64-bit fixed point for FP32 plans, and for
+    FP64 plans exactly when there are at least 512 tiles holding at least
+    128 particles on average; explicit choices are kept."""
     for name, h, r, q, prm in SYSTEMS:
         for tile in (0, 8):
             plan = make_plan(h, len(q), prm, "fp32", tile=tile)
+            assert plan.params["spread_fixed"] == 1, (name, tile)
+            plan.close()
+            plan = make_plan(h, len(q), prm, "fp64", tile=tile)
             nt = plan.params["ntiles"]
             want = nt >= 512 and len(q) >= 128 * nt
             assert plan.params["spread_fixed"] == int(want), (name, tile)
             plan.close()
-        for accum, want in (("fixed", 1), ("fp64", 0)):
-            plan = make_plan(h, len(q), prm, "fp32", spread_accum=accum)
-            assert plan.params["spread_fixed"] == want
-            plan.close()
+        for precision in ("fp32", "fp64"):
+            for accum, want in (("fixed", 1), ("fp64", 0)):
+                plan = make_plan(h, len(q), prm, precision, spread_accum=accum)
+                assert plan.params["spread_fixed"] == want
+                plan.close()
 
 
 @pytest.mark.parametrize("accum", ["fixed", "fp64"])
