@@ -221,22 +221,52 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// One DPP step on a double (both 32-bit halves moved the same way); lanes of
+// rows outside ROWMASK, or without a source lane, read 0.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_double(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), CTRL, ROWMASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, ROWMASK, 0xf, false);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// Sum of a double over the 64 lanes, left in lane 63, with DPP moves only
+// (no LDS permutes): quad swaps, half-row and row mirrors give every lane its
+// row's sum; row broadcasts of lanes 15 and 31 then carry rows 0 + 1 and
+// rows 0..2 into row 3.
+__device__ __forceinline__ double wave_sum_to_last(double v) {
+  v += dpp_double<0xb1, 0xf>(v);     // quad_perm [1, 0, 3, 2]
+  v += dpp_double<0x4e, 0xf>(v);     // quad_perm [2, 3, 0, 1]
+  v += dpp_double<0x141, 0xf>(v);    // row_half_mirror
+  v += dpp_double<0x140, 0xf>(v);    // row_mirror
+  v += dpp_double<0x142, 0xa>(v);    // row_bcast:15 into rows 1 and 3
+  v += dpp_double<0x143, 0xc>(v);    // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
 // Block-wide sums of NV doubles (fixed order, deterministic).  red: LDS of
-// at least NV * (blockDim / 64) doubles.  Result valid in thread 0.
+// at least NV * 16 doubles.  Result valid in thread 0.
 template <int NV>
 __device__ void block_sum(double* v, double* red) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #pragma unroll
-  for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
-  if (lane == 0)
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum_to_last(v[k]);
+  if (lane == 63)
 #pragma unroll
     for (int k = 0; k < NV; ++k) red[k * 16 + wid] = v[k];
   __syncthreads();
   if (threadIdx.x == 0) {
+    // all 16 slots are read at once (those of absent waves are selected
+    // out), so the loads overlap instead of forming a chain of LDS round trips
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
       double s = 0;
-      for (int w = 0; w < nw; ++w) s += red[k * 16 + w];
+#pragma unroll
+      for (int w = 0; w < 16; ++w) {
+        const double t = red[k * 16 + w];
+        s += w < nw ? t : 0.0;
+      }
       v[k] = s;
     }
   }

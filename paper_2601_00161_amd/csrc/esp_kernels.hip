@@ -543,6 +543,16 @@ __global__ void __launch_bounds__(256) k_fft_z(KArg<R, BATCH> ka, int mode) {
   }
   const Cplx<R> twv = d.tw[d.f3.tw + min(tid, M3 - 1)];
   const R kfv = d.kerf[min(tid, d.nker)], kgv = d.kerg[min(tid, d.nker)];
+  // the 1 / W_hat^2 factors of the scaling, fetched with the column
+  R iw1p[U], iw3p[U];
+  const R iwy = d.iw2[y];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int k = min(tid + u * nth, nc * M3 - 1);
+    const int z = k / nc, c = k - z * nc;
+    iw1p[u] = d.iw1[k0 + c];
+    iw3p[u] = d.iw3[z];
+  }
 #pragma unroll
   for (int u = 0; u < U; ++u)
     if (tid + u * nth < nc * M3) A[tid + u * nth] = cv[u];
@@ -571,7 +581,8 @@ __global__ void __launch_bounds__(256) k_fft_z(KArg<R, BATCH> ka, int mode) {
   }
   Acc<R> acc[kNumSums];
   const int m2 = y <= (M2 - 1) / 2 ? y : y - M2;
-  for (int k = tid; k < nc * M3; k += nth) {
+  // element k of the block; iw = 1 / W_hat^2 of its mode
+  auto scale_one = [&](int k, R iw) {
     const int z = k / nc, c = k - z * nc;
     const int i1 = k0 + c;
     const int m1 = i1 <= (M1 - 1) / 2 ? i1 : i1 - M1;
@@ -591,7 +602,6 @@ __global__ void __launch_bounds__(256) k_fft_z(KArg<R, BATCH> ka, int mode) {
       const R ik = R(1) / kk;
       const R Fh = d.A * f * ik;
       const R beta = (d.A * xg * ik - R(2) * Fh) * ik;
-      const R iw = d.iw1[i1] * d.iw2[y] * d.iw3[z];
       const R wgt = (i1 == 0 || 2 * i1 == M1) ? R(1) : R(2);
       const R e = wgt * (v.x * v.x + v.y * v.y) * iw;
       const R Fe = Fh * e, be = beta * e;
@@ -611,16 +621,34 @@ __global__ void __launch_bounds__(256) k_fft_z(KArg<R, BATCH> ka, int mode) {
       fw[k] = fl;
       bw[k] = bl;
     }
+  };
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (tid + u * nth < nc * M3) scale_one(tid + u * nth, iw1p[u] * iwy * iw3p[u]);
+  for (int k = tid + U * nth; k < nc * M3; k += nth) {
+    const int z = k / nc, c = k - z * nc;
+    scale_one(k, d.iw1[k0 + c] * iwy * d.iw3[z]);
   }
-  double sums[kNumSums];
+  // block sums: wave sums by DPP, one LDS slot per wave, and the barrier that
+  // also orders the scaled column before the inverse transform; thread k then
+  // adds the wave slots of sum k (in wave order, as block_sum does)
 #pragma unroll
-  for (int k = 0; k < kNumSums; ++k) sums[k] = acc[k].value();
-  block_sum<kNumSums>(sums, red);
-  if (tid == 0)
-#pragma unroll
-    for (int k = 0; k < kNumSums; ++k) d.zpart[static_cast<size_t>(blk) * kNumSums + k] = sums[k];
-  if (mode == Z_ENERGY) return;
+  for (int k = 0; k < kNumSums; ++k) {
+    const double w = wave_sum_to_last(acc[k].value());
+    if ((tid & 63) == 63) red[k * 16 + (tid >> 6)] = w;
+  }
   __syncthreads();
+  if (tid < kNumSums) {
+    const int nw = nth >> 6;
+    double s = 0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) {
+      const double t = red[tid * 16 + w];
+      s += w < nw ? t : 0.0;
+    }
+    d.zpart[static_cast<size_t>(blk) * kNumSums + tid] = s;
+  }
+  if (mode == Z_ENERGY) return;
   Cplx<R>* oth = res == A ? B : A;
   if (mode == Z_POTENTIAL) {
     res = fft_lines(res, oth, d.f3, nc, 1, nc, tw3, true, nth);

@@ -170,8 +170,10 @@ def test_coulomb_overlapped_matches_the_two_calls(precision, force):
         assert plan.check() == esp.ESP_OK
         results.append((f.double().cpu().numpy(), o.cpu().numpy()))
     for f, o in results:
+        # two GPU runs whose FP32 sums differ in order: compared on the scale of
+        # the largest component (the off-diagonal virial is 100x smaller)
         assert rel_rms(f, f_ref) < same
-        assert np.allclose(o, o_ref, rtol=same, atol=0)
+        assert np.max(np.abs(o - o_ref)) <= same * np.max(np.abs(o_ref))
         assert abs(o[0] - exact.energy) <= 1e-5 * abs(exact.energy)
         assert tensor_rel(o, exact.virial) < 1e-5
         assert rel_rms(f, exact.forces) < 1e-5
