@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "esp_device.h"
 
@@ -231,6 +232,30 @@ __device__ __forceinline__ double dpp_double(double v) {
   return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
 }
 
+// Sum over aligned groups of L lanes (L = 2, 4, 8 or 16), left in every lane
+// of the group, with DPP moves only: quad swaps, then half-row and row
+// mirrors (each pairs lanes of the two halves of the next larger group).
+template <int CTRL>
+__device__ __forceinline__ float dpp_float(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+template <int L, typename R>
+__device__ __forceinline__ R lane_group_sum(R v) {
+  static_assert(L == 1 || L == 2 || L == 4 || L == 8 || L == 16, "groups within one DPP row");
+  auto step = [](R x, auto ctrl) {
+    constexpr int C = decltype(ctrl)::value;
+    if constexpr (sizeof(R) == 8)
+      return x + dpp_double<C, 0xf>(x);
+    else
+      return x + dpp_float<C>(x);
+  };
+  if constexpr (L >= 2) v = step(v, std::integral_constant<int, 0xb1>{});    // quad_perm [1, 0, 3, 2]
+  if constexpr (L >= 4) v = step(v, std::integral_constant<int, 0x4e>{});    // quad_perm [2, 3, 0, 1]
+  if constexpr (L >= 8) v = step(v, std::integral_constant<int, 0x141>{});   // row_half_mirror
+  if constexpr (L >= 16) v = step(v, std::integral_constant<int, 0x140>{});  // row_mirror
+  return v;
+}
+
 // Sum of a double over the 64 lanes, left in lane 63, with DPP moves only
 // (no LDS permutes): quad swaps, half-row and row mirrors give every lane its
 // row's sum; row broadcasts of lanes 15 and 31 then carry rows 0 + 1 and
@@ -257,16 +282,10 @@ __device__ void block_sum(double* v, double* red) {
     for (int k = 0; k < NV; ++k) red[k * 16 + wid] = v[k];
   __syncthreads();
   if (threadIdx.x == 0) {
-    // all 16 slots are read at once (those of absent waves are selected
-    // out), so the loads overlap instead of forming a chain of LDS round trips
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
       double s = 0;
-#pragma unroll
-      for (int w = 0; w < 16; ++w) {
-        const double t = red[k * 16 + w];
-        s += w < nw ? t : 0.0;
-      }
+      for (int w = 0; w < nw; ++w) s += red[k * 16 + w];
       v[k] = s;
     }
   }

@@ -244,7 +244,7 @@ __global__ void __launch_bounds__(256) k_spread(KArg<R, BATCH> ka) {
 // L = 2^k >= P lanes per particle.  Lanes 0..2 evaluate the P window values
 // and derivatives of one dimension each and stage them in LDS; lane c < P
 // then sums z-plane c of the stencil against phi; the L partial gradients are
-// reduced with cross-lane shuffles.  F = q G grad_u, G = -h^-T diag(M).
+// reduced with DPP lane moves.  F = q G grad_u, G = -h^-T diag(M).
 template <int P>
 struct GatherLanes {
   static constexpr int L = gather_lanes(P);
@@ -320,12 +320,9 @@ __global__ void __launch_bounds__(256) k_gather(KArg<R, BATCH> ka, R* __restrict
     gy = syz * my[4 * P + lane];
     gz = s0z * my[5 * P + lane];
   }
-#pragma unroll
-  for (int off = L / 2; off > 0; off >>= 1) {
-    gx += __shfl_xor(gx, off, 64);
-    gy += __shfl_xor(gy, off, 64);
-    gz += __shfl_xor(gz, off, 64);
-  }
+  gx = lane_group_sum<L>(gx);
+  gy = lane_group_sum<L>(gy);
+  gz = lane_group_sum<L>(gz);
   if (lane == 0 && valid) {
     const R qk = rec.q * d.coulomb_k;
     f[3 * j + 0] = qk * (d.G[0] * gx + d.G[1] * gy + d.G[2] * gz);
@@ -411,12 +408,9 @@ __global__ void __launch_bounds__(256) k_gather_ik(KArg<R, BATCH> ka, R* __restr
     ey *= w3;
     ez *= w3;
   }
-#pragma unroll
-  for (int off = L / 2; off > 0; off >>= 1) {
-    ex += __shfl_xor(ex, off, 64);
-    ey += __shfl_xor(ey, off, 64);
-    ez += __shfl_xor(ez, off, 64);
-  }
+  ex = lane_group_sum<L>(ex);
+  ey = lane_group_sum<L>(ey);
+  ez = lane_group_sum<L>(ez);
   if (lane == 0 && valid) {
     const R qk = -rec.q * d.coulomb_k;
     f[3 * j + 0] = qk * ex;
@@ -500,9 +494,7 @@ __global__ void __launch_bounds__(256) k_gather_local(KArg<R, BATCH> ka, R* __re
     for (int c = 0; c < 6; ++c) acc[c] *= w3;
   }
 #pragma unroll
-  for (int off = L / 2; off > 0; off >>= 1)
-#pragma unroll
-    for (int c = 0; c < 6; ++c) acc[c] += __shfl_xor(acc[c], off, 64);
+  for (int c = 0; c < 6; ++c) acc[c] = lane_group_sum<L>(acc[c]);
   if (lane == 0 && valid) {
     const R qk = rec.q * d.coulomb_k;
 #pragma unroll
@@ -611,12 +603,9 @@ __global__ void __launch_bounds__(256) k_gather_tile(KArg<R, BATCH> ka, R* __res
       gy = syz * my[4 * P + lane];
       gz = s0z * my[5 * P + lane];
     }
-#pragma unroll
-    for (int off = L / 2; off > 0; off >>= 1) {
-      gx += __shfl_xor(gx, off, 64);
-      gy += __shfl_xor(gy, off, 64);
-      gz += __shfl_xor(gz, off, 64);
-    }
+    gx = lane_group_sum<L>(gx);
+    gy = lane_group_sum<L>(gy);
+    gz = lane_group_sum<L>(gz);
     if (lane == 0 && valid) {
       const R qk = rec.q * d.coulomb_k;
       f[3 * j + 0] = qk * (d.G[0] * gx + d.G[1] * gy + d.G[2] * gz);
