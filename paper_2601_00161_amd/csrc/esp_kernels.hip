@@ -24,8 +24,27 @@
 namespace espx {
 
 // ------------------------------------------------------------------- sort
-// Exclusive scan of counts[0..n) into offs[0..n] (LDS) by one workgroup, in a
-// fixed order.  part: LDS scratch of blockDim.x ints.
+// Inclusive scan of an int over the 64 lanes of a wave with DPP moves: row
+// shifts by 1, 2, 4 and 8 scan each row of 16 lanes (lanes without a source
+// add 0), then the row broadcasts of lanes 15 and 31 carry the earlier rows.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ int dpp_int(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWMASK, 0xf, false);
+}
+__device__ __forceinline__ int wave_inclusive_scan(int v) {
+  v += dpp_int<0x111, 0xf>(v);      // row_shr:1
+  v += dpp_int<0x112, 0xf>(v);      // row_shr:2
+  v += dpp_int<0x114, 0xf>(v);      // row_shr:4
+  v += dpp_int<0x118, 0xf>(v);      // row_shr:8
+  v += dpp_int<0x142, 0xa>(v);      // row_bcast:15 into rows 1 and 3
+  v += dpp_int<0x143, 0xc>(v);      // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
+// Exclusive scan of counts[0..n) into offs[0..n] (LDS) by one workgroup
+// (integer sums: exact).  Each thread sums a contiguous chunk; the chunk sums
+// are scanned within each wave by DPP, the wave totals (at most 16) go
+// through LDS with one barrier.  part: LDS scratch of at least 16 ints.
 __device__ void block_scan(const int* __restrict__ counts, int* offs, int n, int* part) {
   const int nth = blockDim.x;
   const int chunk = (n + nth - 1) / nth;
@@ -33,20 +52,23 @@ __device__ void block_scan(const int* __restrict__ counts, int* offs, int n, int
   const int b1 = min(n, b0 + chunk);
   int s = 0;
   for (int k = b0; k < b1; ++k) s += counts[k];
-  part[threadIdx.x] = s;
+  const int incl = wave_inclusive_scan(s);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 63) part[wid] = incl;
   __syncthreads();
-  for (int off = 1; off < nth; off <<= 1) {
-    const int add = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
-    __syncthreads();
-    part[threadIdx.x] += add;
-    __syncthreads();
+  int wpre = 0, total = 0;
+#pragma unroll
+  for (int w = 0; w < 16; ++w) {
+    const int t = w < (nth >> 6) ? part[w] : 0;
+    wpre += w < wid ? t : 0;
+    total += t;
   }
-  int run = part[threadIdx.x] - s;
+  int run = wpre + incl - s;
   for (int k = b0; k < b1; ++k) {
     offs[k] = run;
     run += counts[k];
   }
-  if (threadIdx.x == nth - 1) offs[n] = part[nth - 1];
+  if (threadIdx.x == nth - 1) offs[n] = total;
   __syncthreads();
 }
 
