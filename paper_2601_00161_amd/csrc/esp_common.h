@@ -270,6 +270,17 @@ __device__ __forceinline__ double wave_sum_to_last(double v) {
   return v;
 }
 
+// Sum of a float over the 64 lanes, left in lane 63 (DPP moves, as above).
+__device__ __forceinline__ float wave_sum_to_last(float v) {
+  v += dpp_float<0xb1>(v);
+  v += dpp_float<0x4e>(v);
+  v += dpp_float<0x141>(v);
+  v += dpp_float<0x140>(v);
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xa, 0xf, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xc, 0xf, false));
+  return v;
+}
+
 // Block-wide sums of NV doubles (fixed order, deterministic).  red: LDS of
 // at least NV * 16 doubles.  Result valid in thread 0.
 template <int NV>

@@ -120,9 +120,8 @@ __global__ void __launch_bounds__(256) k_spread(KArg<R, BATCH> ka) {
   if (static_cast<int>(threadIdx.x) < (NW + 1) * P) win[threadIdx.x] = wv;
   for (int k = threadIdx.x + blockDim.x; k < (NW + 1) * P; k += blockDim.x) win[k] = d.win[k];
   if constexpr (FIX) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) qs += __shfl_xor(qs, off);
-    if ((threadIdx.x & 63) == 0) qabs[threadIdx.x >> 6] = qs;
+    qs = wave_sum_to_last(qs);
+    if ((threadIdx.x & 63) == 63) qabs[threadIdx.x >> 6] = qs;
   }
   __syncthreads();
   R scale = R(1);
