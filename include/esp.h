@@ -124,7 +124,8 @@ typedef struct {
                           <= 2^59 (FP32) or < 2^62 (FP64), each term rounded once to
                           2^-e, exact integer sums (FP32 terms: the int32-rounded
                           factors q wx 2^eq and wy wz 2^ka multiplied exactly).
-                          Single plans only; batched launches use FP64. */
+                          Single plans only; batched launches spread FP32 batches
+                          in fixed point and FP64 batches with FP64 adds. */
 } esp_opts;
 
 enum { ESP_GATHER_AUTO = 0, ESP_GATHER_PARTICLE = 1, ESP_GATHER_TILE = 2 };

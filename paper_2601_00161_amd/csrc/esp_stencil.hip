@@ -655,10 +655,14 @@ static hipError_t gather_nw(const DevPlan<R>& d, R* f, double* out7, hipStream_t
 
 template <typename R, int P, int NW>
 static hipError_t spread_nw_batch(const BatchLaunch<R>& b, hipStream_t s) {
+  // FP32 batches spread in fixed point (integer-product terms), FP64 batches
+  // with FP64 adds: the automatic choice of single plans for tiles of the
+  // replica sizes (2,000 to 60,000 particles)
+  constexpr bool FIX = sizeof(R) == 4;
   if (b.lds > 65536)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spread<R, P, NW, true, false>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spread<R, P, NW, true, FIX>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(b.lds));
-  hipLaunchKernelGGL((k_spread<R, P, NW, true, false>), dim3(b.nblk), dim3(256), b.lds, s,
+  hipLaunchKernelGGL((k_spread<R, P, NW, true, FIX>), dim3(b.nblk), dim3(256), b.lds, s,
                      KArg<R, true>{b.plans, b.boff, b.nrep});
   return hipGetLastError();
 }
