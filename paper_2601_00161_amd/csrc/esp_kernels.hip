@@ -181,15 +181,20 @@ __global__ void __launch_bounds__(1024) k_scan_sub(KArg<R, BATCH> ka) {
     d.counts[t] = run;
     sum += run;
   }
-  part[tid] = sum;
+  // pass 2: scan of the per-thread sums (DPP within each wave, wave totals
+  // through LDS), then offsets and bases of the own tiles
+  const int incl = wave_inclusive_scan(sum);
+  const int lane = tid & 63, wid = tid >> 6;
+  if (lane == 63) part[wid] = incl;
   __syncthreads();
-  for (int off = 1; off < nth; off <<= 1) {
-    const int add = tid >= off ? part[tid - off] : 0;
-    __syncthreads();
-    part[tid] += add;
-    __syncthreads();
+  int wpre = 0, total = 0;
+#pragma unroll
+  for (int w = 0; w < 16; ++w) {
+    const int v = w < (nth >> 6) ? part[w] : 0;
+    wpre += w < wid ? v : 0;
+    total += v;
   }
-  int run = part[tid] - sum;
+  int run = wpre + incl - sum;
   for (int t = t0; t < t1; ++t) {
     const int tot = d.counts[t];
     d.counts[t] = 0;
@@ -197,7 +202,7 @@ __global__ void __launch_bounds__(1024) k_scan_sub(KArg<R, BATCH> ka) {
     for (int c = 0; c < d.nsub; ++c) d.sbase[static_cast<size_t>(c) * nt + t] += run;
     run += tot;
   }
-  if (tid == nth - 1) d.offsets[nt] = part[nth - 1];
+  if (tid == nth - 1) d.offsets[nt] = total;
 }
 
 // Cell sort, pass 2.  With one counter per tile every block scans the tile
