@@ -86,6 +86,19 @@ def test_membrane_1m_semi_fp32():
     plan.close()
 
 
+def test_membrane_1m_semi_fp64():
+    """The same slab in FP64: the split x / y passes (its complex plane does not
+    fit one workgroup's LDS) and the fixed-point LDS tile (1,296 tiles of ~770
+    particles), against the oracle at the FP64 bar."""
+    h, r, q = synth.config4()
+    r_, q_, r64, q64 = as_inputs(r, q, "fp64")
+    plan = esp.Plan(h, len(q), 1e-5, precision="fp64", coupling="semi", window_tol=1e-13)
+    assert plan.params["fft_split"] == 1 and plan.params["spread_fixed"] == 1
+    f, out = gpu(plan, r_, q_)
+    compare(h, r64, q64, plan, f, out, "fp64")
+    plan.close()
+
+
 def test_batch_64_replicas():
     """The 64-replica batch (N in [2,000, 60,000], tol in {1e-3 ... 1e-6}) in one
     graph-replayed call per step: replicas against their own single plans, and
