@@ -156,53 +156,54 @@ __global__ void __launch_bounds__(256) k_bin(KArg<R, BATCH> ka, const R* __restr
 // Tile offsets for nsub > 1 counter copies (large systems, where one counter
 // per tile would see hundreds of same-address atomics): one workgroup turns
 // the copies into per-copy bases within each tile and the tile offsets, and
-// clears the counters for the next call.
+// clears the counters for the next call.  Tiles go in rounds of one per
+// thread: the nsub counts of a tile are loaded together, the tile totals are
+// scanned (DPP within waves, wave totals through LDS, a carry across rounds),
+// and the bases are written in one pass.
 template <typename R, bool BATCH>
 __global__ void __launch_bounds__(1024) k_scan_sub(KArg<R, BATCH> ka) {
-  __shared__ int part[1024];
+  __shared__ int part[16];
   int blk;
   const DevPlan<R>& d = plan_of(ka, blk);
   if (d.nsub <= 1) return;
-  const int nt = d.ntiles, nth = blockDim.x, tid = threadIdx.x;
-  const int chunk = (nt + nth - 1) / nth;
-  const int t0 = min(nt, tid * chunk), t1 = min(nt, t0 + chunk);
-  // pass 1 (own tiles only): bases within each tile; the tile total is kept
-  // in the first copy's counter until pass 2
-  int sum = 0;
-  for (int t = t0; t < t1; ++t) {
-    int run = 0;
-    for (int c = 0; c < d.nsub; ++c) {
-      const size_t k = static_cast<size_t>(c) * nt + t;
-      const int v = d.counts[k];
-      d.sbase[k] = run;
-      d.counts[k] = 0;
-      run += v;
-    }
-    d.counts[t] = run;
-    sum += run;
-  }
-  // pass 2: scan of the per-thread sums (DPP within each wave, wave totals
-  // through LDS), then offsets and bases of the own tiles
-  const int incl = wave_inclusive_scan(sum);
-  const int lane = tid & 63, wid = tid >> 6;
-  if (lane == 63) part[wid] = incl;
-  __syncthreads();
-  int wpre = 0, total = 0;
+  const int nt = d.ntiles, nsub = d.nsub, nth = blockDim.x, tid = threadIdx.x;
+  const int lane = tid & 63, wid = tid >> 6, nw = nth >> 6;
+  int carry = 0;
+  for (int r0 = 0; r0 < nt; r0 += nth) {
+    const int t = r0 + tid;
+    int v[kMaxCounterCopies];
+    int tot = 0;
 #pragma unroll
-  for (int w = 0; w < 16; ++w) {
-    const int v = w < (nth >> 6) ? part[w] : 0;
-    wpre += w < wid ? v : 0;
-    total += v;
+    for (int c = 0; c < kMaxCounterCopies; ++c)
+      v[c] = (t < nt && c < nsub) ? d.counts[static_cast<size_t>(c) * nt + t] : 0;
+#pragma unroll
+    for (int c = 0; c < kMaxCounterCopies; ++c) tot += v[c];
+    const int incl = wave_inclusive_scan(tot);
+    if (lane == 63) part[wid] = incl;
+    __syncthreads();
+    int wpre = 0, rtot = 0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) {
+      const int x = w < nw ? part[w] : 0;
+      wpre += w < wid ? x : 0;
+      rtot += x;
+    }
+    if (t < nt) {
+      int run = carry + wpre + incl - tot;
+      d.offsets[t] = run;
+#pragma unroll
+      for (int c = 0; c < kMaxCounterCopies; ++c)
+        if (c < nsub) {
+          const size_t k = static_cast<size_t>(c) * nt + t;
+          d.sbase[k] = run;
+          d.counts[k] = 0;
+          run += v[c];
+        }
+    }
+    carry += rtot;
+    __syncthreads();                          // part is reused by the next round
   }
-  int run = wpre + incl - sum;
-  for (int t = t0; t < t1; ++t) {
-    const int tot = d.counts[t];
-    d.counts[t] = 0;
-    d.offsets[t] = run;
-    for (int c = 0; c < d.nsub; ++c) d.sbase[static_cast<size_t>(c) * nt + t] += run;
-    run += tot;
-  }
-  if (tid == nth - 1) d.offsets[nt] = total;
+  if (tid == 0) d.offsets[nt] = carry;
 }
 
 // Cell sort, pass 2.  With one counter per tile every block scans the tile
