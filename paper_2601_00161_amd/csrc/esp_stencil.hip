@@ -61,19 +61,19 @@ __device__ __forceinline__ void window_d_lanes(const R* __restrict__ win, R t1, 
 // cells (ds_add_f32 is several times slower on gfx950 than the 8-byte LDS
 // adds):
 //  * FIX = false: FP64 (ds_add_f64) of products formed in R.
-//  * FIX = true: 64-bit fixed point (ds_add_u64, faster than ds_add_f64 on
-//    crowded tiles).  The scale 2^e is the tile's own: with
-//    b = wmax^3 sum |q_j| over its particles no cell can exceed b in
-//    magnitude, and 2^e b <= 2^59 (FP32) or < 2^62 (FP64) keeps the int64
+//  * FIX = true: 64-bit fixed point (ds_add_u64).  The scale 2^e is the
+//    tile's own: with b = wmax^3 sum |q_j| over its particles no cell can
+//    exceed b in magnitude, and 2^e b <= 2^59 (FP32) or < 2^62 (FP64) keeps the int64
 //    sums in range.  The integer sums are exact, so a cell does not depend
 //    on the order of the atomics.  FP64 plans round each product q wx wy wz
 //    2^e to an integer.  FP32 plans form each term as an exact integer
 //    product: B_a = q wx_a 2^eq and A = wy wz 2^ka are rounded to int32
 //    (|B|, |A| < 2^31; the float products before the rounding are the same
 //    two roundings as the float path's), and A B 2^-s, s = eq + ka - e >= 1,
-//    is taken with one rounding shift: two VALU instructions per term.
-//    The pass over the tile's charges that gives b costs more than the faster
-//    atomics save when a tile holds few particles.
+//    is taken with one rounding shift: two VALU instructions per term, and
+//    faster than the FP64 tile on every tile shape measured.  For FP64 plans
+//    the pass over the tile's charges and the longer f64 -> i64 rounding pay
+//    only on crowded tiles.
 template <typename R>
 __device__ __forceinline__ long long to_fixed(R y) {
   return static_cast<long long>(rint(y));
