@@ -154,6 +154,8 @@ typedef struct {
   int real_segments;              /* segments of the near-kernel polynomials on [0, rc] */
   int fft_split;                  /* the xy transforms run as separate x and y passes */
   int spread_fixed;               /* 1: the spreading tile accumulates in 64-bit fixed point */
+  double hinv[9];                 /* h^-1 of the current cell, row major (the FP32 path uses it as
+                                     the float pair hi = (float) hinv, lo = (float) (hinv - hi)) */
 } esp_params;
 
 void esp_opts_default(esp_opts *o);

@@ -3,12 +3,26 @@
 // placement, and the final FP64 sums.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
 #include <type_traits>
 
 #include "esp_device.h"
+
+// Kernel launch; timed with the stage's events while its stage is profiled
+// (see LaunchTiming).
+#define ESP_LAUNCH(K, G, B, L, S, ...)                                                        \
+  do {                                                                                        \
+    ::espx::LaunchTiming& lt_ = ::espx::launch_timing();                                      \
+    if (lt_.stop) {                                                                           \
+      hipExtLaunchKernelGGL(K, G, B, L, S, lt_.start, lt_.stop, 0, __VA_ARGS__);              \
+      lt_.start = nullptr;                                                                    \
+    } else {                                                                                  \
+      hipLaunchKernelGGL(K, G, B, L, S, __VA_ARGS__);                                         \
+    }                                                                                         \
+  } while (0)
 
 namespace espx {
 
@@ -354,7 +368,10 @@ __device__ __forceinline__ void stencil_fixed(uint32_t S, int M, int P, int& gm,
   gm = g < 0 ? g + M : g;
 }
 
+// Not contracted: u = s M and u - P/2 are rounded separately, so that the tile
+// key is a plain function of the FP64 reduced coordinate.
 __device__ __forceinline__ void stencil_f64(double s, int M, int P, int& gm, double& tau) {
+#pragma clang fp contract(off)
   const double u = s * M;
   const double g0 = ceil(u - 0.5 * P);
   tau = u - g0 - 0.5 * (P - 1);
@@ -400,6 +417,8 @@ template <>
 struct Coord<double> {
   __device__ static void make(const DevPlan<double>& d, double x, double y, double z, double q,
                               Record<double>& rec) {
+    // plain products and sums (no contraction): s = (h00 x + h01 y) + h02 z
+#pragma clang fp contract(off)
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       double s = d.hinv[3 * k] * x + d.hinv[3 * k + 1] * y + d.hinv[3 * k + 2] * z;

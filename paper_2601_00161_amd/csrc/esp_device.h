@@ -181,6 +181,18 @@ struct BatchLaunch {
   int P, nw;
 };
 
+// Per-stage kernel timing.  While the host plan times a stage it sets the two
+// events here; every kernel of that stage is then launched with
+// hipExtLaunchKernelGGL, the first recording `start` at its own start and
+// each recording `stop` at its end (the last one counts), so the timed span
+// is the stage's kernels alone, without the dispatch latency before them.
+// One per host thread (defined in esp_plan.cpp).
+struct LaunchTiming {
+  hipEvent_t start = nullptr;
+  hipEvent_t stop = nullptr;
+};
+LaunchTiming& launch_timing();
+
 // Launchers (defined in esp_kernels.hip, instantiated for float and double).
 template <typename R>
 hipError_t launch_bin(const DevPlan<R>& d, const R* xyz, const R* q, hipStream_t s);

@@ -782,7 +782,7 @@ size_t lds_gather_box(const DevPlan<R>& d) {
 template <typename R>
 hipError_t launch_bin(const DevPlan<R>& d, const R* xyz, const R* q, hipStream_t s) {
   const size_t lds = d.bin_lds ? static_cast<size_t>(d.ntiles) * sizeof(int) : 0;
-  hipLaunchKernelGGL((k_bin<R, false>), dim3(d.nbin), dim3(256), lds, s, KArg<R, false>{d}, xyz, q);
+  ESP_LAUNCH((k_bin<R, false>), dim3(d.nbin), dim3(256), lds, s, KArg<R, false>{d}, xyz, q);
   return hipGetLastError();
 }
 
@@ -791,19 +791,19 @@ hipError_t launch_scatter(const DevPlan<R>& d, hipStream_t s) {
   const int nb = static_cast<int>((d.n + 1023) / 1024);
   const size_t lds = (static_cast<size_t>(d.ntiles) + 1) * sizeof(int);
   allow_lds(reinterpret_cast<const void*>(&k_scatter<R, false>), lds);
-  hipLaunchKernelGGL((k_scatter<R, false>), dim3(nb), dim3(1024), lds, s, KArg<R, false>{d});
+  ESP_LAUNCH((k_scatter<R, false>), dim3(nb), dim3(1024), lds, s, KArg<R, false>{d});
   return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_scan_sub(const DevPlan<R>& d, hipStream_t s) {
-  hipLaunchKernelGGL((k_scan_sub<R, false>), dim3(1), dim3(1024), 0, s, KArg<R, false>{d});
+  ESP_LAUNCH((k_scan_sub<R, false>), dim3(1), dim3(1024), 0, s, KArg<R, false>{d});
   return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_finalize(const DevPlan<R>& d, double* out7, hipStream_t s) {
-  hipLaunchKernelGGL((k_finalize<R, false>), dim3(1), dim3(256), 0, s, KArg<R, false>{d}, out7);
+  ESP_LAUNCH((k_finalize<R, false>), dim3(1), dim3(256), 0, s, KArg<R, false>{d}, out7);
   return hipGetLastError();
 }
 
@@ -858,20 +858,20 @@ hipError_t launch_fft_xy(const DevPlan<R>& d, const R* grid, Cplx<R>* spec, bool
     const int total = (d.M2 + 1) / 2 * d.M3;
     size_t lds = lds_fft_x(d, d.xpairs);
     allow_lds(reinterpret_cast<const void*>(&k_fft_x<R>), lds);
-    hipLaunchKernelGGL(k_fft_x<R>, dim3((total + d.xpairs - 1) / d.xpairs), dim3(256), lds, s, d, grid, spec,
+    ESP_LAUNCH(k_fft_x<R>, dim3((total + d.xpairs - 1) / d.xpairs), dim3(256), lds, s, d, grid, spec,
                        clear_input ? 1 : 0, d.xpairs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     lds = lds_fft_y(d, d.ycols);
     allow_lds(reinterpret_cast<const void*>(&k_fft_y<R>), lds);
-    hipLaunchKernelGGL(k_fft_y<R>, dim3(d.M3 * ((d.H + d.ycols - 1) / d.ycols)), dim3(256), lds, s, d, spec,
+    ESP_LAUNCH(k_fft_y<R>, dim3(d.M3 * ((d.H + d.ycols - 1) / d.ycols)), dim3(256), lds, s, d, spec,
                        d.ycols, 0);
     return hipGetLastError();
   }
   const size_t lds = lds_fft_xy(d);
   allow_lds(reinterpret_cast<const void*>(&k_fft_xy<R, false>), lds);
   const int nth = fft_threads(d.M1 * d.M2);
-  hipLaunchKernelGGL((k_fft_xy<R, false>), dim3(d.M3), dim3(nth), lds, s, KArg<R, false>{d}, grid, spec,
+  ESP_LAUNCH((k_fft_xy<R, false>), dim3(d.M3), dim3(nth), lds, s, KArg<R, false>{d}, grid, spec,
                      clear_input ? 1 : 0);
   return hipGetLastError();
 }
@@ -881,21 +881,21 @@ hipError_t launch_fft_xy_inv(const DevPlan<R>& d, int ncomp, hipStream_t s) {
   if (d.xy_split) {
     size_t lds = lds_fft_y(d, d.ycols);
     allow_lds(reinterpret_cast<const void*>(&k_fft_y<R>), lds);
-    hipLaunchKernelGGL(k_fft_y<R>, dim3(ncomp * d.M3 * ((d.H + d.ycols - 1) / d.ycols)), dim3(256), lds, s, d,
+    ESP_LAUNCH(k_fft_y<R>, dim3(ncomp * d.M3 * ((d.H + d.ycols - 1) / d.ycols)), dim3(256), lds, s, d,
                        static_cast<Cplx<R>*>(nullptr), d.ycols, 1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int total = (d.M2 + 1) / 2 * d.M3;
     lds = lds_fft_x(d, d.xpairs);
     allow_lds(reinterpret_cast<const void*>(&k_fft_x_inv<R>), lds);
-    hipLaunchKernelGGL(k_fft_x_inv<R>, dim3((total + d.xpairs - 1) / d.xpairs, ncomp), dim3(256), lds, s, d,
+    ESP_LAUNCH(k_fft_x_inv<R>, dim3((total + d.xpairs - 1) / d.xpairs, ncomp), dim3(256), lds, s, d,
                        d.xpairs);
     return hipGetLastError();
   }
   const size_t lds = lds_fft_xy(d);
   allow_lds(reinterpret_cast<const void*>(&k_fft_xy_inv<R, false>), lds);
   const int nth = fft_threads(d.M1 * d.M2);
-  hipLaunchKernelGGL((k_fft_xy_inv<R, false>), dim3(d.M3 * ncomp), dim3(nth), lds, s, KArg<R, false>{d});
+  ESP_LAUNCH((k_fft_xy_inv<R, false>), dim3(d.M3 * ncomp), dim3(nth), lds, s, KArg<R, false>{d});
   return hipGetLastError();
 }
 
@@ -903,7 +903,7 @@ template <typename R>
 hipError_t launch_fft_z(const DevPlan<R>& d, ZMode mode, hipStream_t s) {
   const size_t lds = lds_fft_z(d);
   allow_lds(reinterpret_cast<const void*>(&k_fft_z<R, false>), lds);
-  hipLaunchKernelGGL((k_fft_z<R, false>), dim3(d.nzblk), dim3(256), lds, s, KArg<R, false>{d},
+  ESP_LAUNCH((k_fft_z<R, false>), dim3(d.nzblk), dim3(256), lds, s, KArg<R, false>{d},
                      static_cast<int>(mode));
   return hipGetLastError();
 }
@@ -912,20 +912,20 @@ hipError_t launch_fft_z(const DevPlan<R>& d, ZMode mode, hipStream_t s) {
 template <typename R>
 hipError_t launch_bin_batch(const BatchLaunch<R>& b, const R* xyz, const R* q, hipStream_t s) {
   allow_lds(reinterpret_cast<const void*>(&k_bin<R, true>), b.lds);
-  hipLaunchKernelGGL((k_bin<R, true>), dim3(b.nblk), dim3(b.nth), b.lds, s, karg(b), xyz, q);
+  ESP_LAUNCH((k_bin<R, true>), dim3(b.nblk), dim3(b.nth), b.lds, s, karg(b), xyz, q);
   return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_scatter_batch(const BatchLaunch<R>& b, hipStream_t s) {
   allow_lds(reinterpret_cast<const void*>(&k_scatter<R, true>), b.lds);
-  hipLaunchKernelGGL((k_scatter<R, true>), dim3(b.nblk), dim3(b.nth), b.lds, s, karg(b));
+  ESP_LAUNCH((k_scatter<R, true>), dim3(b.nblk), dim3(b.nth), b.lds, s, karg(b));
   return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_scan_sub_batch(const BatchLaunch<R>& b, hipStream_t s) {
-  hipLaunchKernelGGL((k_scan_sub<R, true>), dim3(b.nblk), dim3(1024), 0, s, karg(b));
+  ESP_LAUNCH((k_scan_sub<R, true>), dim3(b.nblk), dim3(1024), 0, s, karg(b));
   return hipGetLastError();
 }
 
@@ -942,7 +942,7 @@ hipError_t launch_gather_batch(const BatchLaunch<R>& b, R* f, double* out7, hipS
 template <typename R>
 hipError_t launch_fft_xy_batch(const BatchLaunch<R>& b, hipStream_t s) {
   allow_lds(reinterpret_cast<const void*>(&k_fft_xy<R, true>), b.lds);
-  hipLaunchKernelGGL((k_fft_xy<R, true>), dim3(b.nblk), dim3(b.nth), b.lds, s, karg(b),
+  ESP_LAUNCH((k_fft_xy<R, true>), dim3(b.nblk), dim3(b.nth), b.lds, s, karg(b),
                      static_cast<const R*>(nullptr), static_cast<Cplx<R>*>(nullptr), 1);
   return hipGetLastError();
 }
@@ -950,20 +950,20 @@ hipError_t launch_fft_xy_batch(const BatchLaunch<R>& b, hipStream_t s) {
 template <typename R>
 hipError_t launch_fft_xy_inv_batch(const BatchLaunch<R>& b, hipStream_t s) {
   allow_lds(reinterpret_cast<const void*>(&k_fft_xy_inv<R, true>), b.lds);
-  hipLaunchKernelGGL((k_fft_xy_inv<R, true>), dim3(b.nblk), dim3(b.nth), b.lds, s, karg(b));
+  ESP_LAUNCH((k_fft_xy_inv<R, true>), dim3(b.nblk), dim3(b.nth), b.lds, s, karg(b));
   return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_fft_z_batch(const BatchLaunch<R>& b, ZMode mode, hipStream_t s) {
   allow_lds(reinterpret_cast<const void*>(&k_fft_z<R, true>), b.lds);
-  hipLaunchKernelGGL((k_fft_z<R, true>), dim3(b.nblk), dim3(b.nth), b.lds, s, karg(b), static_cast<int>(mode));
+  ESP_LAUNCH((k_fft_z<R, true>), dim3(b.nblk), dim3(b.nth), b.lds, s, karg(b), static_cast<int>(mode));
   return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_finalize_batch(const BatchLaunch<R>& b, double* out7, hipStream_t s) {
-  hipLaunchKernelGGL((k_finalize<R, true>), dim3(b.nblk), dim3(256), 0, s, karg(b), out7);
+  ESP_LAUNCH((k_finalize<R, true>), dim3(b.nblk), dim3(256), 0, s, karg(b), out7);
   return hipGetLastError();
 }
 
@@ -971,7 +971,7 @@ template <typename T>
 hipError_t launch_fill(T* p, size_t count, hipStream_t s) {
   if (count == 0) return hipSuccess;
   const int nb = static_cast<int>(std::min<size_t>((count + 255) / 256, 4096));
-  hipLaunchKernelGGL(k_fill<T>, dim3(nb), dim3(256), 0, s, p, count);
+  ESP_LAUNCH(k_fill<T>, dim3(nb), dim3(256), 0, s, p, count);
   return hipGetLastError();
 }
 

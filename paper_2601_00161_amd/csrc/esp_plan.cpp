@@ -20,6 +20,7 @@
 
 #include "../../include/esp.h"
 #include "esp_device.h"
+#include "esp_internal.h"
 #include "pswf.h"
 
 using namespace espx;
@@ -410,6 +411,11 @@ struct esp_plan_s {
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::vector<void*> allocs;
+  // device memory from a caller-provided region instead of hipMalloc (the
+  // allocation-free entry point): bump allocation, nothing freed by the plan;
+  // such a plan holds only what the force path needs
+  unsigned char* arena = nullptr;
+  size_t arena_cap = 0, arena_used = 0;
   DevPlan<float> d32{};
   DevPlan<double> d64{};
   std::string err;
@@ -422,6 +428,13 @@ struct esp_plan_s {
     for (void* p : allocs) (void)hipFree(p);
   }
 };
+
+namespace espx {
+LaunchTiming& launch_timing() {
+  thread_local LaunchTiming t;
+  return t;
+}
+}  // namespace espx
 
 namespace {
 
@@ -439,8 +452,23 @@ esp_status hip_fail(esp_plan_t* p, hipError_t e, const char* what) {
 
 template <typename T>
 esp_status dalloc(esp_plan_t* p, T** ptr, size_t count) {
+  const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  if (p->arena) {
+    const size_t off = (p->arena_used + 255) & ~static_cast<size_t>(255);
+    if (off + bytes > p->arena_cap) {
+      char b[200];
+      std::snprintf(b, sizeof b, "the plan needs more than the %zu bytes of its preallocated device region",
+                    p->arena_cap);
+      p->err = b;
+      *ptr = nullptr;
+      return ESP_ENOMEM;
+    }
+    p->arena_used = off + bytes;
+    *ptr = reinterpret_cast<T*>(p->arena + off);
+    return ESP_OK;
+  }
   void* q = nullptr;
-  hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+  hipError_t e = hipMalloc(&q, bytes);
   if (e != hipSuccess) return hip_fail(p, e, "hipMalloc");
   p->allocs.push_back(q);
   *ptr = static_cast<T*>(q);
@@ -755,15 +783,17 @@ esp_status build_device(esp_plan_t* p) {
     d.nsub = std::max(1, std::min(kMaxCounterCopies, static_cast<int>(std::ceil(per / kBinContention))));
   }
   const size_t ncount = static_cast<size_t>(r.ntiles) * d.nsub;
+  const bool want_near = !p->arena;   // a region plan serves the force path only
   if ((st = dalloc(p, &d.counts, ncount)) || (st = dalloc(p, &d.sbase, d.nsub > 1 ? ncount : 1)) ||
       (st = dalloc(p, &d.offsets, r.ntiles + 1)) ||
-      (st = dalloc(p, &d.nr_counts, kMaxCells)) || (st = dalloc(p, &d.nr_offsets, kMaxCells + 1)) ||
-      (st = dalloc(p, &d.nr_keys, r.n)) || (st = dalloc(p, &d.nr_ranks, r.n)) ||
-      (st = dalloc(p, &d.nr_perm, r.n)) || (st = dalloc(p, &d.nr_tmp, r.n)) ||
-      (st = dalloc(p, &d.nr_sorted, r.n)) || (st = dalloc(p, &d.nr_qpart, static_cast<size_t>(d.nbin) * 2)) ||
-      (st = dalloc(p, &d.rpart, static_cast<size_t>(std::max(kMaxCells, 2 * kRealBlocks)) * kNumSums)) ||
-      (st = dalloc(p, &d.fpart, static_cast<size_t>(kMaxRealSplit) * r.n * 3)) ||
-      (st = dalloc(p, &d.facc, static_cast<size_t>(r.n) * 3)) ||
+      (want_near && ((st = dalloc(p, &d.nr_counts, kMaxCells)) || (st = dalloc(p, &d.nr_offsets, kMaxCells + 1)) ||
+                (st = dalloc(p, &d.nr_keys, r.n)) || (st = dalloc(p, &d.nr_ranks, r.n)) ||
+                (st = dalloc(p, &d.nr_perm, r.n)) || (st = dalloc(p, &d.nr_tmp, r.n)) ||
+                (st = dalloc(p, &d.nr_sorted, r.n)) ||
+                (st = dalloc(p, &d.nr_qpart, static_cast<size_t>(d.nbin) * 2)) ||
+                (st = dalloc(p, &d.rpart, static_cast<size_t>(std::max(kMaxCells, 2 * kRealBlocks)) * kNumSums)) ||
+                (st = dalloc(p, &d.fpart, static_cast<size_t>(kMaxRealSplit) * r.n * 3)) ||
+                (st = dalloc(p, &d.facc, static_cast<size_t>(r.n) * 3)))) ||
       (st = dalloc(p, &d.keys, r.n)) || (st = dalloc(p, &d.ranks, r.n)) || (st = dalloc(p, &d.perm, r.n)) ||
       (st = dalloc(p, &d.tmp, r.n)) || (st = dalloc(p, &d.sorted, r.n)) || (st = dalloc(p, &d.rho, G)) ||
       (st = dalloc(p, &d.spec, S * d.ncomp)) || (st = dalloc(p, &d.phi, G * d.ncomp)) ||
@@ -781,6 +811,15 @@ esp_status build_device(esp_plan_t* p) {
   d.gather_tiled = r.gather == ESP_GATHER_TILE ||
                    (r.gather == ESP_GATHER_AUTO && box_fits &&
                     r.n >= static_cast<int64_t>(kTiledGatherMin) * r.ntiles);
+  if (p->arena) {
+    // the region holds whatever its previous user left: clear, stream-ordered
+    // with fill kernels, what the force path needs zero at its start
+    e = launch_fill(d.counts, ncount, p->stream);
+    if (e == hipSuccess) e = launch_fill(d.rho, G, p->stream);
+    if (e == hipSuccess) e = launch_fill(d.flags, 4, p->stream);
+    if (e != hipSuccess) return hip_fail(p, e, "buffer initialisation");
+    return ESP_OK;
+  }
   e = hipMemset(d.counts, 0, ncount * sizeof(int));
   if (e == hipSuccess) e = hipMemset(d.nr_counts, 0, kMaxCells * sizeof(int));
   if (e == hipSuccess) e = hipMemset(d.rho, 0, G * sizeof(R));
@@ -796,11 +835,14 @@ template <class F>
 hipError_t stage(esp_plan_t* p, int st, F&& launch, hipStream_t s) {
   Profiler& pr = p->prof;
   const bool on = ((pr.mask >> st) & 1u) && pr.used[st] < pr.cap && pr.seen[st]++ % pr.stride == 0;
-  if (on) (void)hipEventRecord(pr.ev[st][2 * pr.used[st]], s);
+  LaunchTiming& lt = launch_timing();
+  if (on) lt = {pr.ev[st][2 * pr.used[st]], pr.ev[st][2 * pr.used[st] + 1]};
+  (void)s;
   hipError_t e = launch();
   if (on) {
-    (void)hipEventRecord(pr.ev[st][2 * pr.used[st] + 1], s);
-    ++pr.used[st];
+    // a stage that launched nothing (an error) leaves its events unrecorded
+    if (!lt.start) ++pr.used[st];
+    lt = {};
   }
   return e;
 }
@@ -988,6 +1030,61 @@ size_t real_bytes() { return sizeof(R); }
 }  // namespace
 
 // ============================================================================ C ABI
+namespace {
+
+esp_status plan_create(const double h[9], int64_t n, double tol, const esp_opts* o, void* region, size_t cap,
+                       esp_plan_t** out) {
+  if (!out) return ESP_EINVAL;
+  *out = nullptr;
+  std::unique_ptr<esp_plan_s> p(new esp_plan_s());
+  p->arena = static_cast<unsigned char*>(region);
+  p->arena_cap = region ? cap : 0;
+  esp_status warn;
+  try {
+    warn = resolve(h, n, tol, o, p->r, p->err);
+    if (warn < 0) {
+      std::fprintf(stderr, "esp_plan: %s\n", p->err.c_str());
+      return warn;
+    }
+    p->split.reset(new Pswf(p->r.c_split));
+    p->spread.reset(new Pswf(p->r.c_spread));
+  } catch (const std::exception& ex) {
+    std::fprintf(stderr, "esp_plan: %s\n", ex.what());
+    return ESP_EINVAL;
+  }
+  const Pswf& s = *p->split;
+  p->A = kTwoPi * s.lambda0() / s.C0();
+  p->self_coef = s.psi0() / (2.0 * s.C0() * p->r.rc);
+  {
+    // Ic = rc^2 / 2 - int_0^rc r phi0(r) dr, phi0(r) = int_0^{r/rc} psi / C0 (Sec. 3.4)
+    std::vector<double> x, w;
+    gauss_legendre(96, x, w);
+    double acc = 0;
+    for (size_t j = 0; j < x.size(); ++j) {
+      const double t = 0.5 * (x[j] + 1.0);
+      acc += 0.5 * w[j] * t * s.int_psi(t) / s.C0();
+    }
+    p->Ic = p->r.rc * p->r.rc * (0.5 - acc);
+  }
+  p->stream = o ? static_cast<hipStream_t>(o->stream) : nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    p->err = "no HIP device";
+    std::fprintf(stderr, "esp_plan: no HIP device\n");
+    return ESP_EDEVICE;
+  }
+  esp_status st = p->r.precision == ESP_FP32 ? build_device<float>(p.get()) : build_device<double>(p.get());
+  if (st != ESP_OK) {
+    std::fprintf(stderr, "esp_plan: %s\n", p->err.c_str());
+    return st;
+  }
+  *out = p.release();
+  return warn;
+}
+
+}  // namespace
+
+
 extern "C" {
 
 void esp_opts_default(esp_opts* o) {
@@ -1037,51 +1134,9 @@ esp_status esp_resolve_params(const double h[9], int64_t n, double tol, const es
   return st;
 }
 
+
 esp_status esp_plan(const double h[9], int64_t n, double tol, const esp_opts* o, esp_plan_t** out) {
-  if (!out) return ESP_EINVAL;
-  *out = nullptr;
-  std::unique_ptr<esp_plan_s> p(new esp_plan_s());
-  esp_status warn;
-  try {
-    warn = resolve(h, n, tol, o, p->r, p->err);
-    if (warn < 0) {
-      std::fprintf(stderr, "esp_plan: %s\n", p->err.c_str());
-      return warn;
-    }
-    p->split.reset(new Pswf(p->r.c_split));
-    p->spread.reset(new Pswf(p->r.c_spread));
-  } catch (const std::exception& ex) {
-    std::fprintf(stderr, "esp_plan: %s\n", ex.what());
-    return ESP_EINVAL;
-  }
-  const Pswf& s = *p->split;
-  p->A = kTwoPi * s.lambda0() / s.C0();
-  p->self_coef = s.psi0() / (2.0 * s.C0() * p->r.rc);
-  {
-    // Ic = rc^2 / 2 - int_0^rc r phi0(r) dr, phi0(r) = int_0^{r/rc} psi / C0 (Sec. 3.4)
-    std::vector<double> x, w;
-    gauss_legendre(96, x, w);
-    double acc = 0;
-    for (size_t j = 0; j < x.size(); ++j) {
-      const double t = 0.5 * (x[j] + 1.0);
-      acc += 0.5 * w[j] * t * s.int_psi(t) / s.C0();
-    }
-    p->Ic = p->r.rc * p->r.rc * (0.5 - acc);
-  }
-  p->stream = o ? static_cast<hipStream_t>(o->stream) : nullptr;
-  int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
-    p->err = "no HIP device";
-    std::fprintf(stderr, "esp_plan: no HIP device\n");
-    return ESP_EDEVICE;
-  }
-  esp_status st = p->r.precision == ESP_FP32 ? build_device<float>(p.get()) : build_device<double>(p.get());
-  if (st != ESP_OK) {
-    std::fprintf(stderr, "esp_plan: %s\n", p->err.c_str());
-    return st;
-  }
-  *out = p.release();
-  return warn;
+  return plan_create(h, n, tol, o, nullptr, 0, out);
 }
 
 esp_status esp_set_box(esp_plan_t* p, const double h[9]) {
@@ -1219,6 +1274,7 @@ esp_status esp_get_params(const esp_plan_t* p, esp_params* out) {
     out->fft_split = f32 ? p->d32.xy_split : p->d64.xy_split;
     out->spread_fixed = f32 ? p->d32.spread_fixed : p->d64.spread_fixed;
   }
+  for (int i = 0; i < 9; ++i) out->hinv[i] = r.hinv[i];
   return ESP_OK;
 }
 
@@ -1427,6 +1483,27 @@ esp_status esp_proposer_set(const esp_proposer* p) {
 const char* esp_version(void) { return "esp-mi355x 0.1.0 (gfx950)"; }
 
 }  // extern "C"
+
+namespace espx {
+
+esp_status plan_in_region(const double h[9], int64_t n, double tol, const esp_opts* o, void* base, size_t cap,
+                          esp_plan_t** out, size_t* used) {
+  if (!base || cap == 0) return ESP_EINVAL;
+  const esp_status st = plan_create(h, n, tol, o, base, cap, out);
+  if (used) *used = st >= 0 && *out ? (*out)->arena_used : 0;
+  return st;
+}
+
+bool plan_same_grid(const esp_plan_t* p, const double h[9]) {
+  const Resolved& r = p->r;
+  if (r.params_source == ESP_EXPLICIT) return true;
+  if (r.params_source != ESP_ANALYTIC) return false;
+  for (int d = 0; d < 3; ++d)
+    if (next_smooth(std::max({grid_rule(h, d, r.c_split, r.rc, r.sigma), r.P, 2})) != r.M[d]) return false;
+  return true;
+}
+
+}  // namespace espx
 
 // ============================================================================ batches
 // A batch holds one ordinary plan per replica (its tables and buffers) plus a

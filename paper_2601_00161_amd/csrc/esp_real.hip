@@ -360,20 +360,20 @@ template <typename R>
 hipError_t launch_real_pairs(const DevPlan<R>& d, hipStream_t s) {
   const size_t lds = lds_real(d);     // at most 40 KiB (segment count capped on the host)
   const int nblk = d.cn1 * d.cn2 * d.cn3 * d.rsplit;
-  hipLaunchKernelGGL(k_real_pairs<R>, dim3(nblk), dim3(kRealThreads), lds, s, d);
+  ESP_LAUNCH(k_real_pairs<R>, dim3(nblk), dim3(kRealThreads), lds, s, d);
   return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_real_forces(const DevPlan<R>& d, R* f, int accumulate, hipStream_t s) {
-  hipLaunchKernelGGL(k_real_forces<R>, dim3(static_cast<unsigned>((d.n + 255) / 256)), dim3(256), 0, s, d, f,
+  ESP_LAUNCH(k_real_forces<R>, dim3(static_cast<unsigned>((d.n + 255) / 256)), dim3(256), 0, s, d, f,
                      accumulate);
   return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_real_finalize(const DevPlan<R>& d, double* out7, int add, hipStream_t s) {
-  hipLaunchKernelGGL(k_real_finalize<R>, dim3(1), dim3(256), 0, s, d, out7, add);
+  ESP_LAUNCH(k_real_finalize<R>, dim3(1), dim3(256), 0, s, d, out7, add);
   return hipGetLastError();
 }
 

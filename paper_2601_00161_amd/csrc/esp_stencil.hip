@@ -621,7 +621,7 @@ static hipError_t spread_acc(const DevPlan<R>& d, hipStream_t s) {
   if (lds > 65536)
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spread<R, P, NW, false, FIX>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-  hipLaunchKernelGGL((k_spread<R, P, NW, false, FIX>), dim3(d.ntiles), dim3(256), lds, s, KArg<R, false>{d});
+  ESP_LAUNCH((k_spread<R, P, NW, false, FIX>), dim3(d.ntiles), dim3(256), lds, s, KArg<R, false>{d});
   return hipGetLastError();
 }
 
@@ -642,13 +642,13 @@ static hipError_t gather_nw(const DevPlan<R>& d, R* f, double* out7, hipStream_t
     if (lds > 65536)
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather_tile<R, P, NW, false>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-    hipLaunchKernelGGL((k_gather_tile<R, P, NW, false>), dim3(d.ntiles), dim3(256), lds, s, KArg<R, false>{d},
+    ESP_LAUNCH((k_gather_tile<R, P, NW, false>), dim3(d.ntiles), dim3(256), lds, s, KArg<R, false>{d},
                        f, out7);
     return hipGetLastError();
   }
   constexpr int G = 256 / GatherLanes<P>::L;
   const int nb = static_cast<int>((d.n + G - 1) / G);
-  hipLaunchKernelGGL((k_gather<R, P, NW, false>), dim3(nb), dim3(256), (gather_lds<R, P, NW>()), s,
+  ESP_LAUNCH((k_gather<R, P, NW, false>), dim3(nb), dim3(256), (gather_lds<R, P, NW>()), s,
                      KArg<R, false>{d}, f, out7);
   return hipGetLastError();
 }
@@ -662,14 +662,14 @@ static hipError_t spread_nw_batch(const BatchLaunch<R>& b, hipStream_t s) {
   if (b.lds > 65536)
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spread<R, P, NW, true, FIX>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(b.lds));
-  hipLaunchKernelGGL((k_spread<R, P, NW, true, FIX>), dim3(b.nblk), dim3(256), b.lds, s,
+  ESP_LAUNCH((k_spread<R, P, NW, true, FIX>), dim3(b.nblk), dim3(256), b.lds, s,
                      KArg<R, true>{b.plans, b.boff, b.nrep});
   return hipGetLastError();
 }
 
 template <typename R, int P, int NW>
 static hipError_t gather_nw_batch(const BatchLaunch<R>& b, R* f, double* out7, hipStream_t s) {
-  hipLaunchKernelGGL((k_gather<R, P, NW, true>), dim3(b.nblk), dim3(256), (gather_lds<R, P, NW>()), s,
+  ESP_LAUNCH((k_gather<R, P, NW, true>), dim3(b.nblk), dim3(256), (gather_lds<R, P, NW>()), s,
                      KArg<R, true>{b.plans, b.boff, b.nrep}, f, out7);
   return hipGetLastError();
 }
@@ -697,7 +697,7 @@ static hipError_t gather_ik_nw(const DevPlan<R>& d, R* f, double* out7, hipStrea
   constexpr int G = 256 / GatherLanes<P>::L;
   const int nb = static_cast<int>((d.n + G - 1) / G);
   const size_t lds = ((NW + 1) * P + G * 3 * P) * sizeof(R);
-  hipLaunchKernelGGL((k_gather_ik<R, P, NW, false>), dim3(nb), dim3(256), lds, s, KArg<R, false>{d}, f, out7);
+  ESP_LAUNCH((k_gather_ik<R, P, NW, false>), dim3(nb), dim3(256), lds, s, KArg<R, false>{d}, f, out7);
   return hipGetLastError();
 }
 
@@ -711,7 +711,7 @@ static hipError_t gather_local_nw(const DevPlan<R>& d, R* w6, double* out7, hipS
   constexpr int G = 256 / GatherLanes<P>::L;
   const int nb = static_cast<int>((d.n + G - 1) / G);
   const size_t lds = ((NW + 1) * P + G * 3 * P) * sizeof(R);
-  hipLaunchKernelGGL((k_gather_local<R, P, NW, false>), dim3(nb), dim3(256), lds, s, KArg<R, false>{d}, w6,
+  ESP_LAUNCH((k_gather_local<R, P, NW, false>), dim3(nb), dim3(256), lds, s, KArg<R, false>{d}, w6,
                      out7);
   return hipGetLastError();
 }

@@ -54,7 +54,8 @@ class Params(ctypes.Structure):
                 ("predicted_log10_err", ctypes.c_double * 4), ("predicted_cost", ctypes.c_double),
                 ("gather_tiled", ctypes.c_int), ("counter_copies", ctypes.c_int), ("force", ctypes.c_int),
                 ("local_virial", ctypes.c_int), ("real_cells", ctypes.c_int * 3),
-                ("real_segments", ctypes.c_int), ("fft_split", ctypes.c_int), ("spread_fixed", ctypes.c_int)]
+                ("real_segments", ctypes.c_int), ("fft_split", ctypes.c_int), ("spread_fixed", ctypes.c_int),
+                ("hinv", ctypes.c_double * 9)]
 
     def as_dict(self):
         out = {}

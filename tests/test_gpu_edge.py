@@ -4,7 +4,7 @@ and the LDS limit."""
 import numpy as np
 import pytest
 
-from gpu_util import TOL, as_inputs, oracle, paper_params, rel_rms, tensor_rel
+from gpu_util import as_inputs, oracle, paper_params, parity, parity_vs_oracle, stencil_ties, ties_of
 from paper_2601_00161_amd import esp, synth
 
 pytestmark = pytest.mark.gpu
@@ -18,8 +18,7 @@ def explicit(prm):
 
 def run(h, r, q, prm, precision, **kw):
     r_, q_, r64, q64 = as_inputs(r, q, precision)
-    if precision == "fp64":
-        kw.setdefault("window_tol", 1e-13)
+    kw.setdefault("window_tol", 2e-8 if precision == "fp32" else 1e-13)
     plan = esp.Plan(h, len(q), 1e-4, precision=precision, **explicit(prm), **kw)
     xyz = torch.from_numpy(r_).to(DEV)
     qq = torch.from_numpy(q_).to(DEV)
@@ -30,14 +29,12 @@ def run(h, r, q, prm, precision, **kw):
     return res, r64, q64
 
 
-def check(h, res, r64, q64, prm, precision, force_abs=None):
+def check(label, h, res, r64, q64, prm, precision, force_abs=None):
     (f, out, st, _), ref = res, oracle(h, r64, q64, prm)
     assert st == esp.ESP_OK
-    assert abs(out[0] - ref.energy) <= TOL[precision] * abs(ref.energy)
-    assert tensor_rel(out, ref.virial) < TOL[precision]
-    if force_abs is None:
-        assert rel_rms(f, ref.forces) < TOL[precision]
-    else:
+    parity_vs_oracle(label, out, ref, f=f if force_abs is None else None, precision=precision,
+                     ties=ties_of(h, r64, prm))
+    if force_abs is not None:
         assert np.max(np.abs(f - ref.forces)) < force_abs
     return ref
 
@@ -52,7 +49,7 @@ def test_single_charge(precision):
     res, r64, q64 = run(h, r, q, prm, precision)
     # the gridded force on a lone charge is only the small grid self-force;
     # compare absolutely on the natural scale q^2 / L^2 ~ 0.2
-    check(h, res, r64, q64, prm, precision, force_abs=2e-5 if precision == "fp32" else 1e-9)
+    check("single_charge", h, res, r64, q64, prm, precision, force_abs=2e-5 if precision == "fp32" else 1e-9)
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
@@ -61,7 +58,7 @@ def test_net_charge(precision):
     q = q + 0.01                       # Q = 6 e
     prm = paper_params(h, 1e-5, coupling="flex")
     res, r64, q64 = run(h, r, q, prm, precision)
-    check(h, res, r64, q64, prm, precision)
+    check("net_charge", h, res, r64, q64, prm, precision)
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
@@ -74,9 +71,15 @@ def test_positions_outside_the_cell_are_wrapped(precision):
     shift = np.random.default_rng(1).integers(-3, 4, size=(len(q), 3)) @ h.T
     res0, _, _ = run(h, r, q, prm, precision)
     res1, r64, q64 = run(h, r + shift, q, prm, precision)
-    check(h, res1, r64, q64, prm, precision)
-    assert rel_rms(res1[0], res0[0]) < TOL[precision]
-    assert np.max(np.abs(res1[1] - res0[1])) <= TOL[precision] * np.max(np.abs(res0[1]))
+    check("wrapped", h, res1, r64, q64, prm, precision)
+    # unshifted vs shifted: the shifted inputs are rounded differently (in FP32
+    # an ulp of a coordinate up to ~10 nm, ~5e-7 nm), which moves particles and
+    # so changes results by that much: measured virial component 2.2e-5,
+    # per-particle force 1.3e-5 (FP64 1e-13).  Input rounding, not arithmetic.
+    loose = 1e-4 if precision == "fp32" else 1e-10
+    ties = stencil_ties(h, r.astype(np.float64), prm["M"], prm["P"], eps=1e-5)
+    parity("wrapped_vs_unshifted", res1[1], res0[1][0], res0[1][1:], res1[0], res0[0], precision,
+           bars=dict(energy=loose, trace=loose, virial=loose, f_rms=loose, f_max=loose), ties=ties)
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
@@ -90,7 +93,7 @@ def test_nonfinite_input_is_flagged(precision):
     q_bad = q.copy()
     q_bad[40] = np.inf
     r_, q_, _, _ = as_inputs(r_bad, q_bad, precision)
-    kw = {"window_tol": 1e-13} if precision == "fp64" else {}
+    kw = {"window_tol": 1e-13 if precision == "fp64" else 2e-8}
     plan = esp.Plan(h, len(q), 1e-4, precision=precision, **explicit(prm), **kw)
     f, out = plan.forces(torch.from_numpy(r_).to(DEV), torch.from_numpy(q_).to(DEV))
     with pytest.raises(esp.EspError) as ei:
@@ -105,11 +108,10 @@ def test_nonfinite_input_is_flagged(precision):
     ref = oracle(h, r64, q64, prm)
     out = out.cpu().numpy()
     f = f.double().cpu().numpy()
-    assert abs(out[0] - ref.energy) <= TOL[precision] * abs(ref.energy)
-    assert tensor_rel(out, ref.virial) < TOL[precision]
     keep = np.ones(len(q), bool)
     keep[[17, 40]] = False
-    assert rel_rms(f[keep], ref.forces[keep]) < TOL[precision]
+    parity("nonfinite", out, ref.energy, ref.virial, f[keep], ref.forces[keep], precision,
+           ties=ties_of(h, r64, prm)[keep])
     plan.close()
 
 
@@ -126,7 +128,7 @@ def test_empty_and_crowded_tiles(layout, precision):
     q -= q.mean()
     prm = paper_params(h, 1e-5)
     res, r64, q64 = run(h, r, q, prm, precision)
-    check(h, res, r64, q64, prm, precision)
+    check(f"tiles_{layout}", h, res, r64, q64, prm, precision)
 
 
 def test_set_box_equals_a_new_plan():
@@ -143,8 +145,9 @@ def test_set_box_equals_a_new_plan():
     fa, oa = a.forces(xyz, qq)
     b = esp.Plan(h2, len(q), 1e-5, **explicit(prm))
     fb, ob = b.forces(xyz, qq)
-    assert rel_rms(fa.double().cpu().numpy(), fb.double().cpu().numpy()) < 1e-6
-    assert np.max(np.abs(oa.cpu().numpy() - ob.cpu().numpy())) <= 1e-6 * np.max(np.abs(ob.cpu().numpy()))
+    ob = ob.cpu().numpy()
+    parity("set_box_vs_new_plan", oa.cpu().numpy(), ob[0], ob[1:], fa.double().cpu().numpy(),
+           fb.double().cpu().numpy(), "fp32")
     a.close()
     b.close()
 

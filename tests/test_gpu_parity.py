@@ -7,7 +7,7 @@ FP64) inputs converted exactly to FP64 and the same explicit parameters.
 import numpy as np
 import pytest
 
-from gpu_util import TOL, as_inputs, oracle, paper_params, rel_rms, tensor_rel, w6
+from gpu_util import BARS, as_inputs, oracle, paper_params, parity_vs_oracle, rel_rms, ties_of
 from paper_2601_00161_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -24,8 +24,10 @@ def dev():
 def make_plan(h, n, prm, precision, **kw):
     from paper_2601_00161_amd.esp import Plan
     extra = dict(kw)
-    if precision == "fp64":
-        extra.setdefault("window_tol", 1e-13)
+    # window polynomials fitted far below the parity bars (FP32: the tightest
+    # fit the FP32 path takes; FP64: 1e-13), so that what is compared is the
+    # arithmetic of the path, not the fit tolerance a plan is allowed to use
+    extra.setdefault("window_tol", 2e-8 if precision == "fp32" else 1e-13)
     return Plan(h, n, 1e-4, precision=precision, c_split=prm["c_split"], c_spread=prm["c_spread"],
                 P=prm["P"], M=prm["M"], rc=prm["rc"], **extra)
 
@@ -70,35 +72,90 @@ SYSTEMS = systems()
 IDS = [s[0] for s in SYSTEMS]
 
 
+def _two_sum(a, b):
+    s = a + b
+    bb = s - a
+    return s, (a - (s - bb)) + (b - bb)
+
+
+def host_tile_keys(hinv, r_, M, P, T, precision):
+    """A1 on the host, operation for operation as the library defines it, for a
+    bit-exact comparison of the tile keys.
+    FP32: s_d = (h^-1 r)_d in float-float arithmetic (h^-1 as the float pair
+    hi + lo, products split exactly, error terms summed in float), wrapped to
+    [0, 1) and taken as 32-bit fixed point S = floor(frac(s) 2^32); then
+    U = M S, g0 = ceil(U / 2^32 - P/2) in integer arithmetic, wrapped into
+    [0, M).  FP64: s = (h00 x + h01 y) + h02 z (plain products and sums),
+    s - floor(s), u = s M, g0 = ceil(u - P/2).  Key = tile of g0."""
+    n = r_.shape[0]
+    g = np.empty((n, 3), np.int64)
+    if precision == "fp32":
+        f32 = np.float32
+        hi = hinv.astype(f32)
+        lo = (hinv - hi.astype(np.float64)).astype(f32)
+        x = r_.astype(f32)
+        two32 = f32(4294967296.0)
+        for k in range(3):
+            sh = np.zeros(n, f32)
+            sl = np.zeros(n, f32)
+            for j in range(3):
+                h = hi[3 * k + j]
+                p = h * x[:, j]
+                # the exact product error, as fmaf(h, x, -p) gives it
+                pe = (np.float64(h) * x[:, j].astype(np.float64) - p.astype(np.float64)).astype(f32)
+                sh, e = _two_sum(sh, p)
+                sl = sl + ((e + pe) + lo[3 * k + j] * x[:, j])
+            fh, e2 = _two_sum(sh, -np.floor(sh))
+            sl = sl + e2
+            xh = fh * two32
+            ih = np.floor(xh)
+            t = (xh - ih) + sl * two32
+            S = (ih.astype(np.int64) + np.floor(t).astype(np.int64)) & 0xFFFFFFFF
+            U = S * int(M[k])
+            g0 = (U - (int(P) << 31) + 0xFFFFFFFF) >> 32
+            g[:, k] = np.where(g0 < 0, g0 + M[k], g0)
+    else:
+        x = r_.astype(np.float64)
+        for k in range(3):
+            s = (hinv[3 * k] * x[:, 0] + hinv[3 * k + 1] * x[:, 1]) + hinv[3 * k + 2] * x[:, 2]
+            s = s - np.floor(s)
+            s = np.where(s < 1.0, s, 0.0)
+            g0 = np.ceil(s * float(M[k]) - 0.5 * P).astype(np.int64)
+            g[:, k] = np.where(g0 < 0, g0 + M[k], np.where(g0 >= M[k], g0 - M[k], g0))
+    nt = [(M[d] + T[d] - 1) // T[d] for d in range(3)]
+    return ((g[:, 2] // T[2]) * nt[1] + g[:, 1] // T[1]) * nt[0] + g[:, 0] // T[0]
+
+
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 @pytest.mark.parametrize("case", SYSTEMS, ids=IDS)
-def test_sort_is_a_valid_binning(case, precision, dev):
-    """A1: the permutation is a permutation, tile offsets partition it, and each
-    particle sits in the tile of its stencil base g0 = ceil(u - P/2) (checked on
-    the host from FP64 reduced coordinates; near-tie cases may go either way)."""
+def test_sort_keys_bit_exact(case, precision, dev):
+    """A1: the permutation is a permutation, the tile offsets are exactly the
+    prefix sums of the host's per-tile counts, and every particle sits in the
+    tile the host computes from the same arithmetic (no tolerance, no
+    exemption for stencil ties).  Positions near cell faces and exact grid
+    ties are added to each system."""
     name, h, r, q, prm = case
+    r = np.array(r, np.float64)
+    # particles placed exactly on grid planes (u - P/2 an integer) and on the cell faces
+    M0 = np.array(prm["M"], np.float64)
+    k = min(8, len(q) // 4)
+    s_tie = (np.arange(k)[:, None] % M0[None, :] + (prm["P"] % 2) * 0.5) / M0[None, :]
+    r[:k] = s_tie @ h.T
+    r[k:2 * k] = np.array([0.0, 1.0, -1e-7])[np.arange(k) % 3][:, None] * h[:, np.arange(k) % 3].T
     r_, q_, r64, q64 = as_inputs(r, q, precision)
     plan = make_plan(h, len(q), prm, precision)
     perm, off = plan.stage_sort(to_dev(r_, dev), to_dev(q_, dev))
     perm, off = perm.cpu().numpy(), off.cpu().numpy()
     n = len(q)
     assert np.array_equal(np.sort(perm), np.arange(n))
-    assert off[0] == 0 and off[-1] == n and np.all(np.diff(off) >= 0)
-    T = plan.params["tile"]
-    M = np.array(plan.params["M"])
-    s = np.linalg.solve(h, r64.T).T
-    s -= np.floor(s)
-    u = s * M
-    g0 = np.ceil(u - prm["P"] / 2.0)
-    frac = np.abs((u - prm["P"] / 2.0) - np.round(u - prm["P"] / 2.0))
-    g0 = g0.astype(np.int64) % M
-    nt = [(M[d] + T[d] - 1) // T[d] for d in range(3)]
-    key = ((g0[:, 2] // T[2]) * nt[1] + g0[:, 1] // T[1]) * nt[0] + g0[:, 0] // T[0]
+    key = host_tile_keys(np.array(plan.params["hinv"]), r_, plan.params["M"], prm["P"], plan.params["tile"],
+                         precision)
+    counts = np.bincount(key, minlength=plan.params["ntiles"])
+    assert np.array_equal(off, np.concatenate([[0], np.cumsum(counts)]))
     tile_of_pos = np.searchsorted(off, np.arange(n), side="right") - 1
     got = np.empty(n, dtype=np.int64)
     got[perm] = tile_of_pos
-    ok = (got == key) | np.any(frac < 1e-6, axis=1)
-    assert ok.all(), f"{(~ok).sum()} particles in the wrong tile"
+    assert np.array_equal(got, key), f"{int(np.sum(got != key))} particles in a different tile than the host's"
     plan.close()
 
 
@@ -192,8 +249,7 @@ def test_energy_virial(case, precision, dev):
     plan = make_plan(h, len(q), prm, precision)
     out = plan.energy_virial(to_dev(r_, dev), to_dev(q_, dev)).cpu().numpy()
     ref = oracle(h, r64, q64, prm, forces=False)
-    assert abs(out[0] - ref.energy) / abs(ref.energy) < TOL[precision]
-    assert tensor_rel(out, ref.virial) < TOL[precision]
+    parity_vs_oracle(f"energy_virial/{name}", out, ref, precision=precision)
     plan.close()
 
 
@@ -226,10 +282,10 @@ def test_forces(case, precision, accum, dev):
     out = out.cpu().numpy()
     out_ev = plan.energy_virial(xyz, qq).cpu().numpy()
     ref = oracle(h, r64, q64, prm)
-    assert rel_rms(f, ref.forces) < TOL[precision]
-    assert abs(out[0] - ref.energy) / abs(ref.energy) < TOL[precision]
-    assert tensor_rel(out, ref.virial) < TOL[precision]
-    assert np.max(np.abs(out - out_ev)) <= 1e-6 * np.max(np.abs(out_ev)) + 1e-12
+    parity_vs_oracle(f"forces/{name}/{accum}", out, ref, f=f, precision=precision, ties=ties_of(h, r64, prm))
+    # the force path's energy and virial are those of the single-FFT path, up
+    # to the order in which the spreading adds its tiles into the grid
+    assert np.max(np.abs(out - out_ev)) <= (1e-6 if precision == "fp32" else 1e-12) * np.max(np.abs(out_ev))
     plan.close()
 
 
@@ -249,9 +305,7 @@ def test_forces_ik(case, precision, dev):
     out = out.cpu().numpy()
     ref = esp_grid.esp_grid_ik(h, r64, q64, esp_grid.GridParams(prm["c_split"], prm["c_spread"], prm["P"],
                                                                 tuple(prm["M"]), prm["rc"]))
-    assert rel_rms(f, ref.forces) < TOL[precision]
-    assert abs(out[0] - ref.energy) / abs(ref.energy) < TOL[precision]
-    assert tensor_rel(out, ref.virial) < TOL[precision]
+    parity_vs_oracle(f"forces_ik/{name}", out, ref, f=f, precision=precision, ties=ties_of(h, r64, prm))
     fscale = np.sqrt(np.mean(np.sum(ref.forces ** 2, axis=1)))
     eps = 1e-6 if precision == "fp32" else 1e-12
     assert np.linalg.norm(f.sum(axis=0)) < eps * np.sqrt(len(q)) * fscale
@@ -274,7 +328,14 @@ def test_local_virial(case, precision, dev):
     ref = esp_grid.local_virial(h, r64, q64, esp_grid.GridParams(prm["c_split"], prm["c_spread"], prm["P"],
                                                                  tuple(prm["M"]), prm["rc"]))
     ref6 = np.stack([ref[:, 0, 0], ref[:, 1, 1], ref[:, 2, 2], ref[:, 0, 1], ref[:, 0, 2], ref[:, 1, 2]], axis=1)
-    assert rel_rms(w6, ref6) < TOL[precision]
+    # each of the six components over all particles: relative RMS, and the
+    # largest per-particle difference against the component's RMS
+    keep = ~ties_of(h, r64, prm)
+    for c in range(6):
+        e_rms = rel_rms(w6[keep, c], ref6[keep, c])
+        e_max = np.max(np.abs(w6[keep, c] - ref6[keep, c])) / np.sqrt(np.mean(ref6[keep, c] ** 2))
+        print(f"PARITY local_virial/{name}[{c}] {precision} rms={e_rms:.2e} max={e_max:.2e}", flush=True)
+        assert e_rms < BARS[precision]["f_rms"] and e_max < BARS[precision]["f_max"], (c, e_rms, e_max)
     total = w6.sum(axis=0)
     assert np.max(np.abs(total - out[1:])) <= (1e-6 if precision == "fp32" else 1e-11) * np.max(np.abs(out[1:]))
     plan.close()
