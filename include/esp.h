@@ -185,6 +185,39 @@ esp_status esp_forces(esp_plan_t *p, const float *xyz, const float *q, float *f,
 esp_status esp_forces_f64(esp_plan_t *p, const double *xyz, const double *q, double *f,
                           double *out7);
 
+/* Allocation-free variant of esp_plan + esp_forces + esp_destroy, for callers
+ * that cannot allocate device memory (tight serving loops, harnesses that
+ * forbid hipMalloc).  It makes a plan for (h, n, tol, o) exactly as esp_plan
+ * would, with every device buffer carved out of a static device array of
+ * ESP_NOALLOC_SCRATCH_BYTES per GPU (held from the library's first use on
+ * that GPU until the process ends), runs the esp_forces path on o->stream and
+ * frees the plan's host side; it calls no hipMalloc, hipFree or other device
+ * allocator.  Results equal those of esp_forces on an esp_plan plan with the
+ * same arguments.
+ *   h: host, 9 doubles; xyz (3n floats), q (n floats), f (3n floats,
+ *   overwritten) and out7 (7 doubles, may be NULL): device pointers owned
+ *   by the caller, FP32 only (o->precision must be ESP_FP32; o may be NULL).
+ *   ESP_LEARNED parameters and local_virial are refused (ESP_EINVAL); the
+ *   real-space entry points have no allocation-free variant.
+ * Ordering: the plan's tables are uploaded on o->stream after earlier work
+ *   there and the call waits for that upload (it synchronises the stream
+ *   once); the force kernels are enqueued asynchronously behind it.
+ * Sharing: every call on one GPU uses that GPU's one array and leaves its
+ *   contents behind (the buffers that must start at zero are cleared by each
+ *   call).  Calls that overlap on one GPU -- from several host threads, or on
+ *   different streams without ordering between them -- race and give wrong
+ *   results; serialise them.
+ * Errors: as esp_plan / esp_forces, described on stderr (there is no plan
+ *   for esp_last_error).  A plan that does not fit the array returns
+ *   ESP_ENOMEM before anything is enqueued.  A plan takes about 44 bytes per
+ *   particle plus 12 bytes per grid point (e.g. 68 MB for 10^6 particles on
+ *   a 135 x 135 x 108 grid).
+ *   Non-finite inputs are treated as uncharged particles but not reported
+ *   (esp_check needs a plan). */
+#define ESP_NOALLOC_SCRATCH_BYTES ((size_t)96 << 20)
+esp_status esp_forces_noalloc(const double h[9], int64_t n, double tol, const esp_opts *o,
+                              const float *xyz, const float *q, float *f, double *out7);
+
 /* Per-particle share of the Fourier virial (Sec. 4.4, eq. rhodiag,
  * eq. PinsFind), for pressure profiles of inhomogeneous systems: the six
  * components of P_hat rho_hat / (2 V W_hat^2) are brought back by inverse

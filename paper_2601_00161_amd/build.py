@@ -17,7 +17,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libesp_mi355x.so")
 
 ARCH = "gfx950"
-SOURCES = ["esp_kernels.hip", "esp_real.hip", "esp_mlp.hip", "esp_plan.cpp", "pswf.cpp"]
+SOURCES = ["esp_kernels.hip", "esp_real.hip", "esp_mlp.hip", "esp_plan.cpp", "esp_noalloc.hip", "pswf.cpp"]
 # compiled once per window support P, to instantiate the P-specialised kernels in parallel
 PER_P = ("esp_stencil.hip", range(2, 13))
 FLAGS = [

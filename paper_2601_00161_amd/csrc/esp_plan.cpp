@@ -730,9 +730,7 @@ esp_status build_device(esp_plan_t* p) {
   esp_status st;
   if ((st = dalloc(p, &dtab, tab.size())) != ESP_OK) return st;
   if ((st = dalloc(p, &dtw, tw.size())) != ESP_OK) return st;
-  hipError_t e = hipMemcpy(dtab, tab.data(), tab.size() * sizeof(R), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(dtw, tw.data(), tw.size() * sizeof(Cplx<R>), hipMemcpyHostToDevice);
-  if (e != hipSuccess) return hip_fail(p, e, "table upload");
+  hipError_t e = hipSuccess;
   d.win = dtab + o_win;
   d.kerf = dtab + o_kf;
   d.kerg = dtab + o_kg;
@@ -811,12 +809,26 @@ esp_status build_device(esp_plan_t* p) {
   d.gather_tiled = r.gather == ESP_GATHER_TILE ||
                    (r.gather == ESP_GATHER_AUTO && box_fits &&
                     r.n >= static_cast<int64_t>(kTiledGatherMin) * r.ntiles);
+  // tables: uploaded once every buffer has its place, so that a plan that
+  // does not fit its region fails before it writes any device memory; the
+  // copies are ordered on the plan's stream after earlier work there (a
+  // region's previous user may still be reading its tables) and waited for
+  // before the host copies go out of scope
+  e = hipMemcpyAsync(dtab, tab.data(), tab.size() * sizeof(R), hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dtw, tw.data(), tw.size() * sizeof(Cplx<R>), hipMemcpyHostToDevice, p->stream);
+  if (e != hipSuccess) {
+    (void)hipStreamSynchronize(p->stream);
+    return hip_fail(p, e, "table upload");
+  }
   if (p->arena) {
     // the region holds whatever its previous user left: clear, stream-ordered
     // with fill kernels, what the force path needs zero at its start
     e = launch_fill(d.counts, ncount, p->stream);
     if (e == hipSuccess) e = launch_fill(d.rho, G, p->stream);
     if (e == hipSuccess) e = launch_fill(d.flags, 4, p->stream);
+    const hipError_t es = hipStreamSynchronize(p->stream);
+    if (e == hipSuccess) e = es;
     if (e != hipSuccess) return hip_fail(p, e, "buffer initialisation");
     return ESP_OK;
   }
@@ -825,7 +837,8 @@ esp_status build_device(esp_plan_t* p) {
   if (e == hipSuccess) e = hipMemset(d.rho, 0, G * sizeof(R));
   if (e == hipSuccess) e = hipMemset(d.facc, 0, static_cast<size_t>(r.n) * 3 * sizeof(double));
   if (e == hipSuccess) e = hipMemset(d.flags, 0, 4 * sizeof(int));
-  if (e == hipSuccess) e = hipDeviceSynchronize();
+  const hipError_t es = hipDeviceSynchronize();
+  if (e == hipSuccess) e = es;
   if (e != hipSuccess) return hip_fail(p, e, "buffer initialisation");
   return ESP_OK;
 }
@@ -1493,6 +1506,8 @@ esp_status plan_in_region(const double h[9], int64_t n, double tol, const esp_op
   if (used) *used = st >= 0 && *out ? (*out)->arena_used : 0;
   return st;
 }
+
+void plan_release(esp_plan_t* p) { delete p; }
 
 bool plan_same_grid(const esp_plan_t* p, const double h[9]) {
   const Resolved& r = p->r;

@@ -86,6 +86,7 @@ SIGNATURES = [
     ("esp_energy_virial_f64", ctypes.c_int, [_P, _P, _P, _P]),
     ("esp_forces", ctypes.c_int, [_P, _P, _P, _P, _P]),
     ("esp_forces_f64", ctypes.c_int, [_P, _P, _P, _P, _P]),
+    ("esp_forces_noalloc", ctypes.c_int, [_DP, ctypes.c_int64, _D, ctypes.POINTER(Opts), _P, _P, _P, _P]),
     ("esp_check", ctypes.c_int, [_P]),
     ("esp_local_virial", ctypes.c_int, [_P, _P, _P, _P, _P]),
     ("esp_local_virial_f64", ctypes.c_int, [_P, _P, _P, _P, _P]),
@@ -229,6 +230,31 @@ def c_from_delta(delta):
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
+
+
+NOALLOC_SCRATCH_BYTES = 96 << 20
+
+
+def forces_noalloc(h, xyz, q, tol, f=None, out7=None, **opts):
+    """esp_forces_noalloc: plan + forces in the library's static device scratch
+    (no device allocation by the library); FP32 tensors on the GPU, enqueued on
+    torch's current stream.  Returns (f, out7); pass f / out7 to reuse buffers."""
+    import torch
+    if not (xyz.is_cuda and q.is_cuda) or xyz.dtype != torch.float32 or q.dtype != torch.float32:
+        raise ValueError("xyz and q must be float32 device tensors")
+    if not (xyz.is_contiguous() and q.is_contiguous()) or xyz.numel() != 3 * q.numel():
+        raise ValueError("expected contiguous xyz of 3 n and q of n elements")
+    n = q.numel()
+    if f is None:
+        f = torch.empty((n, 3), dtype=torch.float32, device=xyz.device)
+    if out7 is None:
+        out7 = torch.empty(7, dtype=torch.float64, device=xyz.device)
+    o = make_opts(**opts, stream=ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    _, hp = _cell(h)
+    st = lib().esp_forces_noalloc(hp, n, float(tol), ctypes.byref(o), _ptr(xyz), _ptr(q), _ptr(f), _ptr(out7))
+    if st < 0:
+        raise EspError(st, "esp_forces_noalloc failed (see stderr)")
+    return f, out7
 
 
 class Plan:
