@@ -5,20 +5,32 @@ One step = one esp_forces call (cell sort, spreading, forward FFT, scaling and
 reduction, potential, inverse FFT, gather, finalisation) for all N particles
 of the workload, inputs already resident in device memory.
 
-Workload (default): bulk-water-shaped system, 10,000 rigid 3-site triplets in
+Workload (headline): bulk-water-shaped system, 10,000 rigid 3-site triplets in
 a cubic 6.7 nm cell (N = 30,000), tolerance 1e-5, seeded synthetic input.
-The headline value is the FP32 path with learned parameters (the
-registered proposer; the analytic rule if it declines); the FP32 path with
-the analytic rule and the plain FP64 path (analytic parameters) are timed
-beside it on the same input.  The CPU leg runs the oracle: the baseline
-timing, parity at identical parameters, and the error of every GPU result
-against an exact reference.
+The headline value is the FP32 path with learned parameters (the registered
+proposer; the analytic rule if it declines), timed over exactly --steps
+steps; the FP32 path with the analytic rule and the plain FP64 path (analytic
+parameters) are timed beside it, all three in interleaved windows whose
+median and spread are reported with every comparison.
+
+Other workloads, reported under their own keys: the ionic-liquid-shaped
+triclinic cell (N = 19,200, fully flexible coupling: pressure-only path vs
+force path), the membrane-shaped slab (N = 10^6, semi-isotropic: FP32 learned,
+FP32 analytic and FP64 analytic, with per-kernel HBM and VALU fractions) and
+the 64-replica batch.  Every GPU result is scored against an exact reference
+from the oracle (computed here for the small systems; for the slab, the
+stored reference that tests/golden/make_membrane_reference.py computes with
+the oracle).
+
+The CPU baseline is the oracle's gridded FP64 ESP at the FP64 plan's
+parameters, one instance per host core (up to 16), timed before anything
+touches the GPU.
 
 Prints ONE JSON line.  Its "roofline" object rates the dominant kernel by
-algorithmic bytes per launch (stage_bytes below: e.g. spreading reads 16 B
-per particle record and writes 4 B per grid point) over its live launch
-time, against the 8 TB/s HBM peak, next to the HBM traffic measured by the
-FETCH_SIZE / WRITE_SIZE counter passes recorded under profiles/.
+algorithmic bytes per launch (stage_bytes below) over its launch time from
+HIP events recorded at the kernel's own start and end, against the 8 TB/s
+HBM peak, next to the kernel time and HBM traffic of the rocprofv3 runs
+recorded under profiles/ (while the kernel's sources still match).
 """
 from __future__ import annotations
 
@@ -34,6 +46,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+VALU_PEAK_TFLOPS = {4: 157.3, 8: 78.6}          # FP32 / FP64 vector peak of the MI355X
+MEMBRANE_REF = os.path.join(ROOT, "tests", "golden", "membrane_1m_reference.json")
+
 
 # Algorithmic bytes per launch (per particle / per grid point) of each stage;
 # r = bytes of a real, N particles, G = M1 M2 M3 grid points, S = complex
@@ -52,6 +67,14 @@ def stage_bytes(stage, N, G, S, r):
     }[stage]
 
 
+# Algorithmic flops per particle of the two stencil stages (window support P,
+# window polynomials of degree nw): Horner values (and derivatives) of the 3 P
+# polynomials, the P^3 products, and the P^2 partial products.
+def stage_flops(stage, N, P, nw):
+    return N * {"spread": 6 * P * nw + 2 * P ** 3 + P ** 2,
+                "gather": 12 * P * nw + 4 * P ** 3 + 12 * P ** 2}[stage]
+
+
 def run_plan(plan, xyz, q, steps, warmup, torch):
     f, out7 = plan.forces(xyz, q)
     for _ in range(warmup):
@@ -64,6 +87,39 @@ def run_plan(plan, xyz, q, steps, warmup, torch):
     dt = time.perf_counter() - t0
     plan.check()
     return dt, f, out7
+
+
+def timed(fn, steps, warmup, torch):
+    """Seconds for `steps` calls of fn after `warmup` calls (device synchronised)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def windows(fns, steps, reps, torch):
+    """ms per step of each named function over `reps` interleaved windows of
+    `steps` calls: {name: [ms, ...]}."""
+    out = {k: [] for k in fns}
+    for _ in range(reps):
+        for k, fn in fns.items():
+            out[k].append(timed(fn, steps, 2, torch) / steps * 1e3)
+    return out
+
+
+def spread_stats(ms):
+    a = np.asarray(ms)
+    return {"median": float(np.median(a)), "min": float(a.min()), "max": float(a.max()), "windows": len(a)}
+
+
+def ratio_stats(num, den):
+    """Median and range of the per-window ratios num/den (interleaved windows)."""
+    r = np.asarray(num) / np.asarray(den)
+    return {"median": float(np.median(r)), "min": float(r.min()), "max": float(r.max())}
 
 
 KERNEL_SOURCES = {
@@ -86,37 +142,186 @@ def sources_sha(kernel):
     return hsh.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload_key):
-    """HBM bytes per launch from the committed counter summary, or None when
-    there is none for this kernel and workload or the kernel's sources have
-    changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "traffic_water30k.md")
-    if not os.path.exists(path):
-        return None
+def profile_record(tag, kernel, workload_key, field):
+    """A figure recorded under profiles/ as a line `TAG kernel=.. workload=..
+    sources=.. field=value` (rocprofv3 counter or trace summaries), or None
+    when there is none for this kernel and workload or the kernel's sources
+    have changed since it was measured."""
     want = sources_sha(kernel)
-    for line in open(path):
-        if line.startswith("TRAFFIC "):
-            kv = dict(item.split("=", 1) for item in line.split()[1:])
-            if kv.get("kernel") == kernel and kv.get("workload") == workload_key and kv.get("sources") == want:
-                return float(kv["bytes_per_launch"])
+    pdir = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(pdir):
+        return None
+    for name in sorted(os.listdir(pdir)):
+        if not name.endswith(".md"):
+            continue
+        for line in open(os.path.join(pdir, name)):
+            if line.startswith(tag + " "):
+                kv = dict(item.split("=", 1) for item in line.split()[1:])
+                if (kv.get("kernel") == kernel and kv.get("workload") == workload_key
+                        and kv.get("sources") == want and field in kv):
+                    return float(kv[field])
     return None
 
 
-def oracle_leg(h, r32, q32, plans, headline):
-    """CPU side (the oracle, FP64): baseline timing, parity of each GPU plan at
-    identical parameters, and the headline's error against an exact reference
-    (the oracle's ESP at Delta = 1e-11, P = 12, whose CPU tests pin it to
-    classical Ewald) with the oracle's real-space part added."""
+def kernel_rates(stage_ms, N, G, S, r, P, nw):
+    """HBM and VALU fractions of spread and gather from per-stage times (ms per
+    launch)."""
+    out = {}
+    for k in ("spread", "gather"):
+        if k not in stage_ms:
+            continue
+        t = stage_ms[k] * 1e-3
+        b = stage_bytes(k, N, G, S, r)
+        fl = stage_flops(k, N, P, nw)
+        out[k] = {"us": t * 1e6, "bytes": b, "hbm_gbs": b / t / 1e9, "hbm_frac": b / t / 1e9 / HBM_PEAK_GBS,
+                  "flops": fl, "valu_tflops": fl / t / 1e12, "valu_frac": fl / t / 1e12 / VALU_PEAK_TFLOPS[r]}
+    return out
+
+
+def stage_times(plan, xyz, q, steps, torch):
+    """ms per launch of every stage of the force path (events at each stage's
+    kernels' own start and end)."""
+    plan.profile(["bin", "scatter", "spread", "fft_xy", "fft_z", "fft_xy_inv", "gather"], steps)
+    f, o = plan.forces(xyz, q)
+    for _ in range(steps - 1):
+        plan.forces(xyz, q, f=f, out7=o)
+    st = plan.profile_read()
+    plan.profile([], 0)
+    return {k: v[0] / v[1] for k, v in st.items()}
+
+
+def w6(W):
+    return np.array([W[0, 0], W[1, 1], W[2, 2], W[0, 1], W[0, 2], W[1, 2]])
+
+
+def accuracy(E, W, F, E_ex, W_ex, F_ex):
+    """Errors of a total Coulomb result against the exact one: energy,
+    the paper's diagonal and off-diagonal pressure norms (Sec. 5.1), each
+    virial component against max(|W_c|, 0.05 max|W_aa|), and the relative
+    RMS force."""
+    dg = [W[a, a] - W_ex[a, a] for a in range(3)]
+    od = [W[a, b] - W_ex[a, b] for a, b in ((0, 1), (0, 2), (1, 2))]
+    ref = w6(W_ex)
+    den = np.maximum(np.abs(ref), 0.05 * np.max(np.abs(ref[:3])))
+    return {"energy": float(abs(E - E_ex) / abs(E_ex)),
+            "pressure_diag": float(np.linalg.norm(dg) / np.linalg.norm(np.diag(W_ex))),
+            "pressure_offdiag": float(np.linalg.norm(od) / np.linalg.norm([W_ex[0, 1], W_ex[0, 2], W_ex[1, 2]])),
+            "virial_components": [float(x) for x in np.abs(w6(W) - ref) / den],
+            "forces_rms": float(np.sqrt(np.sum((F - F_ex) ** 2) / np.sum(F_ex ** 2)))}
+
+
+def tensor(o):
+    return np.array([[o[1], o[4], o[5]], [o[4], o[2], o[6]], [o[5], o[6], o[3]]])
+
+
+def exact_reference(h, r64, q64, delta=1e-11, P=12):
+    """Total Coulomb energy, virial and forces from the oracle's ESP at a
+    tight split (the CPU tests pin it to classical Ewald)."""
     from oracle import esp_direct, esp_grid
     from oracle.pswf import c_from_tol
+    c_ref = c_from_tol(delta)
+
+    def smooth(m):
+        k = m
+        for p in (2, 3, 5):
+            while k % p == 0:
+                k //= p
+        return k == 1
+    M = []
+    for d in range(3):
+        m = int(np.ceil(1.07 * np.linalg.norm(h[:, d]) * c_ref / (np.pi * 0.9)))
+        while not smooth(m):
+            m += 1
+        M.append(m)
+    ex = esp_grid.esp_grid(h, r64, q64, esp_grid.GridParams(c_ref, c_ref, P, tuple(M), 0.9))
+    U_N, W_N, F_N = esp_direct.real_space(h, r64, q64, c_ref, 0.9)
+    return ex.energy + U_N, ex.virial + W_N, ex.forces + F_N, f"oracle ESP at Delta={delta:g}, P={P}, M={M}"
+
+
+# --------------------------------------------------------------------------- CPU
+def analytic_params_oracle(h, tol, rc=0.9, sigma=1.07):
+    """The analytic parameter rule (Sec. 5.1: Delta = tol, c from
+    psi(1)/psi(0) = Delta, P = ceil(-log10 Delta) + 1, M_d the next
+    2,3,5-smooth integer >= sigma |h_d| c / (pi rc)) evaluated with the
+    oracle's PSWF, without loading the HIP library."""
+    from oracle.pswf import c_from_tol
+    c = c_from_tol(tol)
+    P = int(np.ceil(-np.log10(tol) - 1e-9)) + 1
+
+    def smooth(m):
+        for p in (2, 3, 5):
+            while m % p == 0:
+                m //= p
+        return m == 1
+    M = []
+    for d in range(3):
+        m = max(int(np.ceil(sigma * np.linalg.norm(h[:, d]) * c / (np.pi * rc) - 1e-9)), P)
+        while not smooth(m):
+            m += 1
+        M.append(m)
+    return {"c_split": c, "c_spread": c, "P": P, "M": M, "rc": rc}
+
+
+def _oracle_steps(job):
+    """One worker of the CPU baseline: full oracle steps on the workload until
+    `seconds` have passed after the common start time."""
+    h, r64, q64, prm, seconds, t_start = job
+    from oracle import esp_grid
+    gp = esp_grid.GridParams(*prm)
+    esp_grid.esp_grid(h, r64, q64, gp)               # warm-up (PSWF tables)
+    late = time.time() > t_start
+    while time.time() < t_start:
+        time.sleep(0.01)
+    n, t0 = 0, time.perf_counter()
+    while n < 1 or time.perf_counter() - t0 < seconds:
+        esp_grid.esp_grid(h, r64, q64, gp)
+        n += 1
+    return n, time.perf_counter() - t0, late
+
+
+def cpu_baseline(h, r32, q32, prm, seconds=12.0):
+    """The oracle's gridded FP64 ESP (numpy, one thread per process), one
+    process per host core up to 16, all timed over the same window."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
     r64, q64 = r32.astype(np.float64), q32.astype(np.float64)
-    N = len(q64)
+    gp = (prm["c_split"], prm["c_spread"], prm["P"], tuple(prm["M"]), prm["rc"])
+    keys = ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")
+    saved = {k: os.environ.get(k) for k in keys}
+    for k in keys:
+        os.environ[k] = "1"                          # inherited by the spawned workers
+    try:
+        t_start = time.time() + 10.0
+        with ProcessPoolExecutor(max_workers=cores, mp_context=mp.get_context("spawn")) as ex:
+            res = list(ex.map(_oracle_steps, [(h, r64, q64, gp, seconds, t_start)] * cores))
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    N = len(q32)
+    rate = sum(n / t for n, t, _ in res) * N / 1e6
+    steps = sum(n for n, _, _ in res)
+    return {"value": rate, "unit": "M particle-steps/s", "cores": cores, "kind": "oracle",
+            "sample": (f"{steps} full steps of the oracle's gridded FP64 ESP (numpy, one thread each) in {cores} "
+                       f"processes over a common {seconds:g} s window, on the same N={N} workload at the FP64 "
+                       f"plan's parameters (P={prm['P']}, M={prm['M']}); host has "
+                       f"{len(os.sched_getaffinity(0))} cores; {sum(1 for *_, late in res if late)} workers "
+                       f"started late")}
+
+
+# --------------------------------------------------------------------------- legs
+def oracle_leg(h, r32, q32, plans):
+    """CPU side (the oracle, FP64) of the headline workload: parity of each GPU
+    plan at identical parameters, and each result's error against an exact
+    reference with the oracle's real-space part added."""
+    from oracle import esp_direct, esp_grid
+    r64, q64 = r32.astype(np.float64), q32.astype(np.float64)
 
     def gp(prm):
         return esp_grid.GridParams(prm["c_split"], prm["c_spread"], prm["P"], tuple(prm["M"]), prm["rc"])
-
-    def w6(W):
-        return np.array([W[0, 0], W[1, 1], W[2, 2], W[0, 1], W[0, 2], W[1, 2]])
 
     out = {"parity_vs_oracle": {}}
     refs = {}
@@ -127,56 +332,149 @@ def oracle_leg(h, r32, q32, plans, headline):
             refs[key] = (esp_grid.esp_grid_ik if prm["force"] == 1 else esp_grid.esp_grid)(h, r64, q64, gp(prm))
         ref = refs[key]
         fo, oo = f.cpu().numpy().astype(np.float64), o.cpu().numpy()
+        Fr = ref.forces
+        frms = np.sqrt(np.mean(np.sum(Fr ** 2, axis=1)))
+        wc = np.abs(oo[1:] - w6(ref.virial)) / np.maximum(np.abs(w6(ref.virial)),
+                                                           0.05 * np.max(np.abs(w6(ref.virial)[:3])))
         out["parity_vs_oracle"][name] = {
             "energy": float(abs(oo[0] - ref.energy) / abs(ref.energy)),
-            "virial": float(np.linalg.norm(oo[1:] - w6(ref.virial)) / np.linalg.norm(w6(ref.virial))),
-            "forces_rms": float(np.sqrt(np.sum((fo - ref.forces) ** 2) / np.sum(ref.forces ** 2)))}
+            "virial_components": [float(x) for x in wc],
+            "forces_rms": float(np.sqrt(np.sum((fo - Fr) ** 2) / np.sum(Fr ** 2))),
+            "forces_max_over_rms": float(np.max(np.linalg.norm(fo - Fr, axis=1)) / frms)}
 
-    # CPU baseline: the oracle's gridded ESP at the FP64 plan's parameters
-    p64 = plans["fp64_analytic"][0].params
-    reps, t0 = 0, time.perf_counter()
-    while reps < 1 or time.perf_counter() - t0 < 10.0:
-        esp_grid.esp_grid(h, r64, q64, gp(p64))
-        reps += 1
-    tc = (time.perf_counter() - t0) / reps
-    out["cpu_baseline"] = {
-        "value": N / tc / 1e6, "unit": "M particle-steps/s", "cores": 1, "kind": "oracle",
-        "sample": f"{reps} full steps of the oracle's gridded FP64 ESP (numpy, single thread) on the same "
-                  f"N={N} workload at the FP64 plan's parameters; host has {len(os.sched_getaffinity(0))} cores"}
-
-    # exact reference of the total Coulomb energy, virial and forces
-    c_ref = c_from_tol(1e-11)
-    M_ref = int(np.ceil(1.07 * max(np.linalg.norm(h, axis=0)) * c_ref / (np.pi * 0.9)))
-    M_ref += M_ref % 2
-    ex_F = esp_grid.esp_grid(h, r64, q64, esp_grid.GridParams(c_ref, c_ref, 12, (M_ref,) * 3, 0.9))
-    U_N, W_N, F_N = esp_direct.real_space(h, r64, q64, c_ref, 0.9)
-    E_ex, W_ex, F_ex = ex_F.energy + U_N, ex_F.virial + W_N, ex_F.forces + F_N
+    E_ex, W_ex, F_ex, what = exact_reference(h, r64, q64)
     acc = {}
     for name, (plan, f, o) in plans.items():
         prm = plan.params
         u_n, w_n, f_n = esp_direct.real_space(h, r64, q64, prm["c_split"], prm["rc"])
         oo = o.cpu().numpy()
-        W = np.array([[oo[1], oo[4], oo[5]], [oo[4], oo[2], oo[6]], [oo[5], oo[6], oo[3]]]) + w_n
-        F = f.cpu().numpy().astype(np.float64) + f_n
-        dg = [(W[a, a] - W_ex[a, a]) for a in range(3)]
-        od = [(W[a, b] - W_ex[a, b]) for a, b in ((0, 1), (0, 2), (1, 2))]
-        acc[name] = {
-            "energy": float(abs(oo[0] + u_n - E_ex) / abs(E_ex)),
-            "pressure_diag": float(np.linalg.norm(dg) / np.linalg.norm(np.diag(W_ex))),
-            "pressure_offdiag": float(np.linalg.norm(od) / np.linalg.norm([W_ex[0, 1], W_ex[0, 2], W_ex[1, 2]])),
-            "forces_rms": float(np.sqrt(np.sum((F - F_ex) ** 2) / np.sum(F_ex ** 2)))}
+        acc[name] = accuracy(oo[0] + u_n, tensor(oo) + w_n, f.cpu().numpy().astype(np.float64) + f_n,
+                             E_ex, W_ex, F_ex)
     out["accuracy_vs_exact"] = acc
-    out["accuracy_reference"] = (f"total Coulomb (real + reciprocal) from the oracle's ESP at Delta=1e-11, P=12, "
-                                 f"M={M_ref}^3; each GPU result gets the oracle's real-space part at its own c")
+    out["accuracy_reference"] = (f"total Coulomb (real + reciprocal) from the {what}; each GPU result gets the "
+                                 f"oracle's real-space part at its own c")
     return out
 
 
-def batch_throughput(torch, dev, steps=20):
-    """The 64-replica batch (N in [2,000, 60,000], per-replica tol in
-    {1e-3 ... 1e-6}, FP32, learned parameters): particle-steps per second of
-    one graph-replayed call per step, next to the same replicas run as 64
-    single-plan calls."""
+def ionic_leg(torch, dev, steps, reps, with_cpu):
+    """Ionic-liquid-shaped triclinic cell (N = 19,200), fully flexible coupling
+    (all six components must meet tol), FP32, tol 1e-5: the pressure-only path
+    (one forward FFT) against the force path, learned and analytic
+    parameters."""
     from paper_2601_00161_amd import synth
+    from paper_2601_00161_amd.esp import PARAMS, Plan
+    h, r, q = synth.config3(0)
+    N = len(q)
+    r32, q32 = r.astype(np.float32), q.astype(np.float32)
+    x, c = torch.from_numpy(r32).to(dev), torch.from_numpy(q32).to(dev)
+    out = {"workload": "ionic-liquid-shaped triclinic cell 9 nm (tilts 1.2, 0.8, 0.5 nm), 1,200 cations + "
+                       "1,200 15-site anions, N=19200, FLEX coupling, tol 1e-5, FP32", "n": N}
+    plans = {}
+    for src in ("learned", "analytic"):
+        p = Plan(h, N, 1e-5, precision="fp32", params=src, coupling="flex")
+        f, o = p.forces(x, c)
+        oe = torch.empty(7, dtype=torch.float64, device=dev)
+        fns = {"forces": lambda p=p, f=f, o=o: p.forces(x, c, f=f, out7=o),
+               "energy_virial": lambda p=p, oe=oe: p.energy_virial(x, c, out7=oe)}
+        ms = windows(fns, steps, reps, torch)
+        torch.cuda.synchronize()
+        p.check()
+        prm = p.params
+        out[src] = {"source": {v: k for k, v in PARAMS.items()}[prm["params_source"]], "delta": prm["delta"],
+                    "c": prm["c_split"], "P": prm["P"], "M": prm["M"],
+                    "forces_ms": spread_stats(ms["forces"]), "energy_virial_ms": spread_stats(ms["energy_virial"]),
+                    "forces_value": N / np.median(ms["forces"]) / 1e3,
+                    "energy_virial_value": N / np.median(ms["energy_virial"]) / 1e3,
+                    "pressure_only_speedup": ratio_stats(ms["forces"], ms["energy_virial"])}
+        plans[src] = (p, f, o)
+    if with_cpu:
+        from oracle import esp_direct
+        r64, q64 = r32.astype(np.float64), q32.astype(np.float64)
+        E_ex, W_ex, F_ex, what = exact_reference(h, r64, q64)
+        for src, (p, f, o) in plans.items():
+            prm = p.params
+            u_n, w_n, f_n = esp_direct.real_space(h, r64, q64, prm["c_split"], prm["rc"])
+            oo = o.cpu().numpy()
+            out[src]["accuracy_vs_exact"] = accuracy(oo[0] + u_n, tensor(oo) + w_n,
+                                                     f.cpu().numpy().astype(np.float64) + f_n, E_ex, W_ex, F_ex)
+        out["accuracy_reference"] = f"total Coulomb from the {what}; oracle real-space part at each plan's c"
+    for p, _, _ in plans.values():
+        p.close()
+    return out
+
+
+def membrane_leg(torch, dev, steps, reps):
+    """Membrane-shaped slab (N = 10^6), semi-isotropic, tol 1e-5: FP32 with
+    learned parameters, FP32 analytic and FP64 analytic; per-kernel rates of
+    spread and gather; accuracy against the stored exact reference."""
+    from paper_2601_00161_amd import synth
+    from paper_2601_00161_amd.esp import PARAMS, Plan
+    h, r, q = synth.config4(0)
+    N = len(q)
+    r32, q32 = r.astype(np.float32), q.astype(np.float32)
+    x32, c32 = torch.from_numpy(r32).to(dev), torch.from_numpy(q32).to(dev)
+    x64, c64 = x32.double(), c32.double()
+    out = {"workload": "membrane-shaped slab 25x25x20 nm, N=1,000,000 (two Gaussian sheets of +-0.5 dipole "
+                       "pairs, water-shaped triplets elsewhere), semi-isotropic, tol 1e-5", "n": N}
+    ref = None
+    if os.path.exists(MEMBRANE_REF):
+        with open(MEMBRANE_REF) as f:
+            ref = json.load(f)
+    specs = {"fp32_learned": ("fp32", "learned", x32, c32), "fp32_analytic": ("fp32", "analytic", x32, c32),
+             "fp64_analytic": ("fp64", "analytic", x64, c64)}
+    plans, fns = {}, {}
+    for name, (prec, src, x, c) in specs.items():
+        p = Plan(h, N, 1e-5, precision=prec, params=src, coupling="semi")
+        f, o = p.forces(x, c)
+        plans[name] = (p, f, o, x, c)
+        fns[name] = lambda p=p, f=f, o=o, x=x, c=c: p.forces(x, c, f=f, out7=o)
+    ms = windows(fns, steps, reps, torch)
+    torch.cuda.synchronize()
+    for name, (p, f, o, x, c) in plans.items():
+        p.check()
+        prm = p.params
+        r_bytes = 4 if prm["precision"] == 0 else 8
+        G = prm["M"][0] * prm["M"][1] * prm["M"][2]
+        S = (prm["M"][0] // 2 + 1) * prm["M"][1] * prm["M"][2]
+        st = stage_times(p, x, c, 10, torch)
+        ent = {"source": {v: k for k, v in PARAMS.items()}[prm["params_source"]], "delta": prm["delta"],
+               "c": prm["c_split"], "P": prm["P"], "M": prm["M"], "tile": prm["tile"],
+               "gather_tiled": prm["gather_tiled"], "ms_per_step": spread_stats(ms[name]),
+               "value": N / np.median(ms[name]) / 1e3, "stage_ms": st,
+               "kernels": kernel_rates(st, N, G, S, r_bytes, prm["P"], prm["window_degree"])}
+        if ref is not None:
+            # the near part at the plan's own split, from an FP64 plan with the
+            # same parameters (its error is at the 1e-12 level)
+            pn = Plan(h, N, 1e-5, precision="fp64", params="explicit", c_split=prm["c_split"],
+                      c_spread=prm["c_spread"], P=prm["P"], M=prm["M"], rc=prm["rc"])
+            fn, on = pn.real_space(x64, c64)
+            torch.cuda.synchronize()
+            pn.check()
+            oo = o.cpu().numpy() + on.cpu().numpy()
+            idx = np.asarray(ref["sample_index"])
+            Ff = (f.double() + fn)[torch.as_tensor(idx, device=dev)].cpu().numpy()
+            pn.close()
+            ent["accuracy_vs_exact"] = accuracy(oo[0], tensor(oo), Ff, ref["energy"], np.asarray(ref["virial"]),
+                                                np.asarray(ref["sample_forces"]))
+            ent["accuracy_vs_exact"]["forces_rms_sample"] = len(idx)
+        out[name] = ent
+    out["fp32_learned_vs_fp64"] = ratio_stats(ms["fp64_analytic"], ms["fp32_learned"])
+    out["fp32_learned_vs_fp32_analytic"] = ratio_stats(ms["fp32_analytic"], ms["fp32_learned"])
+    if ref is not None:
+        out["accuracy_reference"] = (f"{ref['reference']} (stored by tests/golden/make_membrane_reference.py); "
+                                     f"GPU reciprocal part plus the library's FP64 near part at the plan's c; "
+                                     f"forces on {len(ref['sample_index'])} sampled particles")
+    for p, *_ in plans.values():
+        p.close()
+    return out
+
+
+def batch_throughput(torch, dev, steps=20, tune_cache=None):
+    """The 64-replica batch (N in [2,000, 60,000], per-replica tol in
+    {1e-3 ... 1e-6}, FP32, learned parameters, tiles from the autotuner):
+    particle-steps per second of one graph-replayed call per step, next to the
+    same replicas run as 64 single-plan calls."""
+    from paper_2601_00161_amd import autotune, synth
     from paper_2601_00161_amd.esp import Batch, Plan
     reps = synth.replicas()
     cells = [x[0] for x in reps]
@@ -184,16 +482,12 @@ def batch_throughput(torch, dev, steps=20):
     tols = [x[3] for x in reps]
     xyz = torch.tensor(np.concatenate([x[1] for x in reps]), dtype=torch.float32, device=dev)
     q = torch.tensor(np.concatenate([x[2] for x in reps]), dtype=torch.float32, device=dev)
-    b = Batch(cells, ns, tols, graph=True, params="learned")
+    tuned = autotune.tune_batch(cells, ns, tols, xyz, q, cache=tune_cache, params="learned")
+    b = Batch(cells, ns, tols, tiles=tuned["tiles"], graph=True, params="learned")
     f, out = b.forces(xyz, q)
     for _ in range(3):
         b.forces(xyz, q, f=f, out7=out)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        b.forces(xyz, q, f=f, out7=out)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
+    ms = windows({"batch": lambda: b.forces(xyz, q, f=f, out7=out)}, steps, 5, torch)["batch"]
     b.check()
     launches = b.num_launches(True)
     b.close()
@@ -202,18 +496,18 @@ def batch_throughput(torch, dev, steps=20):
     offs = np.concatenate([[0], np.cumsum(ns)])
     views = [(xyz[offs[k]:offs[k + 1]], q[offs[k]:offs[k + 1]]) for k in range(len(ns))]
     outs = [p.forces(*v) for p, v in zip(plans, views)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
+
+    def singles():
         for p, v, (fo, oo) in zip(plans, views, outs):
             p.forces(*v, f=fo, out7=oo)
-    torch.cuda.synchronize()
-    ds = (time.perf_counter() - t0) / steps
+    ds = timed(singles, steps, 2, torch) / steps
     for p in plans:
         p.close()
     total = int(sum(ns))
+    dt = np.median(ms) * 1e-3
     return {"replicas": len(ns), "particles": total, "launches_per_step": launches,
-            "ms_per_step": dt * 1e3, "value": total / dt / 1e6, "unit": "M particle-steps/s",
+            "ms_per_step": spread_stats(ms), "value": total / dt / 1e6, "unit": "M particle-steps/s",
+            "tiles": {"groups": tuned["groups"], "default_ms": tuned["default_ms"], "tuned_ms": tuned["ms"]},
             "single_plans_ms_per_step": ds * 1e3, "speedup_vs_single_plans": ds / dt}
 
 
@@ -224,7 +518,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--tol", type=float, default=1e-5)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--windows", type=int, default=7, help="interleaved timing windows of the comparisons")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
     ap.add_argument("--tile", type=int, default=0, help="spreading tile edge (0 = plan default)")
     ap.add_argument("--params", default="learned", choices=["learned", "analytic"],
                     help="parameter source of the FP32 headline plan")
@@ -233,7 +528,10 @@ def main():
                     help="gather variant when the launch shape is given (--tile or --no-tune)")
     ap.add_argument("--counters-only", action="store_true",
                     help="run only the headline plan (at --tile / --gather) and the near part, for counter passes")
+    ap.add_argument("--workload", default="water30k", choices=["water30k", "membrane1m"],
+                    help="workload of the --counters-only run")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-replica batch measurement")
+    ap.add_argument("--no-extra", action="store_true", help="skip the ionic and membrane workloads")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="first run 5 plain device copies of MIB MiB (float32), the known-size "
                          "kernel that calibrates the FETCH_SIZE / WRITE_SIZE counters")
@@ -243,10 +541,25 @@ def main():
               "over several GPUs is designed but not implemented.", file=sys.stderr)
         sys.exit(2)
 
-    import torch
-
     from paper_2601_00161_amd import synth
     from paper_2601_00161_amd.esp import PARAMS, Plan
+
+    h, r, q = synth.config2(args.seed)
+    N = len(q)
+    r32, q32 = r.astype(np.float32), q.astype(np.float32)
+
+    # ---- CPU baseline first: its worker processes are started before this
+    # process loads the HIP library or touches the GPU, and nothing else runs
+    # beside them.  The parameters are the analytic rule's, computed on the
+    # oracle side (the FP64 plan below must resolve to the same ones) -----------------
+    cpu = None
+    if not args.no_cpu and not args.counters_only:
+        cpu_prm = analytic_params_oracle(h, args.tol)
+        cpu = cpu_baseline(h, r32, q32, cpu_prm)
+        print(f"cpu baseline: {cpu['value']:.4f} M particle-steps/s on {cpu['cores']} cores",
+              file=sys.stderr, flush=True)
+
+    import torch
 
     dev = torch.device("cuda:0")
     if args.copy_calib > 0:
@@ -258,37 +571,42 @@ def main():
         torch.cuda.synchronize()
         print(f"copy calibration: 5 copies of {args.copy_calib} MiB", file=sys.stderr, flush=True)
         del a, b
-    h, r, q = synth.config2(args.seed)
-    N = len(q)
-    r32, q32 = r.astype(np.float32), q.astype(np.float32)
     x32, c32 = torch.from_numpy(r32).to(dev), torch.from_numpy(q32).to(dev)
     x64, c64 = torch.from_numpy(r32.astype(np.float64)).to(dev), torch.from_numpy(q32.astype(np.float64)).to(dev)
 
     if args.counters_only:
         # one plan at a fixed launch shape, so that per-kernel counters are not
         # mixed with the autotuner's trial shapes
-        p = Plan(h, N, args.tol, precision="fp32", params=args.params, tile=args.tile, gather=args.gather)
+        if args.workload == "membrane1m":
+            h, r, q = synth.config4(args.seed)
+            N = len(q)
+            x32 = torch.from_numpy(r.astype(np.float32)).to(dev)
+            c32 = torch.from_numpy(q.astype(np.float32)).to(dev)
+            p = Plan(h, N, args.tol, precision="fp32", params=args.params, coupling="semi", tile=args.tile,
+                     gather=args.gather)
+        else:
+            p = Plan(h, N, args.tol, precision="fp32", params=args.params, tile=args.tile, gather=args.gather)
         f, o = p.forces(x32, c32)
-        fn, on = p.real_space(x32, c32)
         for _ in range(args.warmup + args.steps):
             p.forces(x32, c32, f=f, out7=o)
-            p.real_space(x32, c32, f=fn, out7=on)
         torch.cuda.synchronize()
-        print(json.dumps({"counters_run": True, "tile": p.params["tile"], "gather_tiled": p.params["gather_tiled"],
-                          "P": p.params["P"], "M": p.params["M"], "launches": args.warmup + args.steps}))
+        p.check()
+        print(json.dumps({"counters_run": True, "workload": args.workload, "tile": p.params["tile"],
+                          "gather_tiled": p.params["gather_tiled"], "P": p.params["P"], "M": p.params["M"],
+                          "launches": args.warmup + args.steps + 1}))
         p.close()
         return
 
     import tempfile
     from paper_2601_00161_amd import autotune
     tune_dir = tempfile.TemporaryDirectory()
+    tune_cache = os.path.join(tune_dir.name, "tune.json")
 
     def make_plan(precision, params, xyz, q):
         """A plan with the autotuned launch shape (tile edge, gather variant)."""
         if args.no_tune or args.tile:
             return Plan(h, N, args.tol, precision=precision, params=params, tile=args.tile, gather=args.gather), None
-        return autotune.tuned_plan(h, N, args.tol, xyz, q, cache=os.path.join(tune_dir.name, "tune.json"),
-                                   precision=precision, params=params)
+        return autotune.tuned_plan(h, N, args.tol, xyz, q, cache=tune_cache, precision=precision, params=params)
 
     # ---- FP32 headline path (learned parameters, autotuned launch shape) ------------
     p32, tuned = make_plan("fp32", args.params, x32, c32)
@@ -296,20 +614,25 @@ def main():
         p32.forces(x32, c32)
     torch.cuda.synchronize()
     # pre-pass: every stage timed once per step to find the dominant kernel
-    p32.profile(["bin", "scatter", "spread", "fft_xy", "fft_z", "fft_xy_inv", "gather"], 64)
-    for _ in range(32):
-        p32.forces(x32, c32)
-    stages = p32.profile_read()
-    dominant = max(stages, key=lambda s: stages[s][0] / stages[s][1])
-    # timed region, with events around every 8th launch of the dominant kernel
+    stages = stage_times(p32, x32, c32, 64, torch)
+    dominant = max(stages, key=lambda s: stages[s])
+    # timed region (exactly --steps steps), with events around every 8th launch
+    # of the dominant kernel
     p32.profile([dominant], args.steps + args.warmup + 2, stride=8)
     dt32, f32, o32 = run_plan(p32, x32, c32, args.steps, args.warmup, torch)
     dom_ms, dom_n = p32.profile_read()[dominant]
     p32.profile([], 0)
 
-    # ---- FP32 with the analytic rule (the proposer's gain) ---------------------
+    # ---- FP32 with the analytic rule, and the plain FP64 path (analytic) -------------
     pa, tuned_a = make_plan("fp32", "analytic", x32, c32)
     dta, fa, oa = run_plan(pa, x32, c32, args.steps, args.warmup, torch)
+    p64, tuned_64 = make_plan("fp64", "analytic", x64, c64)
+    dt64, f64, o64 = run_plan(p64, x64, c64, args.steps, args.warmup, torch)
+    # interleaved windows of the three, for medians and spreads of the comparisons
+    win = windows({"fp32_headline": lambda: p32.forces(x32, c32, f=f32, out7=o32),
+                   "fp32_analytic": lambda: pa.forces(x32, c32, f=fa, out7=oa),
+                   "fp64_analytic": lambda: p64.forces(x64, c64, f=f64, out7=o64)},
+                  max(args.steps, 20), args.windows, torch)
 
     # ---- FP32 with ik-differentiated forces (momentum-conserving option) ------------
     pik = Plan(h, N, args.tol, precision="fp32", params=args.params, force="ik", tile=p32.params["tile"][0])
@@ -318,65 +641,45 @@ def main():
     # ---- FP32 per-particle virial (local pressure) ----------------------------------
     ploc = Plan(h, N, args.tol, precision="fp32", params=args.params, local_virial=True,
                 tile=p32.params["tile"][0])
-    w6, o_loc = ploc.local_virial(x32, c32, out7=torch.empty(7, dtype=torch.float64, device=dev))
-    for _ in range(args.warmup):
-        ploc.local_virial(x32, c32, w6=w6, out7=o_loc)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ploc.local_virial(x32, c32, w6=w6, out7=o_loc)
-    torch.cuda.synchronize()
-    dtloc = time.perf_counter() - t0
-    loc_sum_err = float(np.max(np.abs(w6.double().sum(0).cpu().numpy() - o_loc.cpu().numpy()[1:]))
+    w6l, o_loc = ploc.local_virial(x32, c32, out7=torch.empty(7, dtype=torch.float64, device=dev))
+    dtloc = timed(lambda: ploc.local_virial(x32, c32, w6=w6l, out7=o_loc), args.steps, args.warmup, torch)
+    loc_sum_err = float(np.max(np.abs(w6l.double().sum(0).cpu().numpy() - o_loc.cpu().numpy()[1:]))
                         / np.max(np.abs(o_loc.cpu().numpy()[1:])))
     ploc.close()
 
-    # ---- real-space (near) part, and the total Coulomb step (Fourier forces plus
-    # near forces accumulated in place) on the headline plan --------------------------
-    def timed(fn):
-        for _ in range(args.warmup):
-            fn()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            fn()
-        torch.cuda.synchronize()
-        return time.perf_counter() - t0
-
-    # pressure-only path (energy and virial from one forward FFT, no forces)
+    # ---- pressure-only path, real-space part, total Coulomb step ---------------------
     o_ev = torch.empty(7, dtype=torch.float64, device=dev)
-    dt_ev = timed(lambda: p32.energy_virial(x32, c32, out7=o_ev))
-
+    dt_ev = timed(lambda: p32.energy_virial(x32, c32, out7=o_ev), args.steps, args.warmup, torch)
     f_near = torch.empty_like(f32)
     o_near = torch.empty(7, dtype=torch.float64, device=dev)
-    dt_near = timed(lambda: p32.real_space(x32, c32, f=f_near, out7=o_near))
+    dt_near = timed(lambda: p32.real_space(x32, c32, f=f_near, out7=o_near), args.steps, args.warmup, torch)
     f_tot = torch.empty_like(f32)
     o_tot = torch.empty(7, dtype=torch.float64, device=dev)
 
     def total_step():
         p32.forces(x32, c32, f=f_tot, out7=o_tot)
         p32.real_space(x32, c32, f=f_tot, out7=o_near, accumulate=True)
-    dt_tot = timed(total_step)
+    dt_tot = timed(total_step, args.steps, args.warmup, torch)
     # the same total with the near part on a second stream beside the Fourier part
-    dt_ovl = timed(lambda: p32.coulomb(x32, c32, f=f_tot, out7=o_tot))
-
-    # ---- plain FP64 path, analytic parameters -------------------------------------
-    p64, tuned_64 = make_plan("fp64", "analytic", x64, c64)
-    dt64, f64, o64 = run_plan(p64, x64, c64, args.steps, args.warmup, torch)
-
+    dt_ovl = timed(lambda: p32.coulomb(x32, c32, f=f_tot, out7=o_tot), args.steps, args.warmup, torch)
     f64_near = torch.empty_like(f64)
     o64_near = torch.empty(7, dtype=torch.float64, device=dev)
-    dt64_near = timed(lambda: p64.real_space(x64, c64, f=f64_near, out7=o64_near))
+    dt64_near = timed(lambda: p64.real_space(x64, c64, f=f64_near, out7=o64_near), args.steps, args.warmup, torch)
+    # the headline plan's results again (the timed loops above overwrote nothing of them)
+    torch.cuda.synchronize()
 
-    batch = None if args.no_batch else batch_throughput(torch, dev)
+    ionic = membrane = None
+    if not args.no_extra:
+        ionic = ionic_leg(torch, dev, max(args.steps, 20), args.windows, not args.no_cpu)
+        print("ionic leg done", file=sys.stderr, flush=True)
+        membrane = membrane_leg(torch, dev, max(min(args.steps, 50), 10), 5)
+        print("membrane leg done", file=sys.stderr, flush=True)
+    batch = None if args.no_batch else batch_throughput(torch, dev, tune_cache=tune_cache)
 
-    cpu = None
     extra = {}
     if not args.no_cpu:
         extra = oracle_leg(h, r32, q32, {"fp32_headline": (p32, f32, o32), "fp32_analytic": (pa, fa, oa),
-                                         "fp64_analytic": (p64, f64, o64), "fp32_ik": (pik, fik, oik)},
-                           "fp32_headline")
-        cpu = extra.pop("cpu_baseline")
+                                         "fp64_analytic": (p64, f64, o64), "fp32_ik": (pik, fik, oik)})
 
     prm = p32.params
     G = prm["M"][0] * prm["M"][1] * prm["M"][2]
@@ -387,7 +690,8 @@ def main():
     workload_key = (f"water30k_tol{args.tol:g}_P{prm['P']}_M{prm['M'][0]}x{prm['M'][1]}x{prm['M'][2]}"
                     f"_T{prm['tile'][0]}_{'gtile' if prm['gather_tiled'] else 'gpart'}"
                     f"{'_fixed' if prm['spread_fixed'] else ''}")
-    traffic = measured_traffic(dominant, workload_key)
+    traffic = profile_record("TRAFFIC", dominant, workload_key, "bytes_per_launch")
+    rocprof_us = profile_record("KTIME", dominant, workload_key, "avg_us")
     value = N * args.steps / dt32 / 1e6
     v64 = N * args.steps / dt64 / 1e6
     va = N * args.steps / dta / 1e6
@@ -416,10 +720,13 @@ def main():
                    "M": prm["M"], "rc": prm["rc"], "tile": prm["tile"], "gather_tiled": prm["gather_tiled"],
                    "autotune": tuned,
                    "predicted_log10_err": prm["predicted_log10_err"] if src == "learned" else None},
+        "windows_ms_per_step": {k: spread_stats(v) for k, v in win.items()},
         "fp64_baseline": {"value": round(v64, 3), "ms_per_step": dt64 / args.steps * 1e3, **brief(p64)},
-        "speedup_vs_fp64": value / v64,
+        "speedup_vs_fp64": ratio_stats(win["fp64_analytic"], win["fp32_headline"]),
         "fp32_analytic": {"value": round(va, 3), "ms_per_step": dta / args.steps * 1e3, **brief(pa)},
-        "learned_gain_vs_analytic": value / va,
+        "learned_gain_vs_analytic": ratio_stats(win["fp32_analytic"], win["fp32_headline"]),
+        "ionic_19k_flex": ionic,
+        "membrane_1m_semi": membrane,
         "batch_64_replicas": batch,
         "local_virial_fp32": {"value": round(N * args.steps / dtloc / 1e6, 3), "unit": "M particle-steps/s",
                               "ms_per_step": dtloc / args.steps * 1e3, "shares_sum_rel_err": loc_sum_err},
@@ -438,12 +745,22 @@ def main():
                        "total_coulomb_overlapped_fp32": {"value": round(N * args.steps / dt_ovl / 1e6, 3),
                                                          "ms_per_step": dt_ovl / args.steps * 1e3}},
         **extra,
-        "stage_ms_fp32": {k: v[0] / v[1] for k, v in stages.items()},
+        "stage_ms_fp32": stages,
+        "kernels_fp32": kernel_rates(stages, N, G, S, 4, prm["P"], prm["window_degree"]),
         "roofline": {"kernel": dominant, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "bytes_per_launch": bytes_dom, "avg_launch_us": avg_s * 1e6, "workload_key": workload_key},
+                     "bytes_per_launch": bytes_dom, "avg_launch_us": avg_s * 1e6,
+                     "rocprof_avg_us": rocprof_us,
+                     "frac_at_rocprof_time": (bytes_dom / (rocprof_us * 1e-6) / 1e9 / HBM_PEAK_GBS
+                                              if rocprof_us else None),
+                     "workload_key": workload_key},
         "cpu_baseline": cpu,
     }
+    if cpu is not None:
+        p64p = p64.params
+        cpu["same_params_as_fp64_plan"] = bool(
+            p64p["P"] == cpu_prm["P"] and list(p64p["M"]) == list(cpu_prm["M"])
+            and abs(p64p["c_split"] - cpu_prm["c_split"]) < 1e-9 * cpu_prm["c_split"])
     print(json.dumps(line))
 
 

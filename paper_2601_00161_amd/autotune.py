@@ -13,6 +13,10 @@ same sums, reassociated (and, in fixed point, each term rounded to at most
 2^-61 of its tile's charge bound).
 
     plan, info = autotune.tuned_plan(h, n, tol, xyz, q, cache="tune.json", precision="fp32")
+
+Batches (many replicas, one launch per stage) are tuned on the batch itself:
+tune_batch times the whole batched step for each candidate tile edge of
+each window-support group.
 """
 from __future__ import annotations
 
@@ -112,24 +116,73 @@ def tuned_plan(h, n, tol, xyz, q, cache=DEFAULT_CACHE, retune=False, **opts):
     return plan, dict(rec, key=key)
 
 
-def tuned_tiles(cells, ns, tols, positions, charges, cache=DEFAULT_CACHE, **opts):
-    """Per-replica tile edges for esp.Batch, tuning each distinct problem key once
-    on that replica's own particles."""
+def _batch_ms(batch, xyz, q, reps=10, windows=3):
+    """Median over `windows` of the milliseconds per batched esp_batch_forces
+    call (HIP events around `reps` graph-replayed calls)."""
     import torch
+    f, out = batch.forces(xyz, q)
+    for _ in range(3):
+        batch.forces(xyz, q, f=f, out7=out)
+    ms = []
+    for _ in range(windows):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            batch.forces(xyz, q, f=f, out7=out)
+        b.record()
+        b.synchronize()
+        ms.append(a.elapsed_time(b) / reps)
+    return sorted(ms)[len(ms) // 2]
+
+
+def _batch_key(params):
+    import hashlib
+    txt = ";".join(_key(p) for p in params)
+    return "batch:" + hashlib.sha256(txt.encode()).hexdigest()[:16]
+
+
+def tune_batch(cells, ns, tols, xyz, q, cache=DEFAULT_CACHE, retune=False, tiles=TILES, **opts):
+    """Spreading tile edges for esp.Batch, chosen by timing the batch itself.
+
+    The batch spreads and gathers in one launch per window support P, so the
+    tile edge is chosen per P group: starting from each plan's own rule, every
+    group tries every admissible edge for all its replicas (the other groups
+    at their current choice) and keeps the fastest batch step; one pass over
+    the groups.  Returns {"tiles": per replica (0 = the plan's rule),
+    "groups": {P: edge}, "default_ms", "ms", "key"}; cached like tuned_plan.
+    Results of a tuned batch equal the default batch's up to reassociation
+    (the tile edge only changes which workgroup adds which terms)."""
+    probe = esp.Batch(cells, ns, tols, graph=True, **opts)
+    key = _batch_key(probe.params)
+    Ps = [p["P"] for p in probe.params]
     data = _load(cache)
-    tiles = []
-    changed = False
-    for h, n, tol, r, qq in zip(cells, ns, tols, positions, charges):
-        probe = esp.Plan(h, n, tol, **opts)
-        key = _key(probe.params)
-        dt = probe.dtype
+    if not retune and key in data:
         probe.close()
-        if key not in data:
-            xyz = torch.as_tensor(r, dtype=dt, device="cuda").contiguous()
-            qt = torch.as_tensor(qq, dtype=dt, device="cuda").contiguous()
-            data[key] = tune(h, n, tol, xyz, qt, gathers=("particle",), accums=("fp64",), **opts)
-            changed = True
-        tiles.append(data[key]["tile"])
-    if changed:
-        _save(cache, data)
-    return tiles
+        return dict(data[key], key=key)
+    base = _batch_ms(probe, xyz, q)
+    probe.close()
+    current = [0] * len(ns)
+    best = base
+    groups = {}
+    for P in sorted(set(Ps)):
+        idx = [i for i, p in enumerate(Ps) if p == P]
+        pick = 0
+        for t in tiles:
+            trial = list(current)
+            for i in idx:
+                trial[i] = t
+            try:
+                b = esp.Batch(cells, ns, tols, tiles=trial, graph=True, **opts)
+            except esp.EspError:
+                continue                      # not admissible for some replica of the group
+            ms = _batch_ms(b, xyz, q)
+            b.close()
+            if ms < best:
+                best, pick = ms, t
+        for i in idx:
+            current[i] = pick
+        groups[str(P)] = pick
+    rec = {"tiles": current, "groups": groups, "default_ms": round(base, 4), "ms": round(best, 4)}
+    data[key] = rec
+    _save(cache, data)
+    return dict(rec, key=key)

@@ -59,3 +59,41 @@ def test_forced_gather_variants_agree():
     assert np.max(np.abs(ob.cpu().numpy() - oa.cpu().numpy())) <= 1e-6 * np.max(np.abs(oa.cpu().numpy()))
     a.close()
     b.close()
+
+
+def test_tuned_batch_matches_default_batch(tmp_path):
+    """The batch autotuner (tile edge per window-support group, timed on the
+    batch itself) picks admissible tiles, caches its choice, and the tuned
+    batch computes the default batch's results up to reassociation."""
+    import gpu_util as gu
+    reps = synth.replicas(n_rep=6, config=5, seed=3, n_range=(2000, 9000))
+    cells = [x[0] for x in reps]
+    ns = [len(x[2]) for x in reps]
+    tols = [x[3] for x in reps]
+    xyz = torch.tensor(np.concatenate([x[1] for x in reps]), dtype=torch.float32, device=DEV)
+    qq = torch.tensor(np.concatenate([x[2] for x in reps]), dtype=torch.float32, device=DEV)
+    cache = str(tmp_path / "tune.json")
+    info = autotune.tune_batch(cells, ns, tols, xyz, qq, cache=cache, tiles=(4, 6, 8))
+    b0 = esp.Batch(cells, ns, tols)
+    Ps = sorted({p["P"] for p in b0.params})
+    assert len(info["tiles"]) == len(ns)
+    assert sorted(int(k) for k in info["groups"]) == Ps
+    assert all(t in (0, 4, 6, 8) for t in info["tiles"])
+    assert info["ms"] <= info["default_ms"]
+    assert autotune.tune_batch(cells, ns, tols, xyz, qq, cache=cache, tiles=(4, 6, 8))["tiles"] == info["tiles"]
+    b1 = esp.Batch(cells, ns, tols, tiles=info["tiles"])
+    for b, t in zip(b1.params, info["tiles"]):
+        if t:
+            assert b["tile"][0] == min(t, b["M"][0])
+    f0, o0 = b0.forces(xyz, qq)
+    f1, o1 = b1.forces(xyz, qq)
+    torch.cuda.synchronize()
+    b0.check()
+    b1.check()
+    o0, o1 = o0.cpu().numpy(), o1.cpu().numpy()
+    f0, f1 = f0.double().cpu().numpy(), f1.double().cpu().numpy()
+    for r in range(len(ns)):
+        a, e = b0.offsets[r], b0.offsets[r + 1]
+        gu.parity(f"tuned_batch_rep{r}", o1[r], o0[r][0], o0[r][1:], f1[a:e], f0[a:e], "fp32")
+    b0.close()
+    b1.close()
