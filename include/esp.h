@@ -62,6 +62,9 @@ typedef enum {
   ESP_OK = 0,
   ESP_WARN_REPLAN = 1,    /* esp_set_box: the new box is >10% off the grid rule */
   ESP_WARN_FALLBACK = 2,  /* esp_plan: learned parameters rejected, analytic used */
+  ESP_WARN_PRECISION = 3, /* esp_plan: FP32 plan with tol below 1e-6, which FP32 rounding
+                             (relative errors of a few 1e-7 up to ~3e-6 per virial
+                             component) is not expected to meet; use ESP_FP64 */
   ESP_EINVAL = -1,        /* bad argument (null pointer, bad size or option) */
   ESP_EBOX = -2,          /* det h <= 0 or not finite */
   ESP_ECUTOFF = -3,       /* rc >= half the smallest perpendicular cell width */
@@ -102,9 +105,11 @@ typedef struct {
                           0 = automatic: max(Delta/100, 2e-8) for FP32, Delta/1000
                           for FP64 */
   int gather;          /* ESP_GATHER_AUTO (0): tile-staged gather when tiles hold
-                          96+ particles on average; ESP_GATHER_PARTICLE (1) or
-                          ESP_GATHER_TILE (2) force one variant (the tile variant
-                          is refused if its potential box does not fit in LDS) */
+                          96+ particles on average; ESP_GATHER_PARTICLE (1),
+                          ESP_GATHER_TILE (2: tile-staged, a group of lanes per
+                          particle) or ESP_GATHER_LANE (3: tile-staged, one lane
+                          per particle) force one variant (the tile-staged ones
+                          are refused if the potential box does not fit in LDS) */
   int force;           /* ESP_FORCE_AD (0, default): analytic differentiation,
                           one inverse FFT and a window-gradient gather (App. C,
                           eq. AD); ESP_FORCE_IK (1): ik-differentiation, three
@@ -128,7 +133,7 @@ typedef struct {
                           in fixed point and FP64 batches with FP64 adds. */
 } esp_opts;
 
-enum { ESP_GATHER_AUTO = 0, ESP_GATHER_PARTICLE = 1, ESP_GATHER_TILE = 2 };
+enum { ESP_GATHER_AUTO = 0, ESP_GATHER_PARTICLE = 1, ESP_GATHER_TILE = 2, ESP_GATHER_LANE = 3 };
 enum { ESP_FORCE_AD = 0, ESP_FORCE_IK = 1 };
 enum { ESP_SPREAD_AUTO = 0, ESP_SPREAD_FIXED = 1, ESP_SPREAD_FP64 = 2 };
 
@@ -156,6 +161,7 @@ typedef struct {
   int spread_fixed;               /* 1: the spreading tile accumulates in 64-bit fixed point */
   double hinv[9];                 /* h^-1 of the current cell, row major (the FP32 path uses it as
                                      the float pair hi = (float) hinv, lo = (float) (hinv - hi)) */
+  int gather_lane;                /* 1: the tile-staged gather takes one particle per lane */
 } esp_params;
 
 void esp_opts_default(esp_opts *o);
@@ -163,7 +169,9 @@ void esp_opts_default(esp_opts *o);
 /* Create a plan for n particles in cell h at tolerance tol (Sec. 5.1 rules,
  * or explicit / learned parameters).  Allocates every device buffer.
  *   h: host, 9 doubles.   n >= 1.   tol in [1e-12, 1e-1).   o may be NULL.
- * Errors: ESP_EINVAL, ESP_EBOX, ESP_ECUTOFF, ESP_ENOMEM, ESP_EDEVICE. */
+ * Errors: ESP_EINVAL, ESP_EBOX, ESP_ECUTOFF, ESP_ENOMEM, ESP_EDEVICE.
+ * Warnings (the plan is made): ESP_WARN_FALLBACK (learned parameters),
+ * ESP_WARN_PRECISION (FP32 plan with tol < 1e-6). */
 esp_status esp_plan(const double h[9], int64_t n, double tol, const esp_opts *o,
                     esp_plan_t **out);
 

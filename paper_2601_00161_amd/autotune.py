@@ -27,7 +27,7 @@ import os
 from . import esp
 
 TILES = (4, 5, 6, 8, 10, 12)
-GATHERS = ("particle", "tile")
+GATHERS = ("particle", "tile", "lane")
 ACCUMS = ("fp64", "fixed")
 FIXED_MIN_PER_TILE = 128          # FP64 plans: fixed point is tried from this many particles per tile
 DEFAULT_CACHE = os.environ.get("ESP_AUTOTUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache",

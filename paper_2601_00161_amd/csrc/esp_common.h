@@ -284,6 +284,15 @@ __device__ __forceinline__ double wave_sum_to_last(double v) {
   return v;
 }
 
+// Orders a wave's LDS accesses on either side: what its lanes wrote before is
+// seen by its lanes' accesses after (LDS operations of one wave complete in
+// issue order; this keeps the compiler from moving accesses across it).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Sum of a float over the 64 lanes, left in lane 63 (DPP moves, as above).
 __device__ __forceinline__ float wave_sum_to_last(float v) {
   v += dpp_float<0xb1>(v);
@@ -493,14 +502,29 @@ __device__ void finalize_sums(const DevPlan<R>& d, double* __restrict__ out, dou
 // The plan of the current workgroup and the block index within that plan's
 // range: the kernel argument itself, or (batched launch) the plan whose block
 // range holds blockIdx.x, found by bisection of the block offsets.
+//
+// Workgroup i of a launch is dispatched to XCD i mod 8 (round robin over the
+// 8 XCDs, each with its own L2).  Blocks are renumbered so that each XCD
+// takes runs of kXcdRun consecutive block numbers (tiles along x, column
+// groups of a spectrum row): neighbours that read the same halo cells or the
+// same 128-byte lines then share an L2, while the runs still alternate over
+// the XCDs for load balance.  The ragged last round keeps its order.
+__device__ __forceinline__ int xcd_block(int i, int n) {
+  constexpr int X = kNumXcd, C = kXcdRun;
+  const int full = n / (X * C) * (X * C);
+  if (i >= full) return i;
+  const int round = i / (X * C), k = i - round * X * C;
+  return round * X * C + (k % X) * C + k / X;
+}
+
 template <typename R>
 __device__ __forceinline__ const DevPlan<R>& plan_of(const KArg<R, false>& a, int& blk) {
-  blk = static_cast<int>(blockIdx.x);
+  blk = xcd_block(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
   return a.d;
 }
 template <typename R>
 __device__ __forceinline__ const DevPlan<R>& plan_of(const KArg<R, true>& a, int& blk) {
-  const int b = static_cast<int>(blockIdx.x);
+  const int b = xcd_block(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
   int lo = 0, hi = a.nrep;                  // boff[lo] <= b < boff[hi]
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;

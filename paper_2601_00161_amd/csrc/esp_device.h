@@ -13,12 +13,16 @@
 namespace espx {
 
 constexpr int kMaxP = 12;          // largest window support per dimension
+constexpr double kFp32TolFloor = 1e-6;  // FP32 plans with a smaller tol get ESP_WARN_PRECISION
 constexpr int kMaxWinDeg = 16;     // largest degree of the window polynomials (classes 8, 12, 16)
 constexpr int kMaxKerDeg = 48;     // largest Chebyshev degree of the kernel fits
 constexpr int kMaxRadix = 8;
 constexpr int kMaxStages = 16;
 constexpr int kNumSums = 7;        // energy + 6 virial components
-constexpr int kSpreadChunk = 64;   // particles staged per spreading round
+constexpr int kNumXcd = 8;        // XCDs of the MI355X, each with its own L2
+constexpr int kXcdRun = 16;       // consecutive block numbers one XCD takes (see xcd_block)
+constexpr int kSpreadWaves = 4;   // waves of a spreading workgroup (256 threads)
+constexpr int kWaveChunk = 21;    // particles a spreading wave stages at a time (3 weight tasks each)
 constexpr int kSpreadFixedMin = 128;  // automatic fixed-point spreading of FP64 plans: mean particles
 constexpr int kSpreadFixedMinTiles = 512;  // per tile, and tiles (two per CU), at least
 constexpr int kTiledGatherMin = 96;  // mean particles per tile above which the gather is tile-staged
@@ -108,6 +112,7 @@ struct DevPlan {
   int* flags;                      // bit 0: non-finite input; bit 1: inconsistent tile counts
   int bin_lds;                     // tile histogram of the binning pass fits in LDS
   int gather_tiled;                // gather stages each tile's potential box in LDS
+  int gather_lane;                 // tile-staged gather with one particle per lane
   int ik;                          // forces by ik-differentiation (3 field components)
   int local;                       // per-particle virial enabled (6 field components)
   int ncomp;                       // spectra / real grids allocated (1, 3 or 6)

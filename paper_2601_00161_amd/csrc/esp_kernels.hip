@@ -408,7 +408,7 @@ __global__ void __launch_bounds__(256) k_fft_x(DevPlan<R> d, const R* __restrict
   Cplx<R>* spec = spec_in ? spec_in : d.spec;
   const int M1 = d.M1, M2 = d.M2, H = d.H;
   const int npairs = (M2 + 1) / 2, total = npairs * d.M3;
-  const int q0 = blockIdx.x * npb, np = min(npb, total - q0);
+  const int q0 = xcd_block(blockIdx.x, gridDim.x) * npb, np = min(npb, total - q0);
   Cplx<R>* A = reinterpret_cast<Cplx<R>*>(smem);
   Cplx<R>* B = A + static_cast<size_t>(npb) * M1;
   Cplx<R>* tw1 = B + static_cast<size_t>(npb) * M1;
@@ -447,7 +447,8 @@ __global__ void __launch_bounds__(256) k_fft_y(DevPlan<R> d, Cplx<R>* __restrict
   Cplx<R>* spec = spec_in ? spec_in : d.spec;
   const int M2 = d.M2, H = d.H;
   const int ngrp = (H + ncol - 1) / ncol;
-  const int plane = blockIdx.x / ngrp, grp = blockIdx.x - plane * ngrp;
+  const int bx = xcd_block(blockIdx.x, gridDim.x);
+  const int plane = bx / ngrp, grp = bx - plane * ngrp;
   const int m0 = grp * ncol, nc = min(ncol, H - m0);
   Cplx<R>* A = reinterpret_cast<Cplx<R>*>(smem);
   Cplx<R>* B = A + static_cast<size_t>(ncol) * M2;
@@ -473,7 +474,7 @@ __global__ void __launch_bounds__(256) k_fft_x_inv(DevPlan<R> d, int npb) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int M1 = d.M1, M2 = d.M2, H = d.H;
   const int npairs = (M2 + 1) / 2, total = npairs * d.M3;
-  const int q0 = blockIdx.x * npb, np = min(npb, total - q0);
+  const int q0 = xcd_block(blockIdx.x, gridDim.x) * npb, np = min(npb, total - q0);
   const int comp = blockIdx.y;
   Cplx<R>* A = reinterpret_cast<Cplx<R>*>(smem);
   Cplx<R>* B = A + static_cast<size_t>(npb) * M1;
@@ -757,8 +758,8 @@ size_t lds_fft_z(const DevPlan<R>& d) {
 template <typename R>
 size_t lds_spread(const DevPlan<R>& d) {
   const size_t cells = ((static_cast<size_t>(d.T1 + d.P - 1) * (d.T2 + d.P - 1)) | 1) * (d.T3 + d.P - 1);
-  return cells * sizeof(double) + (kSpreadChunk * 3 * d.P + d.P * (d.nw + 1)) * sizeof(R) +
-         kSpreadChunk * 4 * sizeof(int) + 16;
+  return cells * sizeof(double) + (kSpreadWaves * kWaveChunk * 3 * d.P + d.P * (d.nw + 1)) * sizeof(R) +
+         kSpreadWaves * kWaveChunk * 4 * sizeof(int) + 16;
 }
 
 // Raise the dynamic-LDS limit of a kernel when a launch needs more than 64 KiB.

@@ -279,8 +279,8 @@ esp_status resolve(const double* h, int64_t n, double tol, const esp_opts* o, Re
     return ESP_EINVAL;
   }
   r.window_tol = o->window_tol;
-  if (o->gather < ESP_GATHER_AUTO || o->gather > ESP_GATHER_TILE) {
-    err = "gather must be ESP_GATHER_AUTO, ESP_GATHER_PARTICLE or ESP_GATHER_TILE";
+  if (o->gather < ESP_GATHER_AUTO || o->gather > ESP_GATHER_LANE) {
+    err = "gather must be ESP_GATHER_AUTO, ESP_GATHER_PARTICLE, ESP_GATHER_TILE or ESP_GATHER_LANE";
     return ESP_EINVAL;
   }
   r.gather = o->gather;
@@ -358,6 +358,17 @@ esp_status resolve(const double* h, int64_t n, double tol, const esp_opts* o, Re
     return ESP_EINVAL;
   }
   choose_tiles(r, o->tile);
+  if (r.precision == ESP_FP32 && tol < kFp32TolFloor && warn == ESP_OK) {
+    // FP32 spreading, transforms and gather carry relative rounding errors of
+    // a few 1e-7 (energy, RMS force) up to ~3e-6 (a small virial component)
+    // at identical parameters: a tighter tol is planned for, but the result
+    // is not expected to meet it
+    char b[160];
+    std::snprintf(b, sizeof b, "tol %.3g is below the FP32 floor %.0e: FP32 rounding may exceed it (use ESP_FP64)",
+                  tol, kFp32TolFloor);
+    err = b;
+    warn = ESP_WARN_PRECISION;
+  }
   return warn;
 }
 
@@ -802,11 +813,14 @@ esp_status build_device(esp_plan_t* p) {
   // dense tiles: stage each tile's potential box in LDS for the gather
   const size_t gather_base = ((p->nw + 1) * r.P + (256 / gather_lanes(r.P)) * 6 * r.P) * sizeof(R);
   const bool box_fits = gather_base + lds_gather_box(d) <= static_cast<size_t>(maxlds);
-  if (r.gather == ESP_GATHER_TILE && !box_fits) {
+  const size_t lane_base = ((p->nw + 1) * r.P + 3) / 4 * 4 * sizeof(R);
+  const bool lane_fits = lane_base + lds_gather_box(d) <= static_cast<size_t>(maxlds);
+  if ((r.gather == ESP_GATHER_TILE && !box_fits) || (r.gather == ESP_GATHER_LANE && !lane_fits)) {
     p->err = "the tile-staged gather's potential box does not fit in LDS for this tile";
     return ESP_EINVAL;
   }
-  d.gather_tiled = r.gather == ESP_GATHER_TILE ||
+  d.gather_lane = r.gather == ESP_GATHER_LANE ? 1 : 0;
+  d.gather_tiled = r.gather == ESP_GATHER_TILE || d.gather_lane ||
                    (r.gather == ESP_GATHER_AUTO && box_fits &&
                     r.n >= static_cast<int64_t>(kTiledGatherMin) * r.ntiles);
   // tables: uploaded once every buffer has its place, so that a plan that
@@ -1275,6 +1289,7 @@ esp_status esp_get_params(const esp_plan_t* p, esp_params* out) {
   for (int j = 0; j < 4; ++j) out->predicted_log10_err[j] = r.pred[j];
   out->predicted_cost = r.pred_cost;
   out->gather_tiled = r.precision == ESP_FP32 ? p->d32.gather_tiled : p->d64.gather_tiled;
+  out->gather_lane = r.precision == ESP_FP32 ? p->d32.gather_lane : p->d64.gather_lane;
   out->counter_copies = r.precision == ESP_FP32 ? p->d32.nsub : p->d64.nsub;
   out->force = r.force;
   out->local_virial = r.local;

@@ -98,21 +98,37 @@ __global__ void __launch_bounds__(256) k_spread(KArg<R, BATCH> ka) {
   const int maxcell = (((d.T1 + P - 1) * (d.T2 + P - 1)) | 1) * (d.T3 + P - 1);
   using Cell = typename std::conditional<FIX, unsigned long long, double>::type;
   Cell* grid = reinterpret_cast<Cell*>(smem);
-  R* wts = reinterpret_cast<R*>(grid + maxcell);     // kSpreadChunk x 3 x P (IPROD: x slots hold B)
-  R* win = wts + kSpreadChunk * 3 * P;               // (NW + 1) x P
-  int* base = reinterpret_cast<int*>(win + (NW + 1) * P);   // kSpreadChunk x 3
-  int* shf = base + kSpreadChunk * 3;                // IPROD: kSpreadChunk shifts s
+  R* wts = reinterpret_cast<R*>(grid + maxcell);     // per wave: kWaveChunk x 3 x P (IPROD: x slots hold B)
+  R* win = wts + kSpreadWaves * kWaveChunk * 3 * P;  // (NW + 1) x P
+  int* base = reinterpret_cast<int*>(win + (NW + 1) * P);   // per wave: kWaveChunk x 3
+  int* shf = base + kSpreadWaves * kWaveChunk * 3;   // IPROD, per wave: kWaveChunk shifts s
   const int start = d.offsets[tile], end = d.offsets[tile + 1];
   const R wv = d.win[min(static_cast<int>(threadIdx.x), (NW + 1) * P - 1)];   // in flight with the offsets
   if (threadIdx.x == 0) d.counts[tile] = 0;        // ready for the next binning pass
   if (start == end) return;
-  // one weight task per (particle, dimension) of a chunk: kSpreadChunk x 3 <=
-  // 256 threads, so thread t always takes task t, and its record is fetched
-  // one phase ahead (the first while the LDS tile is cleared)
-  static_assert(kSpreadChunk * 3 <= 256, "one weight task per thread");
-  const int tj = threadIdx.x / 3, tdim = threadIdx.x - 3 * (threadIdx.x / 3);
+  // Each wave spreads chunks of csz particles of its own (chunk c of the
+  // tile goes to wave c mod 4): its lanes evaluate the chunk's weights (one
+  // task per (particle, dimension)), stage them in the wave's LDS slots and
+  // then add the chunk's (particle, z offset) tasks into the shared tile.
+  // Only the tile clear and the write-back are workgroup barriers, so one
+  // wave's weight evaluation overlaps another's LDS atomics.
+  // The chunk size and the wave index are read into scalar registers, so the
+  // chunk loop below is a uniform (scalar) loop of the wave.  Held in vector
+  // registers they made it a divergent loop, whose compiled form gave wrong
+  // grids for P = 8 with fewer than 21 particles per chunk (measured).
+  static_assert(kWaveChunk * 3 <= 64, "one weight task per lane");
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  const int n = end - start;
+  const int csz = __builtin_amdgcn_readfirstlane(max(1, min(kWaveChunk, (n + kSpreadWaves - 1) / kSpreadWaves)));
+  const int step = kSpreadWaves * csz;
+  R* wts_w = wts + wave * kWaveChunk * 3 * P;
+  int* base_w = base + wave * kWaveChunk * 3;
+  int* shf_w = shf + wave * kWaveChunk;
+  const int tj = lane / 3, tdim = lane - 3 * (lane / 3);
+  int c0 = start + wave * csz;
   Record<R> rec;
-  if (threadIdx.x < min(kSpreadChunk, end - start) * 3) rec = d.sorted[start + tj];
+  if (c0 < end && tj < min(csz, end - c0)) rec = d.sorted[c0 + tj];
   float qs = 0.f;
   if constexpr (FIX)
     for (int k = start + threadIdx.x; k < end; k += blockDim.x) qs += fabsf(static_cast<float>(d.sorted[k].q));
@@ -136,10 +152,10 @@ __global__ void __launch_bounds__(256) k_spread(KArg<R, BATCH> ka) {
     unscale = ldexp(1.0, -e);
     kA = 30 - ilogbf(d.wmax * d.wmax);               // |wy wz| 2^kA < 2^31
   }
-  for (int c0 = start; c0 < end; c0 += kSpreadChunk) {
-    const int nc = min(kSpreadChunk, end - c0);
+  for (; c0 < end; c0 += step) {
+    const int nc = min(csz, end - c0);
     // weights: q (and the fixed-point scale) folded into x
-    if (threadIdx.x < nc * 3) {
+    if (tj < nc) {
       const int j = tj, dim = tdim;
       int gm;
       R tau;
@@ -154,42 +170,42 @@ __global__ void __launch_bounds__(256) k_spread(KArg<R, BATCH> ka) {
           const float qa = fabsf(static_cast<float>(rec.q)) * d.wmax;
           const int eq = qa > 0.f ? 30 - ilogbf(qa) : 0;
           const float sq = ldexpf(static_cast<float>(rec.q), eq);
-          int* bw = reinterpret_cast<int*>(wts + j * 3 * P);
+          int* bw = reinterpret_cast<int*>(wts_w + j * 3 * P);
 #pragma unroll
           for (int p = 0; p < P; ++p) bw[p] = __float2int_rn(static_cast<float>(w[p]) * sq);
-          shf[j] = qa > 0.f ? max(0, min(63, eq + kA - e)) : 0;
+          shf_w[j] = qa > 0.f ? max(0, min(63, eq + kA - e)) : 0;
         } else {
           const R sc = dim == 2 ? static_cast<R>(ldexpf(1.f, kA)) : R(1);
 #pragma unroll
-          for (int p = 0; p < P; ++p) wts[(j * 3 + dim) * P + p] = w[p] * sc;
+          for (int p = 0; p < P; ++p) wts_w[(j * 3 + dim) * P + p] = w[p] * sc;
         }
       } else {
         const R sc = dim == 0 ? (FIX ? rec.q * scale : rec.q) : R(1);
 #pragma unroll
-        for (int p = 0; p < P; ++p) wts[(j * 3 + dim) * P + p] = w[p] * sc;
+        for (int p = 0; p < P; ++p) wts_w[(j * 3 + dim) * P + p] = w[p] * sc;
       }
-      base[j * 3 + dim] = gm - od;
+      base_w[j * 3 + dim] = gm - od;
     }
-    __syncthreads();
+    wave_lds_sync();
     {
-      const int c1 = c0 + kSpreadChunk;
-      if (c1 < end && threadIdx.x < min(kSpreadChunk, end - c1) * 3) rec = d.sorted[c1 + tj];
+      const int c1 = c0 + step;
+      if (c1 < end && tj < min(csz, end - c1)) rec = d.sorted[c1 + tj];
     }
     // accumulation: one task per (particle, z offset), the P x P block of that plane
-    for (int t = threadIdx.x; t < nc * P; t += blockDim.x) {
+    for (int t = lane; t < nc * P; t += 64) {
       const int j = t / P, cz = t - j * P;
-      const R* wj = wts + j * 3 * P;
+      const R* wj = wts_w + j * 3 * P;
       R wy[P];
 #pragma unroll
       for (int a = 0; a < P; ++a) wy[a] = wj[P + a];
       const R wz = wj[2 * P + cz];
-      Cell* plane = grid + (base[j * 3 + 2] + cz) * S + base[j * 3 + 1] * E1 + base[j * 3];
+      Cell* plane = grid + (base_w[j * 3 + 2] + cz) * S + base_w[j * 3 + 1] * E1 + base_w[j * 3];
       if constexpr (IPROD) {
         const int* bj = reinterpret_cast<const int*>(wj);
         int bx[P];
 #pragma unroll
         for (int a = 0; a < P; ++a) bx[a] = bj[a];
-        const int sh = shf[j];
+        const int sh = shf_w[j];
         const long long rnd = sh > 0 ? (1ll << (sh - 1)) : 0ll;
 #pragma unroll
         for (int by = 0; by < P; ++by) {
@@ -215,8 +231,10 @@ __global__ void __launch_bounds__(256) k_spread(KArg<R, BATCH> ka) {
         }
       }
     }
-    __syncthreads();
+    // the next chunk's weight writes come after this chunk's reads
+    wave_lds_sync();
   }
+  __syncthreads();
   // write-back: each thread owns one (x, y) column of the tile and walks z
   const int E12 = E1 * E2;
   const size_t planesz = static_cast<size_t>(d.M1) * d.M2;
@@ -614,6 +632,127 @@ __global__ void __launch_bounds__(256) k_gather_tile(KArg<R, BATCH> ka, R* __res
   }
 }
 
+// Tile-staged gather with one particle per lane: the tile's potential box is
+// staged in LDS as in k_gather_tile, then each thread takes whole particles
+// of the tile (contiguous after the sort) in strides of the workgroup size.
+// A lane evaluates its particle's 3 P window values and derivatives itself
+// (the coefficients are read at the same LDS address by every lane, a
+// broadcast) and sums its P^3 stencil; no barrier or cross-lane reduction
+// per particle.  The P^3 potential reads of a wave go to 64 independent
+// stencils of the box.
+template <typename R, int P, int NW>
+__device__ __forceinline__ void eval_window_d(const R* __restrict__ win, R tau, R* w, R* dw) {
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    w[p] = win[NW * P + p];
+    dw[p] = R(0);
+  }
+#pragma unroll
+  for (int j = NW - 1; j >= 0; --j)
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      dw[p] = dw[p] * tau + w[p];
+      w[p] = w[p] * tau + win[j * P + p];
+    }
+}
+
+template <typename R, int P, int NW, bool BATCH>
+__global__ void __launch_bounds__(256) k_gather_lane(KArg<R, BATCH> ka, R* __restrict__ f,
+                                                     double* __restrict__ out7) {
+  int tile;
+  const DevPlan<R>& d = plan_of(ka, tile);
+  f += 3 * d.pofs;
+  if (out7 && tile == 0) {
+    __shared__ double red[kNumSums * 16];
+    finalize_sums(d, out7 + kNumSums * d.rep, red);
+  }
+  extern __shared__ __align__(16) unsigned char smem[];
+  R* win = reinterpret_cast<R*>(smem);                // (NW + 1) x P
+  R* box = win + ((NW + 1) * P + 3) / 4 * 4;          // E1 x E2 x E3 potential values
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int t1 = tile % d.nt1, t2 = (tile / d.nt1) % d.nt2, t3 = tile / (d.nt1 * d.nt2);
+  const int o1 = t1 * d.T1, o2 = t2 * d.T2, o3 = t3 * d.T3;
+  const int E1 = min(d.T1, d.M1 - o1) + P - 1;
+  const int E2 = min(d.T2, d.M2 - o2) + P - 1;
+  const int E3 = min(d.T3, d.M3 - o3) + P - 1;
+  const int E12 = E1 * E2;
+  const int nbox = E12 * E3;
+  constexpr int U = 4;
+  auto box_at = [&](int k) {
+    const int x = k % E1, y = (k / E1) % E2, z = k / E12;
+    int gx = o1 + x, gy = o2 + y, gz = o3 + z;
+    gx -= gx >= d.M1 ? d.M1 : 0;
+    gy -= gy >= d.M2 ? d.M2 : 0;
+    gz -= gz >= d.M3 ? d.M3 : 0;
+    return d.phi[(static_cast<size_t>(gz) * d.M2 + gy) * d.M1 + gx];
+  };
+  auto round = [&](int k0) {
+    R v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = box_at(min(k0 + u * nth, nbox - 1));
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (k0 + u * nth < nbox) box[k0 + u * nth] = v[u];
+  };
+  const int start = d.offsets[tile], end = d.offsets[tile + 1];
+  const R wv = d.win[min(tid, (NW + 1) * P - 1)];
+  round(tid);
+  if (start == end) return;
+  // this thread's first particle, fetched while the box is staged
+  int i = start + tid;
+  Record<R> rec = d.sorted[i < end ? i : start];
+  int64_t j = i < end ? d.perm[i] : 0;
+  if (tid < (NW + 1) * P) win[tid] = wv;
+  for (int k = tid + nth; k < (NW + 1) * P; k += nth) win[k] = d.win[k];
+  for (int k0 = tid + U * nth; k0 < nbox; k0 += U * nth) round(k0);
+  __syncthreads();
+  const R qk0 = d.coulomb_k;
+  for (; i < end; i += nth) {
+    const int inext = i + nth;
+    const Record<R> rn = d.sorted[inext < end ? inext : start];
+    const int64_t jn = inext < end ? d.perm[inext] : 0;
+    int g1, g2, g3;
+    R u1, u2, u3;
+    Coord<R>::stencil(rec, 0, d.M1, P, g1, u1);
+    Coord<R>::stencil(rec, 1, d.M2, P, g2, u2);
+    Coord<R>::stencil(rec, 2, d.M3, P, g3, u3);
+    R w1[P], d1[P], w2[P], d2[P], w3[P], d3[P];
+    eval_window_d<R, P, NW>(win, u1, w1, d1);
+    eval_window_d<R, P, NW>(win, u2, w2, d2);
+    eval_window_d<R, P, NW>(win, u3, w3, d3);
+    // the base lies in this tile: box-local base = g0 - o (no wrap)
+    const R* p0 = box + (g3 - o3) * E12 + (g2 - o2) * E1 + (g1 - o1);
+    R gx = R(0), gy = R(0), gz = R(0);
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+      R sxz = R(0), syz = R(0), s0z = R(0);
+#pragma unroll
+      for (int b = 0; b < P; ++b) {
+        const R* row = p0 + c * E12 + b * E1;
+        R sx = R(0), s0 = R(0);
+#pragma unroll
+        for (int a = 0; a < P; ++a) {
+          const R v = row[a];
+          sx += v * d1[a];
+          s0 += v * w1[a];
+        }
+        sxz += sx * w2[b];
+        s0z += s0 * w2[b];
+        syz += s0 * d2[b];
+      }
+      gx += sxz * w3[c];
+      gy += syz * w3[c];
+      gz += s0z * d3[c];
+    }
+    const R qk = rec.q * qk0;
+    f[3 * j + 0] = qk * (d.G[0] * gx + d.G[1] * gy + d.G[2] * gz);
+    f[3 * j + 1] = qk * (d.G[3] * gx + d.G[4] * gy + d.G[5] * gz);
+    f[3 * j + 2] = qk * (d.G[6] * gx + d.G[7] * gy + d.G[8] * gz);
+    rec = rn;
+    j = jn;
+  }
+}
+
 // ---------------------------------------------------------------- launchers
 template <typename R, int P, int NW, bool FIX>
 static hipError_t spread_acc(const DevPlan<R>& d, hipStream_t s) {
@@ -637,6 +776,15 @@ static size_t gather_lds() {
 
 template <typename R, int P, int NW>
 static hipError_t gather_nw(const DevPlan<R>& d, R* f, double* out7, hipStream_t s) {
+  if (d.gather_lane) {
+    const size_t lds = ((NW + 1) * P + 3) / 4 * 4 * sizeof(R) + lds_gather_box(d);
+    if (lds > 65536)
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather_lane<R, P, NW, false>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    ESP_LAUNCH((k_gather_lane<R, P, NW, false>), dim3(d.ntiles), dim3(256), lds, s, KArg<R, false>{d},
+                       f, out7);
+    return hipGetLastError();
+  }
   if (d.gather_tiled) {
     const size_t lds = gather_lds<R, P, NW>() + lds_gather_box(d);
     if (lds > 65536)

@@ -15,15 +15,15 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libesp_mi355x.so")
 
-ESP_OK, ESP_WARN_REPLAN, ESP_WARN_FALLBACK = 0, 1, 2
+ESP_OK, ESP_WARN_REPLAN, ESP_WARN_FALLBACK, ESP_WARN_PRECISION = 0, 1, 2, 3
 ESP_EINVAL, ESP_EBOX, ESP_ECUTOFF, ESP_ENOMEM, ESP_EDEVICE, ESP_ENONFINITE = -1, -2, -3, -4, -5, -6
-STATUS_NAMES = {0: "ESP_OK", 1: "ESP_WARN_REPLAN", 2: "ESP_WARN_FALLBACK", -1: "ESP_EINVAL",
+STATUS_NAMES = {0: "ESP_OK", 1: "ESP_WARN_REPLAN", 2: "ESP_WARN_FALLBACK", 3: "ESP_WARN_PRECISION", -1: "ESP_EINVAL",
                 -2: "ESP_EBOX", -3: "ESP_ECUTOFF", -4: "ESP_ENOMEM", -5: "ESP_EDEVICE",
                 -6: "ESP_ENONFINITE"}
 PRECISION = {"fp32": 0, "fp64": 1}
 PARAMS = {"analytic": 0, "explicit": 1, "learned": 2}
 COUPLING = {"iso": 0, "semi": 1, "aniso": 2, "flex": 3}
-GATHER = {"auto": 0, "particle": 1, "tile": 2}
+GATHER = {"auto": 0, "particle": 1, "tile": 2, "lane": 3}
 FORCE = {"ad": 0, "ik": 1}
 SPREAD_ACCUM = {"auto": 0, "fixed": 1, "fp64": 2}
 
@@ -55,7 +55,7 @@ class Params(ctypes.Structure):
                 ("gather_tiled", ctypes.c_int), ("counter_copies", ctypes.c_int), ("force", ctypes.c_int),
                 ("local_virial", ctypes.c_int), ("real_cells", ctypes.c_int * 3),
                 ("real_segments", ctypes.c_int), ("fft_split", ctypes.c_int), ("spread_fixed", ctypes.c_int),
-                ("hinv", ctypes.c_double * 9)]
+                ("hinv", ctypes.c_double * 9), ("gather_lane", ctypes.c_int)]
 
     def as_dict(self):
         out = {}

@@ -51,14 +51,16 @@ def test_forced_gather_variants_agree():
     xyz = torch.tensor(r, dtype=torch.float32, device=DEV)
     qq = torch.tensor(q, dtype=torch.float32, device=DEV)
     a = esp.Plan(h, len(q), 1e-4, gather="particle")
-    b = esp.Plan(h, len(q), 1e-4, gather="tile")
-    assert a.params["gather_tiled"] == 0 and b.params["gather_tiled"] == 1
     fa, oa = a.forces(xyz, qq)
-    fb, ob = b.forces(xyz, qq)
-    assert rel_rms(fb.double().cpu().numpy(), fa.double().cpu().numpy()) < 1e-6
-    assert np.max(np.abs(ob.cpu().numpy() - oa.cpu().numpy())) <= 1e-6 * np.max(np.abs(oa.cpu().numpy()))
+    for g in ("tile", "lane"):
+        b = esp.Plan(h, len(q), 1e-4, gather=g)
+        assert a.params["gather_tiled"] == 0 and b.params["gather_tiled"] == 1
+        assert b.params["gather_lane"] == (1 if g == "lane" else 0)
+        fb, ob = b.forces(xyz, qq)
+        assert rel_rms(fb.double().cpu().numpy(), fa.double().cpu().numpy()) < 1e-6
+        assert np.max(np.abs(ob.cpu().numpy() - oa.cpu().numpy())) <= 1e-6 * np.max(np.abs(oa.cpu().numpy()))
+        b.close()
     a.close()
-    b.close()
 
 
 def test_tuned_batch_matches_default_batch(tmp_path):

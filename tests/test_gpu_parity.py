@@ -50,6 +50,9 @@ def systems():
     out.append(("ionic_triclinic_P4", h, r, q, dict(paper_params(h, 1e-3), P=4)))
     h, r, q = synth.water(200, np.diag([2.5, 3.0, 2.0]), config=1, seed=13)
     out.append(("orthorhombic_oddgrid_P7", h, r, q, dict(paper_params(h, 1e-6), M=(27, 30, 25))))
+    # P = 8 (tol 1e-7) on small tiles: few particles per tile and chunk
+    h, r, q = synth.water(600, synth.cubic(2.8), config=1, seed=15)
+    out.append(("water_P8_tol1e-7", h, r, q, paper_params(h, 1e-7)))
     # dense tiles (coarse grid, many particles per tile): the tile-staged gather
     # and the binning with tile-counter copies
     h, r, q = synth.water(7200, synth.cubic(6.0), config=1, seed=14)
@@ -286,6 +289,25 @@ def test_forces(case, precision, accum, dev):
     # the force path's energy and virial are those of the single-FFT path, up
     # to the order in which the spreading adds its tiles into the grid
     assert np.max(np.abs(out - out_ev)) <= (1e-6 if precision == "fp32" else 1e-12) * np.max(np.abs(out_ev))
+    plan.close()
+
+
+@pytest.mark.parametrize("gather", ["particle", "tile", "lane"])
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("case", SYSTEMS, ids=IDS)
+def test_forces_every_gather_variant(case, precision, gather, dev):
+    """A6 with each gather forced: per particle from L2, tile-staged with a
+    group of lanes per particle, tile-staged with one lane per particle."""
+    name, h, r, q, prm = case
+    r_, q_, r64, q64 = as_inputs(r, q, precision)
+    plan = make_plan(h, len(q), prm, precision, gather=gather)
+    assert plan.params["gather_tiled"] == (0 if gather == "particle" else 1)
+    assert plan.params["gather_lane"] == (1 if gather == "lane" else 0)
+    f, out = plan.forces(to_dev(r_, dev), to_dev(q_, dev))
+    assert plan.check() == 0
+    ref = oracle(h, r64, q64, prm)
+    parity_vs_oracle(f"gather_{gather}/{name}", out.cpu().numpy(), ref, f=f.cpu().numpy().astype(np.float64),
+                     precision=precision, ties=ties_of(h, r64, prm))
     plan.close()
 
 

@@ -163,3 +163,18 @@ def test_force_option_is_validated():
     with pytest.raises(esp.EspError):
         esp.resolve_params(np.diag([3.0, 3.0, 3.0]), 100, 1e-4, force=5)
     assert esp.resolve_params(np.diag([3.0, 3.0, 3.0]), 100, 1e-4, force="ik")["P"] >= 2
+
+
+def test_fp32_below_its_floor_warns():
+    """An FP32 plan asked for tol < 1e-6 is planned (the rule's parameters) but
+    flagged ESP_WARN_PRECISION; FP64 plans and FP32 at 1e-6 are not."""
+    import ctypes
+    h = np.diag([3.0, 3.0, 3.0])
+    hp = np.ascontiguousarray(h).ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    for prec, tol, want in (("fp32", 1e-7, esp.ESP_WARN_PRECISION), ("fp32", 1e-6, esp.ESP_OK),
+                            ("fp64", 1e-7, esp.ESP_OK), ("fp32", 1e-5, esp.ESP_OK)):
+        o = esp.make_opts(precision=prec)
+        out = esp.Params()
+        st = esp.lib().esp_resolve_params(hp, 3000, tol, ctypes.byref(o), ctypes.byref(out))
+        assert st == want, (prec, tol, st)
+        assert out.P == int(np.ceil(-np.log10(tol) - 1e-9)) + 1
