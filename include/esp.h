@@ -104,8 +104,9 @@ typedef struct {
   double window_tol;   /* max error of the window polynomials relative to psi(0);
                           0 = automatic: max(Delta/100, 2e-8) for FP32, Delta/1000
                           for FP64 */
-  int gather;          /* ESP_GATHER_AUTO (0): tile-staged gather when tiles hold
-                          96+ particles on average; ESP_GATHER_PARTICLE (1),
+  int gather;          /* ESP_GATHER_AUTO (0): tile-staged gather with one lane per
+                          particle when tiles hold 96+ particles on average, else
+                          per particle; ESP_GATHER_PARTICLE (1),
                           ESP_GATHER_TILE (2: tile-staged, a group of lanes per
                           particle) or ESP_GATHER_LANE (3: tile-staged, one lane
                           per particle) force one variant (the tile-staged ones

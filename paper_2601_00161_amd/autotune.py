@@ -101,14 +101,15 @@ def tune(h, n, tol, xyz, q, reps=20, tiles=TILES, gathers=GATHERS, accums=ACCUMS
     return {"tile": best[0], "gather": best[1], "accum": best[2], "us": round(best[3], 2), "table": table}
 
 
-def tuned_plan(h, n, tol, xyz, q, cache=DEFAULT_CACHE, retune=False, **opts):
-    """A plan with the cached (or freshly tuned) launch shape for this problem."""
+def tuned_plan(h, n, tol, xyz, q, cache=DEFAULT_CACHE, retune=False, tiles=TILES, gathers=GATHERS, **opts):
+    """A plan with the cached (or freshly tuned) launch shape for this problem
+    (candidates: the given tile edges and gather variants)."""
     probe = esp.Plan(h, n, tol, **opts)
     key = _key(probe.params)
     probe.close()
     data = _load(cache)
     if retune or key not in data:
-        data[key] = tune(h, n, tol, xyz, q, **opts)
+        data[key] = tune(h, n, tol, xyz, q, tiles=tiles, gathers=gathers, **opts)
         _save(cache, data)
     rec = data[key]
     plan = esp.Plan(h, n, tol, tile=rec["tile"], gather=rec["gather"], spread_accum=rec.get("accum", "fp64"),
