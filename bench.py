@@ -602,7 +602,7 @@ def main():
     ap.add_argument("--params", default="learned", choices=["learned", "analytic"],
                     help="parameter source of the FP32 headline plan")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner (plan defaults)")
-    ap.add_argument("--gather", default="auto", choices=["auto", "particle", "tile"],
+    ap.add_argument("--gather", default="auto", choices=["auto", "particle", "tile", "lane"],
                     help="gather variant when the launch shape is given (--tile or --no-tune)")
     ap.add_argument("--counters-only", action="store_true",
                     help="run only the headline plan (at --tile / --gather) and the near part, for counter passes")
@@ -766,7 +766,7 @@ def main():
     bytes_dom = stage_bytes(dominant, N, G, S, 4)
     achieved = bytes_dom / avg_s / 1e9
     workload_key = (f"water30k_tol{args.tol:g}_P{prm['P']}_M{prm['M'][0]}x{prm['M'][1]}x{prm['M'][2]}"
-                    f"_T{prm['tile'][0]}_{'gtile' if prm['gather_tiled'] else 'gpart'}"
+                    f"_T{prm['tile'][0]}_{'glane' if prm['gather_lane'] else ('gtile' if prm['gather_tiled'] else 'gpart')}"
                     f"{'_fixed' if prm['spread_fixed'] else ''}")
     traffic = profile_record("TRAFFIC", dominant, workload_key, "bytes_per_launch")
     rocprof_us = profile_record("KTIME", dominant, workload_key, "avg_us")
