@@ -712,6 +712,17 @@ def main():
                    "fp64_analytic": lambda: p64.forces(x64, c64, f=f64, out7=o64)},
                   max(args.steps, 20), args.windows, torch)
 
+    # ---- the headline step replayed as a HIP graph: a batch of one replica (its
+    # plan lives in device memory, so set_box needs no re-capture) --------------------
+    from paper_2601_00161_amd.esp import Batch
+    b1 = Batch([h], [N], [args.tol], tiles=[p32.params["tile"][0]], graph=True, params=args.params)
+    fb1, ob1 = b1.forces(x32, c32)
+    win_graph = windows({"graph": lambda: b1.forces(x32, c32, f=fb1, out7=ob1),
+                         "stream": lambda: p32.forces(x32, c32, f=f32, out7=o32)},
+                        max(args.steps, 20), args.windows, torch)
+    b1.check()
+    b1.close()
+
     # ---- FP32 with ik-differentiated forces (momentum-conserving option) ------------
     pik = Plan(h, N, args.tol, precision="fp32", params=args.params, force="ik", tile=p32.params["tile"][0])
     dtik, fik, oik = run_plan(pik, x32, c32, args.steps, args.warmup, torch)
@@ -799,6 +810,10 @@ def main():
                    "autotune": tuned,
                    "predicted_log10_err": prm["predicted_log10_err"] if src == "learned" else None},
         "windows_ms_per_step": {k: spread_stats(v) for k, v in win.items()},
+        "graph_replay": {"what": "the headline step as a one-replica batch replayed from a HIP graph",
+                         "ms_per_step": spread_stats(win_graph["graph"]),
+                         "stream_ms_per_step": spread_stats(win_graph["stream"]),
+                         "graph_over_stream": ratio_stats(win_graph["stream"], win_graph["graph"])},
         "fp64_baseline": {"value": round(v64, 3), "ms_per_step": dt64 / args.steps * 1e3, **brief(p64)},
         "speedup_vs_fp64": ratio_stats(win["fp64_analytic"], win["fp32_headline"]),
         "fp32_analytic": {"value": round(va, 3), "ms_per_step": dta / args.steps * 1e3, **brief(pa)},
