@@ -159,6 +159,15 @@ __device__ __forceinline__ int fast_div(int a, int b, float rb, int& rem) {
   return q;
 }
 
+// Division by a divisor fixed for the workgroup (grid sizes, column counts),
+// for dividends 0 <= a < 2^24: fast_div with the reciprocal formed once.
+struct Divisor {
+  int b;
+  float rb;
+  __device__ explicit Divisor(int b_) : b(b_), rb(1.0f / static_cast<float>(b_)) {}
+  __device__ __forceinline__ int div(int a, int& rem) const { return fast_div(a, b, rb, rem); }
+};
+
 // One Stockham stage of nlines independent length-n transforms held in LDS:
 // element e of line l lives at base[l * lstride + e * estride].  Adjacent
 // threads take adjacent elements of a line when elements are contiguous

@@ -28,6 +28,9 @@ constexpr int kSpreadFixedMinTiles = 512;  // per tile, and tiles (two per CU), 
 constexpr int kTiledGatherMin = 96;  // mean particles per tile above which the gather is tile-staged
 constexpr int kBinContention = 64;   // target same-address atomics per tile counter in binning
 constexpr int kMaxCounterCopies = 16;
+constexpr int kBinThreads = 256;     // threads of a binning workgroup
+constexpr int kBinMaxPpt = 4;        // particles per binning thread, at most
+constexpr int kScanTpt = 4;          // rounds of tiles the counter-copy scan loads at once
 
 template <typename R>
 struct Cplx {
@@ -74,6 +77,8 @@ struct DevPlan {
   int T1, T2, T3, nt1, nt2, nt3, ntiles;
   int cz;                          // columns per block in the z-pass
   int nbin;                        // blocks of the binning kernel
+  int binppt;                      // particles per binning thread: block b takes particles
+                                   // [b, b + 1) x kBinThreads x binppt
   int nzblk;                       // blocks of the z-pass
   // cell (updated by esp_set_box)
   float hinv_hi[9], hinv_lo[9];    // h^-1 as float-float (FP32 path), row major
@@ -184,6 +189,7 @@ struct BatchLaunch {
   int nrep, nblk, nth;
   size_t lds;
   int P, nw;
+  int ppt;                         // binning stage: largest particles per thread of its plans
 };
 
 // Per-stage kernel timing.  While the host plan times a stage it sets the two

@@ -72,14 +72,38 @@ __device__ void block_scan(const int* __restrict__ counts, int* offs, int n, int
   __syncthreads();
 }
 
+// Binning: turn the block's tile histogram (LDS) into the first rank of the
+// block within each tile, one returning global atomic per occupied tile;
+// U atomics per thread are in flight at once.
+template <int U>
+__device__ __forceinline__ void bin_reserve(int* hist, int* __restrict__ counts, int ntiles, int nth) {
+  for (int k0 = threadIdx.x; k0 < ntiles; k0 += U * nth) {
+    int c[U], r[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + u * nth;
+      c[u] = k < ntiles ? hist[k] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) r[u] = c[u] ? atomicAdd(counts + k0 + u * nth, c[u]) : 0;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (c[u]) hist[k0 + u * nth] = r[u];
+  }
+}
+
 // Cell sort, pass 1.  Each particle gets its reduced coordinates (the sorted
 // record), its tile key (tile of the stencil base g0) and its rank within the
 // tile.  Ranks come from an LDS histogram of the block's keys plus one global
 // atomic per occupied tile and block, so no global counter sees more than
 // one atomic per block.  Also accumulates sum q and sum q^2 per block in FP64.
-template <typename R, bool BATCH>
-__global__ void __launch_bounds__(256) k_bin(KArg<R, BATCH> ka, const R* __restrict__ xyz,
-                                             const R* __restrict__ q) {
+// A thread takes binppt particles (i0 + u x 256, u < binppt): with many tiles
+// the per-block histogram work (clear, read, global atomics) is shared by up
+// to 1,024 particles.
+template <typename R, bool BATCH, int PPT>
+__global__ void __launch_bounds__(kBinThreads) k_bin(KArg<R, BATCH> ka, const R* __restrict__ xyz,
+                                                     const R* __restrict__ q) {
+  static_assert(PPT == 1 || PPT == kBinMaxPpt, "one particle per thread, or up to kBinMaxPpt");
   extern __shared__ int hist[];            // ntiles entries when d.bin_lds
   __shared__ double red[2 * 16];
   int blk;
@@ -87,64 +111,79 @@ __global__ void __launch_bounds__(256) k_bin(KArg<R, BATCH> ka, const R* __restr
   xyz += 3 * d.pofs;
   q += d.pofs;
   const bool lh = d.bin_lds != 0;
-  const int64_t i = static_cast<int64_t>(blk) * blockDim.x + threadIdx.x;
+  const int ppt = PPT == 1 ? 1 : d.binppt, nth = blockDim.x;
+  const int64_t i0 = static_cast<int64_t>(blk) * nth * ppt + threadIdx.x;
   // inputs fetched first; the histogram is cleared while they arrive
-  const int64_t ii = i < d.n ? i : 0;
-  R x = xyz[3 * ii], y = xyz[3 * ii + 1], z = xyz[3 * ii + 2], qi = q[ii];
+  R x[PPT], y[PPT], z[PPT], qi[PPT];
+#pragma unroll
+  for (int u = 0; u < PPT; ++u) {
+    const int64_t i = i0 + static_cast<int64_t>(u) * nth;
+    const int64_t ii = i < d.n ? i : 0;
+    if (u < ppt) {
+      x[u] = xyz[3 * ii];
+      y[u] = xyz[3 * ii + 1];
+      z[u] = xyz[3 * ii + 2];
+      qi[u] = q[ii];
+    }
+  }
   if (lh)
-    for (int k = threadIdx.x; k < d.ntiles; k += blockDim.x) hist[k] = 0;
+    for (int k = threadIdx.x; k < d.ntiles; k += nth) hist[k] = 0;
   __syncthreads();
   double v[2] = {0.0, 0.0};
-  int key = 0, lr = 0;
-  if (i < d.n) {
-    if (!(finite_r(x) && finite_r(y) && finite_r(z) && finite_r(qi))) {
-      atomicOr(d.flags, 1);
-      x = y = z = qi = R(0);
-    }
-    Record<R> rec;
-    Coord<R>::make(d, x, y, z, qi, rec);
-    d.tmp[i] = rec;
-    if (d.cellsort) {
-      key = (Coord<R>::cell(rec, 2, d.cn3) * d.cn2 + Coord<R>::cell(rec, 1, d.cn2)) * d.cn1 +
+  int key[PPT], lr[PPT];
+#pragma unroll
+  for (int u = 0; u < PPT; ++u) {
+    key[u] = 0;
+    lr[u] = 0;
+    const int64_t i = i0 + static_cast<int64_t>(u) * nth;
+    if (u < ppt && i < d.n) {
+      R xu = x[u], yu = y[u], zu = z[u], qu = qi[u];
+      if (!(finite_r(xu) && finite_r(yu) && finite_r(zu) && finite_r(qu))) {
+        atomicOr(d.flags, 1);
+        xu = yu = zu = qu = R(0);
+      }
+      Record<R> rec;
+      Coord<R>::make(d, xu, yu, zu, qu, rec);
+      d.tmp[i] = rec;
+      int k;
+      if (d.cellsort) {
+        k = (Coord<R>::cell(rec, 2, d.cn3) * d.cn2 + Coord<R>::cell(rec, 1, d.cn2)) * d.cn1 +
             Coord<R>::cell(rec, 0, d.cn1);
-    } else {
-      int g1, g2, g3;
-      R t;
-      Coord<R>::stencil(rec, 0, d.M1, d.P, g1, t);
-      Coord<R>::stencil(rec, 1, d.M2, d.P, g2, t);
-      Coord<R>::stencil(rec, 2, d.M3, d.P, g3, t);
-      key = ((g3 / d.T3) * d.nt2 + g2 / d.T2) * d.nt1 + g1 / d.T1;
+      } else {
+        int g1, g2, g3;
+        R t;
+        Coord<R>::stencil(rec, 0, d.M1, d.P, g1, t);
+        Coord<R>::stencil(rec, 1, d.M2, d.P, g2, t);
+        Coord<R>::stencil(rec, 2, d.M3, d.P, g3, t);
+        k = ((g3 / d.T3) * d.nt2 + g2 / d.T2) * d.nt1 + g1 / d.T1;
+      }
+      key[u] = k;
+      lr[u] = lh ? atomicAdd(hist + k, 1)
+                 : atomicAdd(d.counts + static_cast<size_t>(blk % d.nsub) * d.ntiles + k, 1);
+      v[0] += static_cast<double>(qu);
+      v[1] += static_cast<double>(qu) * static_cast<double>(qu);
     }
-    lr = lh ? atomicAdd(hist + key, 1)
-            : atomicAdd(d.counts + static_cast<size_t>(blk % d.nsub) * d.ntiles + key, 1);
-    v[0] = static_cast<double>(qi);
-    v[1] = static_cast<double>(qi) * static_cast<double>(qi);
   }
   __syncthreads();
   int* counts = d.counts + static_cast<size_t>(blk % d.nsub) * d.ntiles;
   if (lh) {
     // a thread issues all of its (returning) atomics before it uses a result,
-    // so their round trips overlap instead of adding up
-    constexpr int U = 4;
-    for (int k0 = threadIdx.x; k0 < d.ntiles; k0 += U * blockDim.x) {
-      int c[U], r[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int k = k0 + u * static_cast<int>(blockDim.x);
-        c[u] = k < d.ntiles ? hist[k] : 0;
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        r[u] = c[u] ? atomicAdd(counts + k0 + u * static_cast<int>(blockDim.x), c[u]) : 0;
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (c[u]) hist[k0 + u * static_cast<int>(blockDim.x)] = r[u];
-    }
+    // so their round trips overlap instead of adding up: rounds of 16 tiles
+    // per thread where tiles are many (10^6 slab, 3,328 tiles: one round trip
+    // instead of four), of 4 otherwise
+    if (d.ntiles > 4 * nth)
+      bin_reserve<16>(hist, counts, d.ntiles, nth);
+    else
+      bin_reserve<4>(hist, counts, d.ntiles, nth);
   }
   __syncthreads();
-  if (i < d.n) {
-    d.keys[i] = key;
-    d.ranks[i] = lh ? hist[key] + lr : lr;
+#pragma unroll
+  for (int u = 0; u < PPT; ++u) {
+    const int64_t i = i0 + static_cast<int64_t>(u) * nth;
+    if (u < ppt && i < d.n) {
+      d.keys[i] = key[u];
+      d.ranks[i] = lh ? hist[key[u]] + lr[u] : lr[u];
+    }
   }
   block_sum<2>(v, red);
   if (threadIdx.x == 0) {
@@ -157,51 +196,60 @@ __global__ void __launch_bounds__(256) k_bin(KArg<R, BATCH> ka, const R* __restr
 // per tile would see hundreds of same-address atomics): one workgroup turns
 // the copies into per-copy bases within each tile and the tile offsets, and
 // clears the counters for the next call.  Tiles go in rounds of one per
-// thread: the nsub counts of a tile are loaded together, the tile totals are
-// scanned (DPP within waves, wave totals through LDS, a carry across rounds),
-// and the bases are written in one pass.
+// thread; the nsub counts of kScanTpt rounds are loaded at once (coalesced,
+// one round trip), then each round's tile totals are scanned (DPP within
+// waves, wave totals through LDS, a carry across rounds) and its bases
+// written.
 template <typename R, bool BATCH>
 __global__ void __launch_bounds__(1024) k_scan_sub(KArg<R, BATCH> ka) {
-  __shared__ int part[16];
+  static_assert(kScanTpt % 2 == 0, "consecutive rounds alternate the two slot sets");
+  __shared__ int part[2][16];
   int blk;
   const DevPlan<R>& d = plan_of(ka, blk);
   if (d.nsub <= 1) return;
   const int nt = d.ntiles, nsub = d.nsub, nth = blockDim.x, tid = threadIdx.x;
   const int lane = tid & 63, wid = tid >> 6, nw = nth >> 6;
   int carry = 0;
-  for (int r0 = 0; r0 < nt; r0 += nth) {
-    const int t = r0 + tid;
-    int v[kMaxCounterCopies];
-    int tot = 0;
+  for (int g0 = 0; g0 < nt; g0 += nth * kScanTpt) {
+    int v[kScanTpt][kMaxCounterCopies];
 #pragma unroll
-    for (int c = 0; c < kMaxCounterCopies; ++c)
-      v[c] = (t < nt && c < nsub) ? d.counts[static_cast<size_t>(c) * nt + t] : 0;
-#pragma unroll
-    for (int c = 0; c < kMaxCounterCopies; ++c) tot += v[c];
-    const int incl = wave_inclusive_scan(tot);
-    if (lane == 63) part[wid] = incl;
-    __syncthreads();
-    int wpre = 0, rtot = 0;
-#pragma unroll
-    for (int w = 0; w < 16; ++w) {
-      const int x = w < nw ? part[w] : 0;
-      wpre += w < wid ? x : 0;
-      rtot += x;
-    }
-    if (t < nt) {
-      int run = carry + wpre + incl - tot;
-      d.offsets[t] = run;
+    for (int j = 0; j < kScanTpt; ++j) {
+      const int t = g0 + j * nth + tid;
 #pragma unroll
       for (int c = 0; c < kMaxCounterCopies; ++c)
-        if (c < nsub) {
-          const size_t k = static_cast<size_t>(c) * nt + t;
-          d.sbase[k] = run;
-          d.counts[k] = 0;
-          run += v[c];
-        }
+        v[j][c] = (t < nt && c < nsub) ? d.counts[static_cast<size_t>(c) * nt + t] : 0;
     }
-    carry += rtot;
-    __syncthreads();                          // part is reused by the next round
+#pragma unroll
+    for (int j = 0; j < kScanTpt; ++j) {
+      const int t = g0 + j * nth + tid;
+      int tot = 0;
+#pragma unroll
+      for (int c = 0; c < kMaxCounterCopies; ++c) tot += v[j][c];
+      const int incl = wave_inclusive_scan(tot);
+      int* pj = part[j & 1];                  // alternating slots: one barrier per round
+      if (lane == 63) pj[wid] = incl;
+      __syncthreads();
+      int wpre = 0, rtot = 0;
+#pragma unroll
+      for (int w = 0; w < 16; ++w) {
+        const int x = w < nw ? pj[w] : 0;
+        wpre += w < wid ? x : 0;
+        rtot += x;
+      }
+      if (t < nt) {
+        int run = carry + wpre + incl - tot;
+        d.offsets[t] = run;
+#pragma unroll
+        for (int c = 0; c < kMaxCounterCopies; ++c)
+          if (c < nsub) {
+            const size_t k = static_cast<size_t>(c) * nt + t;
+            d.sbase[k] = run;
+            d.counts[k] = 0;
+            run += v[j][c];
+          }
+      }
+      carry += rtot;
+    }
   }
   if (tid == 0) d.offsets[nt] = carry;
 }
@@ -219,7 +267,7 @@ __global__ void __launch_bounds__(1024) k_scatter(KArg<R, BATCH> ka) {
   const int64_t i = static_cast<int64_t>(blk) * blockDim.x + threadIdx.x;
   if (d.nsub > 1) {
     if (i < d.n) {
-      const size_t copy = static_cast<size_t>((i / 256) % d.nsub);   // binning block of particle i
+      const size_t copy = static_cast<size_t>((i / (static_cast<int64_t>(kBinThreads) * d.binppt)) % d.nsub);  // binning block of i
       const int pos = d.sbase[copy * d.ntiles + d.keys[i]] + d.ranks[i];
       if (pos >= 0 && pos < d.n) {
         d.sorted[pos] = d.tmp[i];
@@ -270,6 +318,7 @@ __global__ void __launch_bounds__(1024) k_fft_xy(KArg<R, BATCH> ka, const R* __r
   Cplx<R>* spec = spec_in ? spec_in : d.spec;
   const int M1 = d.M1, M2 = d.M2, H = d.H;
   const int npairs = (M2 + 1) / 2;
+  const Divisor dM1(M1), dH(H);
   const int L = max(npairs * M1, M2 * H);
   Cplx<R>* A = reinterpret_cast<Cplx<R>*>(smem);
   Cplx<R>* B = A + L;
@@ -288,7 +337,8 @@ __global__ void __launch_bounds__(1024) k_fft_xy(KArg<R, BATCH> ka, const R* __r
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int k = min(k0 + u * nth, npairs * M1 - 1);
-      const int p = k / M1, x = k - p * M1;
+      int x;
+      const int p = dM1.div(k, x);
       const int y0 = 2 * p;
       re[u] = plane[y0 * M1 + x];
       im[u] = plane[min(y0 + 1, M2 - 1) * M1 + x];
@@ -297,7 +347,8 @@ __global__ void __launch_bounds__(1024) k_fft_xy(KArg<R, BATCH> ka, const R* __r
     for (int u = 0; u < U; ++u) {
       const int k = k0 + u * nth;
       if (k < npairs * M1) {
-        const int p = k / M1, x = k - p * M1;
+        int x;
+        const int p = dM1.div(k, x);
         const int y0 = 2 * p;
         A[k] = {re[u], y0 + 1 < M2 ? im[u] : R(0)};
         if (clear) {
@@ -321,7 +372,8 @@ __global__ void __launch_bounds__(1024) k_fft_xy(KArg<R, BATCH> ka, const R* __r
   // rows 2p (real part) and 2p+1 (imaginary part) were transformed together:
   // X_a[k] = (Z[k] + conj Z[-k]) / 2,  X_b[k] = (Z[k] - conj Z[-k]) / (2 i)
   for (int k = tid; k < npairs * H; k += nth) {
-    const int p = k / H, m = k - p * H;
+    int m;
+    const int p = dH.div(k, m);
     const Cplx<R> Z = res[p * M1 + m];
     const Cplx<R> Zm = res[p * M1 + (m == 0 ? 0 : M1 - m)];
     oth[(2 * p) * H + m] = {R(0.5) * (Z.x + Zm.x), R(0.5) * (Z.y - Zm.y)};
@@ -340,6 +392,7 @@ __global__ void __launch_bounds__(1024) k_fft_xy_inv(KArg<R, BATCH> ka) {
   const DevPlan<R>& d = plan_of(ka, blk);
   const int M1 = d.M1, M2 = d.M2, H = d.H;
   const int npairs = (M2 + 1) / 2;
+  const Divisor dM1(M1);
   const int L = max(npairs * M1, M2 * H);
   Cplx<R>* A = reinterpret_cast<Cplx<R>*>(smem);
   Cplx<R>* B = A + L;
@@ -374,7 +427,8 @@ __global__ void __launch_bounds__(1024) k_fft_xy_inv(KArg<R, BATCH> ka) {
   Cplx<R>* oth = res == A ? B : A;
   // Hermitian rows a (= row 2p) and b (= row 2p+1): Z[x] = X_a[x] + i X_b[x]
   for (int k = tid; k < npairs * M1; k += nth) {
-    const int p = k / M1, x = k - p * M1;
+    int x;
+    const int p = dM1.div(k, x);
     const bool lo = x < H;
     const int xs = lo ? x : M1 - x;
     Cplx<R> a = res[(2 * p) * H + xs];
@@ -389,7 +443,8 @@ __global__ void __launch_bounds__(1024) k_fft_xy_inv(KArg<R, BATCH> ka) {
   res = fft_lines(oth, res, d.f1, npairs, M1, 1, tw1, true, nth);
   R* plane = d.phi + static_cast<size_t>(comp) * d.M3 * M2 * M1 + static_cast<size_t>(zp) * M2 * M1;
   for (int k = tid; k < npairs * M1; k += nth) {
-    const int p = k / M1, x = k - p * M1;
+    int x;
+    const int p = dM1.div(k, x);
     plane[(2 * p) * M1 + x] = res[k].x;
     if (2 * p + 1 < M2) plane[(2 * p + 1) * M1 + x] = res[k].y;
   }
@@ -408,6 +463,7 @@ __global__ void __launch_bounds__(256) k_fft_x(DevPlan<R> d, const R* __restrict
   Cplx<R>* spec = spec_in ? spec_in : d.spec;
   const int M1 = d.M1, M2 = d.M2, H = d.H;
   const int npairs = (M2 + 1) / 2, total = npairs * d.M3;
+  const Divisor dM1(M1), dH(H), dnp(npairs);
   const int q0 = xcd_block(blockIdx.x, gridDim.x) * npb, np = min(npb, total - q0);
   Cplx<R>* A = reinterpret_cast<Cplx<R>*>(smem);
   Cplx<R>* B = A + static_cast<size_t>(npb) * M1;
@@ -416,8 +472,10 @@ __global__ void __launch_bounds__(256) k_fft_x(DevPlan<R> d, const R* __restrict
   for (int k = tid; k < M1; k += nth) tw1[k] = d.tw[d.f1.tw + k];
   R* wgrid = const_cast<R*>(grid);
   for (int k = tid; k < np * M1; k += nth) {
-    const int j = k / M1, x = k - j * M1;
-    const int q = q0 + j, z = q / npairs, y0 = 2 * (q - z * npairs);
+    int x;
+    const int j = dM1.div(k, x);
+    int zr;
+    const int q = q0 + j, z = dnp.div(q, zr), y0 = 2 * zr;
     const size_t r0 = (static_cast<size_t>(z) * M2 + y0) * M1 + x;
     const R re = grid[r0];
     const R im = y0 + 1 < M2 ? grid[r0 + M1] : R(0);
@@ -430,8 +488,10 @@ __global__ void __launch_bounds__(256) k_fft_x(DevPlan<R> d, const R* __restrict
   __syncthreads();
   const Cplx<R>* res = fft_lines(A, B, d.f1, np, M1, 1, tw1, false, nth);
   for (int k = tid; k < np * H; k += nth) {
-    const int j = k / H, m = k - j * H;
-    const int q = q0 + j, z = q / npairs, y0 = 2 * (q - z * npairs);
+    int m;
+    const int j = dH.div(k, m);
+    int zr;
+    const int q = q0 + j, z = dnp.div(q, zr), y0 = 2 * zr;
     const Cplx<R> Z = res[j * M1 + m];
     const Cplx<R> Zm = res[j * M1 + (m == 0 ? 0 : M1 - m)];
     Cplx<R>* row = spec + (static_cast<size_t>(z) * M2 + y0) * H;
@@ -450,6 +510,7 @@ __global__ void __launch_bounds__(256) k_fft_y(DevPlan<R> d, Cplx<R>* __restrict
   const int bx = xcd_block(blockIdx.x, gridDim.x);
   const int plane = bx / ngrp, grp = bx - plane * ngrp;
   const int m0 = grp * ncol, nc = min(ncol, H - m0);
+  const Divisor dnc(nc);
   Cplx<R>* A = reinterpret_cast<Cplx<R>*>(smem);
   Cplx<R>* B = A + static_cast<size_t>(ncol) * M2;
   Cplx<R>* tw2 = B + static_cast<size_t>(ncol) * M2;
@@ -457,13 +518,15 @@ __global__ void __launch_bounds__(256) k_fft_y(DevPlan<R> d, Cplx<R>* __restrict
   for (int k = tid; k < M2; k += nth) tw2[k] = d.tw[d.f2.tw + k];
   Cplx<R>* base = spec + static_cast<size_t>(plane) * M2 * H + m0;
   for (int k = tid; k < M2 * nc; k += nth) {
-    const int y = k / nc, c = k - y * nc;
+    int c;
+    const int y = dnc.div(k, c);
     A[k] = base[static_cast<size_t>(y) * H + c];
   }
   __syncthreads();
   const Cplx<R>* res = fft_lines(A, B, d.f2, nc, 1, nc, tw2, inverse != 0, nth);
   for (int k = tid; k < M2 * nc; k += nth) {
-    const int y = k / nc, c = k - y * nc;
+    int c;
+    const int y = dnc.div(k, c);
     base[static_cast<size_t>(y) * H + c] = res[k];
   }
 }
@@ -474,6 +537,7 @@ __global__ void __launch_bounds__(256) k_fft_x_inv(DevPlan<R> d, int npb) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int M1 = d.M1, M2 = d.M2, H = d.H;
   const int npairs = (M2 + 1) / 2, total = npairs * d.M3;
+  const Divisor dM1(M1), dnp(npairs);
   const int q0 = xcd_block(blockIdx.x, gridDim.x) * npb, np = min(npb, total - q0);
   const int comp = blockIdx.y;
   Cplx<R>* A = reinterpret_cast<Cplx<R>*>(smem);
@@ -485,8 +549,10 @@ __global__ void __launch_bounds__(256) k_fft_x_inv(DevPlan<R> d, int npb) {
   R* phi = d.phi + static_cast<size_t>(comp) * d.M3 * M2 * M1;
   // Hermitian rows a (= row y0) and b (= row y0 + 1): Z[x] = X_a[x] + i X_b[x]
   for (int k = tid; k < np * M1; k += nth) {
-    const int j = k / M1, x = k - j * M1;
-    const int q = q0 + j, z = q / npairs, y0 = 2 * (q - z * npairs);
+    int x;
+    const int j = dM1.div(k, x);
+    int zr;
+    const int q = q0 + j, z = dnp.div(q, zr), y0 = 2 * zr;
     const bool lo = x < H;
     const int xs = lo ? x : M1 - x;
     const Cplx<R>* row = spec + (static_cast<size_t>(z) * M2 + y0) * H;
@@ -501,8 +567,10 @@ __global__ void __launch_bounds__(256) k_fft_x_inv(DevPlan<R> d, int npb) {
   __syncthreads();
   const Cplx<R>* res = fft_lines(A, B, d.f1, np, M1, 1, tw1, true, nth);
   for (int k = tid; k < np * M1; k += nth) {
-    const int j = k / M1, x = k - j * M1;
-    const int q = q0 + j, z = q / npairs, y0 = 2 * (q - z * npairs);
+    int x;
+    const int j = dM1.div(k, x);
+    int zr;
+    const int q = q0 + j, z = dnp.div(q, zr), y0 = 2 * zr;
     const size_t r0 = (static_cast<size_t>(z) * M2 + y0) * M1 + x;
     phi[r0] = res[k].x;
     if (y0 + 1 < M2) phi[r0 + M1] = res[k].y;
@@ -547,6 +615,7 @@ __global__ void __launch_bounds__(256) k_fft_z(KArg<R, BATCH> ka, int mode) {
   const int y = blk / ngrp;
   const int k0 = (blk - y * ngrp) * cz;
   const int nc = min(cz, H - k0);
+  const Divisor dnc(nc);
   double* red = reinterpret_cast<double*>(smem);                   // kNumSums x 16
   Cplx<R>* A = reinterpret_cast<Cplx<R>*>(red + kNumSums * 16);
   Cplx<R>* B = A + cz * M3;
@@ -567,7 +636,8 @@ __global__ void __launch_bounds__(256) k_fft_z(KArg<R, BATCH> ka, int mode) {
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int k = min(tid + u * nth, nc * M3 - 1);
-    const int z = k / nc, c = k - z * nc;
+    int c;
+    const int z = dnc.div(k, c);
     cv[u] = col[z * colstride + c];
   }
   const Cplx<R> twv = d.tw[d.f3.tw + min(tid, M3 - 1)];
@@ -578,7 +648,8 @@ __global__ void __launch_bounds__(256) k_fft_z(KArg<R, BATCH> ka, int mode) {
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int k = min(tid + u * nth, nc * M3 - 1);
-    const int z = k / nc, c = k - z * nc;
+    int c;
+    const int z = dnc.div(k, c);
     iw1p[u] = d.iw1[k0 + c];
     iw3p[u] = d.iw3[z];
   }
@@ -596,14 +667,16 @@ __global__ void __launch_bounds__(256) k_fft_z(KArg<R, BATCH> ka, int mode) {
     kg[k] = d.kerg[k];
   }
   for (int k = tid + U * nth; k < nc * M3; k += nth) {
-    const int z = k / nc, c = k - z * nc;
+    int c;
+    const int z = dnc.div(k, c);
     A[k] = col[z * colstride + c];
   }
   __syncthreads();
   Cplx<R>* res = fft_lines(A, B, d.f3, nc, 1, nc, tw3, false, nth);
   if (mode == Z_FFT_ONLY) {
     for (int k = tid; k < nc * M3; k += nth) {
-      const int z = k / nc, c = k - z * nc;
+      int c;
+      const int z = dnc.div(k, c);
       col[z * colstride + c] = res[k];
     }
     return;
@@ -612,7 +685,8 @@ __global__ void __launch_bounds__(256) k_fft_z(KArg<R, BATCH> ka, int mode) {
   const int m2 = y <= (M2 - 1) / 2 ? y : y - M2;
   // element k of the block; iw = 1 / W_hat^2 of its mode
   auto scale_one = [&](int k, R iw) {
-    const int z = k / nc, c = k - z * nc;
+    int c;
+    const int z = dnc.div(k, c);
     const int i1 = k0 + c;
     const int m1 = i1 <= (M1 - 1) / 2 ? i1 : i1 - M1;
     const int m3 = z <= (M3 - 1) / 2 ? z : z - M3;
@@ -655,7 +729,8 @@ __global__ void __launch_bounds__(256) k_fft_z(KArg<R, BATCH> ka, int mode) {
   for (int u = 0; u < U; ++u)
     if (tid + u * nth < nc * M3) scale_one(tid + u * nth, iw1p[u] * iwy * iw3p[u]);
   for (int k = tid + U * nth; k < nc * M3; k += nth) {
-    const int z = k / nc, c = k - z * nc;
+    int c;
+    const int z = dnc.div(k, c);
     scale_one(k, d.iw1[k0 + c] * iwy * d.iw3[z]);
   }
   // block sums: wave sums by DPP, one LDS slot per wave, and the barrier that
@@ -682,7 +757,8 @@ __global__ void __launch_bounds__(256) k_fft_z(KArg<R, BATCH> ka, int mode) {
   if (mode == Z_POTENTIAL) {
     res = fft_lines(res, oth, d.f3, nc, 1, nc, tw3, true, nth);
     for (int k = tid; k < nc * M3; k += nth) {
-      const int z = k / nc, c = k - z * nc;
+      int c;
+      const int z = dnc.div(k, c);
       col[z * colstride + c] = res[k];
     }
     return;
@@ -697,7 +773,8 @@ __global__ void __launch_bounds__(256) k_fft_z(KArg<R, BATCH> ka, int mode) {
   const int ncomp = mode == Z_IK ? 3 : 6;
   for (int a = 0; a < ncomp; ++a) {
     for (int k = tid; k < nc * M3; k += nth) {
-      const int z = k / nc, c = k - z * nc;
+      int c;
+      const int z = dnc.div(k, c);
       const int i1 = k0 + c;
       const int m1 = i1 <= (M1 - 1) / 2 ? i1 : i1 - M1;
       const int m3 = z <= (M3 - 1) / 2 ? z : z - M3;
@@ -720,7 +797,8 @@ __global__ void __launch_bounds__(256) k_fft_z(KArg<R, BATCH> ka, int mode) {
     Cplx<R>* out = fft_lines(C, oth, d.f3, nc, 1, nc, tw3, true, nth);
     Cplx<R>* dst = col + a * S;
     for (int k = tid; k < nc * M3; k += nth) {
-      const int z = k / nc, c = k - z * nc;
+      int c;
+      const int z = dnc.div(k, c);
       dst[z * colstride + c] = out[k];
     }
     __syncthreads();
@@ -783,7 +861,10 @@ size_t lds_gather_box(const DevPlan<R>& d) {
 template <typename R>
 hipError_t launch_bin(const DevPlan<R>& d, const R* xyz, const R* q, hipStream_t s) {
   const size_t lds = d.bin_lds ? static_cast<size_t>(d.ntiles) * sizeof(int) : 0;
-  ESP_LAUNCH((k_bin<R, false>), dim3(d.nbin), dim3(256), lds, s, KArg<R, false>{d}, xyz, q);
+  if (d.binppt > 1)
+    ESP_LAUNCH((k_bin<R, false, kBinMaxPpt>), dim3(d.nbin), dim3(kBinThreads), lds, s, KArg<R, false>{d}, xyz, q);
+  else
+    ESP_LAUNCH((k_bin<R, false, 1>), dim3(d.nbin), dim3(kBinThreads), lds, s, KArg<R, false>{d}, xyz, q);
   return hipGetLastError();
 }
 
@@ -912,8 +993,13 @@ hipError_t launch_fft_z(const DevPlan<R>& d, ZMode mode, hipStream_t s) {
 // ------------------------------------------------------- batched launchers
 template <typename R>
 hipError_t launch_bin_batch(const BatchLaunch<R>& b, const R* xyz, const R* q, hipStream_t s) {
-  allow_lds(reinterpret_cast<const void*>(&k_bin<R, true>), b.lds);
-  ESP_LAUNCH((k_bin<R, true>), dim3(b.nblk), dim3(b.nth), b.lds, s, karg(b), xyz, q);
+  if (b.ppt > 1) {
+    allow_lds(reinterpret_cast<const void*>(&k_bin<R, true, kBinMaxPpt>), b.lds);
+    ESP_LAUNCH((k_bin<R, true, kBinMaxPpt>), dim3(b.nblk), dim3(b.nth), b.lds, s, karg(b), xyz, q);
+  } else {
+    allow_lds(reinterpret_cast<const void*>(&k_bin<R, true, 1>), b.lds);
+    ESP_LAUNCH((k_bin<R, true, 1>), dim3(b.nblk), dim3(b.nth), b.lds, s, karg(b), xyz, q);
+  }
   return hipGetLastError();
 }
 

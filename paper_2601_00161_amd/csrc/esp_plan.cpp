@@ -640,6 +640,20 @@ int fit_near(esp_plan_t* p, int deg, double eps, int max_seg, std::vector<double
   }
 }
 
+// Binning blocks: 256, 512 or 1,024 particles per block of kBinThreads
+// threads, more where tiles are many, since every block clears and reads the
+// whole tile histogram (10^6 slab, 3,328 tiles: that work was ~70 % of the
+// binning kernel's VALU issue at 256 particles per block).
+template <typename R>
+void set_bin_blocks(DevPlan<R>& d) {
+  d.binppt = d.ntiles >= 2048 ? 4 : (d.ntiles >= 1024 ? 2 : 1);
+  const int64_t per = static_cast<int64_t>(kBinThreads) * d.binppt;
+  d.nbin = static_cast<int>((d.n + per - 1) / per);
+}
+
+// partial-sum slots for any block size set_bin_blocks picks
+size_t bin_blocks_max(int64_t n) { return static_cast<size_t>((n + kBinThreads - 1) / kBinThreads); }
+
 template <typename R>
 esp_status build_device(esp_plan_t* p) {
   const Resolved& r = p->r;
@@ -662,7 +676,7 @@ esp_status build_device(esp_plan_t* p) {
     d.cz = std::max(1, std::min(d.H, per >= 6 ? per : 16));
   }
   d.nzblk = ((d.H + d.cz - 1) / d.cz) * d.M2;
-  d.nbin = static_cast<int>((r.n + 255) / 256);
+  set_bin_blocks(d);
   d.ik = r.force == ESP_FORCE_IK ? 1 : 0;
   d.local = r.local;
   d.ncomp = d.local ? 6 : (d.ik ? 3 : 1);
@@ -789,7 +803,7 @@ esp_status build_device(esp_plan_t* p) {
   const size_t S = static_cast<size_t>(d.H) * r.M[1] * r.M[2];
   // counter copies: about kBinContention same-address atomics per counter at most
   {
-    const double per = static_cast<double>(d.nbin) * std::min(256, r.ntiles) / r.ntiles;
+    const double per = static_cast<double>(d.nbin) * std::min(kBinThreads * d.binppt, r.ntiles) / r.ntiles;
     d.nsub = std::max(1, std::min(kMaxCounterCopies, static_cast<int>(std::ceil(per / kBinContention))));
   }
   const size_t ncount = static_cast<size_t>(r.ntiles) * d.nsub;
@@ -800,7 +814,7 @@ esp_status build_device(esp_plan_t* p) {
                 (st = dalloc(p, &d.nr_keys, r.n)) || (st = dalloc(p, &d.nr_ranks, r.n)) ||
                 (st = dalloc(p, &d.nr_perm, r.n)) || (st = dalloc(p, &d.nr_tmp, r.n)) ||
                 (st = dalloc(p, &d.nr_sorted, r.n)) ||
-                (st = dalloc(p, &d.nr_qpart, static_cast<size_t>(d.nbin) * 2)) ||
+                (st = dalloc(p, &d.nr_qpart, bin_blocks_max(r.n) * 2)) ||
                 (st = dalloc(p, &d.rpart, static_cast<size_t>(std::max(kMaxCells, 2 * kRealBlocks)) * kNumSums)) ||
                 (st = dalloc(p, &d.fpart, static_cast<size_t>(kMaxRealSplit) * r.n * 3)) ||
                 (st = dalloc(p, &d.facc, static_cast<size_t>(r.n) * 3)))) ||
@@ -808,7 +822,7 @@ esp_status build_device(esp_plan_t* p) {
       (st = dalloc(p, &d.tmp, r.n)) || (st = dalloc(p, &d.sorted, r.n)) || (st = dalloc(p, &d.rho, G)) ||
       (st = dalloc(p, &d.spec, S * d.ncomp)) || (st = dalloc(p, &d.phi, G * d.ncomp)) ||
       (st = dalloc(p, &d.zpart, static_cast<size_t>(d.nzblk) * kNumSums)) ||
-      (st = dalloc(p, &d.qpart, static_cast<size_t>(d.nbin) * 2)) || (st = dalloc(p, &d.flags, 4)))
+      (st = dalloc(p, &d.qpart, bin_blocks_max(r.n) * 2)) || (st = dalloc(p, &d.flags, 4)))
     return st;
   d.bin_lds = r.ntiles <= 8192 ? 1 : 0;
   // dense tiles: stage each tile's potential box in LDS for the gather
@@ -973,6 +987,7 @@ DevPlan<R> near_plan(esp_plan_t* p) {
   c.ntiles = c.cn1 * c.cn2 * c.cn3;
   c.nsub = 1;
   c.bin_lds = c.ntiles <= 8192 ? 1 : 0;
+  set_bin_blocks(c);
   c.counts = c.nr_counts;
   c.offsets = c.nr_offsets;
   c.keys = c.nr_keys;
@@ -1552,6 +1567,7 @@ struct BatchStage {
   size_t lds = 0;
   int first = 0, count = 0;
   int P = 0, nw = 0;
+  int ppt = 1;            // binning stage: largest binppt of its replicas
 };
 
 struct esp_batch_s {
@@ -1632,7 +1648,9 @@ esp_status batch_build(esp_batch_t* b) {
   };
   auto zero = [](const DevPlan<R>&) { return size_t(0); };
   make(b->bin, 0, nrep, [](const DevPlan<R>& d) { return d.nbin; },
-       [](const DevPlan<R>& d) { return d.bin_lds ? static_cast<size_t>(d.ntiles) * sizeof(int) : size_t(0); }, 256);
+       [](const DevPlan<R>& d) { return d.bin_lds ? static_cast<size_t>(d.ntiles) * sizeof(int) : size_t(0); },
+       kBinThreads);
+  for (const DevPlan<R>& d : hp) b->bin.ppt = std::max(b->bin.ppt, d.binppt);
   make(b->scatter, 0, nrep, [](const DevPlan<R>& d) { return static_cast<int>((d.n + 1023) / 1024); },
        [](const DevPlan<R>& d) { return (static_cast<size_t>(d.ntiles) + 1) * sizeof(int); }, 1024);
   int nth_xy = 256;
@@ -1684,7 +1702,7 @@ esp_status batch_build(esp_batch_t* b) {
 template <typename R>
 BatchLaunch<R> batch_launch(const esp_batch_t* b, const BatchStage& st) {
   return BatchLaunch<R>{static_cast<const DevPlan<R>*>(b->dplans) + st.first, st.boff, st.count, st.nblk, st.nth,
-                        st.lds, st.P, st.nw};
+                        st.lds, st.P, st.nw, st.ppt};
 }
 
 template <typename R>

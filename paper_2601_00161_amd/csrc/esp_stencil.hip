@@ -53,6 +53,65 @@ __device__ __forceinline__ void window_d_lanes(const R* __restrict__ win, R t1, 
   }
 }
 
+// Walk over the elements tid, tid + nth, tid + 2 nth, ... of a tile's
+// E1 x E2 x E3 box (x fastest) that carries the box coordinates along: a step
+// of nth adds fixed increments with at most one carry per coordinate, so
+// only the first element costs divisions (the staging loops were dominated
+// by three integer divisions per element).
+struct BoxWalk {
+  int k, x, y, z;
+  int dx, dy, dz, E1, E2;
+  __device__ BoxWalk(int k0, int nth, int e1, int e2) : k(k0), E1(e1), E2(e2) {
+    const int e12 = e1 * e2;
+    z = k0 / e12;
+    y = (k0 - z * e12) / e1;
+    x = k0 - z * e12 - y * e1;
+    dz = nth / e12;
+    dy = (nth - dz * e12) / e1;
+    dx = nth - dz * e12 - dy * e1;
+  }
+  __device__ __forceinline__ void step(int nth) {
+    k += nth;
+    x += dx;
+    y += dy;
+    z += dz;
+    if (x >= E1) {
+      x -= E1;
+      ++y;
+    }
+    if (y >= E2) {
+      y -= E2;
+      ++z;
+    }
+  }
+};
+
+// Stage the potential values of the box at grid point (o1, o2, o3) (periodic)
+// into box[(z E2 + y) E1 + x]: rounds of U loads per thread, issued before
+// their stores (elements past the box load the box's first value).  `first`
+// stages only the first round, so that a kernel can put other loads behind
+// it; `w` keeps the position for the remaining rounds.
+template <typename R, int U>
+__device__ __forceinline__ void stage_box_round(const DevPlan<R>& d, R* __restrict__ box, BoxWalk& w, int nbox,
+                                                int o1, int o2, int o3, int nth) {
+  R v[U];
+  int kk[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const bool in = w.k < nbox;
+    int gx = o1 + (in ? w.x : 0), gy = o2 + (in ? w.y : 0), gz = o3 + (in ? w.z : 0);
+    gx -= gx >= d.M1 ? d.M1 : 0;
+    gy -= gy >= d.M2 ? d.M2 : 0;
+    gz -= gz >= d.M3 ? d.M3 : 0;
+    kk[u] = w.k;
+    v[u] = d.phi[(static_cast<size_t>(gz) * d.M2 + gy) * d.M1 + gx];
+    w.step(nth);
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (kk[u] < nbox) box[kk[u]] = v[u];
+}
+
 // ----------------------------------------------------------------- spread
 // One workgroup per tile of T1 x T2 x T3 grid cells.  Its particles (those
 // whose stencil base lies in the tile, contiguous after the cell sort) are
@@ -551,29 +610,14 @@ __global__ void __launch_bounds__(256) k_gather_tile(KArg<R, BATCH> ka, R* __res
   // of U loads per thread, the first together with the offsets (clamped
   // indices: no branches)
   constexpr int U = 4;
-  auto box_at = [&](int k) {
-    const int x = k % E1, y = (k / E1) % E2, z = k / (E1 * E2);
-    int gx = o1 + x, gy = o2 + y, gz = o3 + z;
-    gx -= gx >= d.M1 ? d.M1 : 0;
-    gy -= gy >= d.M2 ? d.M2 : 0;
-    gz -= gz >= d.M3 ? d.M3 : 0;
-    return d.phi[(static_cast<size_t>(gz) * d.M2 + gy) * d.M1 + gx];
-  };
-  auto round = [&](int k0) {
-    R v[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) v[u] = box_at(min(k0 + u * nth, nbox - 1));
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (k0 + u * nth < nbox) box[k0 + u * nth] = v[u];
-  };
+  BoxWalk walk(tid, nth, E1, E2);
   const int start = d.offsets[tile], end = d.offsets[tile + 1];
   const R wv = d.win[min(tid, (NW + 1) * P - 1)];
-  round(tid);
+  stage_box_round<R, U>(d, box, walk, nbox, o1, o2, o3, nth);
   if (start == end) return;
   if (tid < (NW + 1) * P) win[tid] = wv;
   for (int k = tid + nth; k < (NW + 1) * P; k += nth) win[k] = d.win[k];
-  for (int k0 = tid + U * nth; k0 < nbox; k0 += U * nth) round(k0);
+  while (walk.k < nbox) stage_box_round<R, U>(d, box, walk, nbox, o1, o2, o3, nth);
   const int grp = tid / L, lane = tid - grp * L;
   R* my = wt + grp * 6 * P;
   for (int base = start; base < end; base += G) {
@@ -678,25 +722,10 @@ __global__ void __launch_bounds__(256) k_gather_lane(KArg<R, BATCH> ka, R* __res
   const int E12 = E1 * E2;
   const int nbox = E12 * E3;
   constexpr int U = 4;
-  auto box_at = [&](int k) {
-    const int x = k % E1, y = (k / E1) % E2, z = k / E12;
-    int gx = o1 + x, gy = o2 + y, gz = o3 + z;
-    gx -= gx >= d.M1 ? d.M1 : 0;
-    gy -= gy >= d.M2 ? d.M2 : 0;
-    gz -= gz >= d.M3 ? d.M3 : 0;
-    return d.phi[(static_cast<size_t>(gz) * d.M2 + gy) * d.M1 + gx];
-  };
-  auto round = [&](int k0) {
-    R v[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) v[u] = box_at(min(k0 + u * nth, nbox - 1));
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (k0 + u * nth < nbox) box[k0 + u * nth] = v[u];
-  };
+  BoxWalk walk(tid, nth, E1, E2);
   const int start = d.offsets[tile], end = d.offsets[tile + 1];
   const R wv = d.win[min(tid, (NW + 1) * P - 1)];
-  round(tid);
+  stage_box_round<R, U>(d, box, walk, nbox, o1, o2, o3, nth);
   if (start == end) return;
   // this thread's first particle, fetched while the box is staged
   int i = start + tid;
@@ -704,7 +733,7 @@ __global__ void __launch_bounds__(256) k_gather_lane(KArg<R, BATCH> ka, R* __res
   int64_t j = i < end ? d.perm[i] : 0;
   if (tid < (NW + 1) * P) win[tid] = wv;
   for (int k = tid + nth; k < (NW + 1) * P; k += nth) win[k] = d.win[k];
-  for (int k0 = tid + U * nth; k0 < nbox; k0 += U * nth) round(k0);
+  while (walk.k < nbox) stage_box_round<R, U>(d, box, walk, nbox, o1, o2, o3, nth);
   __syncthreads();
   const R qk0 = d.coulomb_k;
   for (; i < end; i += nth) {
