@@ -772,7 +772,9 @@ esp_status build_device(esp_plan_t* p) {
     (void)hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev_id);
   // xy transforms: one workgroup per plane when the plane fits in LDS, else
   // separate x and y passes with as many row pairs / columns per workgroup
-  // (up to 16) as fit
+  // (up to 8) as fit (10^6 slab, 160 x 160 planes: forward and inverse xy
+  // 28.8 / 31.8 us with 8 and 8, 33.6 / 36.2 with 16 and 16, 55.9 / 59.8
+  // with 32 row pairs)
   d.xy_split = r.fft_split || lds_fft_xy(d) > static_cast<size_t>(maxlds) ? 1 : 0;
   // fixed-point spreading: FP32 terms are integer products (two VALU
   // instructions), faster than the FP64 adds on every shape measured (729
@@ -783,7 +785,7 @@ esp_status build_device(esp_plan_t* p) {
                    (r.spread_accum == ESP_SPREAD_AUTO &&
                     (r.precision == ESP_FP32 || (r.ntiles >= kSpreadFixedMinTiles &&
                                                  r.n >= static_cast<int64_t>(kSpreadFixedMin) * r.ntiles)));
-  d.xpairs = d.ycols = 16;
+  d.xpairs = d.ycols = 8;
   while (d.xpairs > 1 && lds_fft_x(d, d.xpairs) > static_cast<size_t>(maxlds)) d.xpairs /= 2;
   while (d.ycols > 1 && lds_fft_y(d, d.ycols) > static_cast<size_t>(maxlds)) d.ycols /= 2;
   const size_t need_xy = d.xy_split ? std::max(lds_fft_x(d, d.xpairs), lds_fft_y(d, d.ycols)) : lds_fft_xy(d);
