@@ -723,6 +723,18 @@ def main():
     b1.check()
     b1.close()
 
+    # ---- the deterministic FP32 plan (int64 grid: outputs repeat bit for bit) -------
+    pdet = Plan(h, N, args.tol, precision="fp32", params=args.params, deterministic=True, spread_accum="fixed",
+                tile=p32.params["tile"][0], gather=tuned["gather"] if tuned else args.gather)
+    fd, od = pdet.forces(x32, c32)
+    fd0, od0 = fd.clone(), od.clone()
+    win_det = windows({"deterministic": lambda: pdet.forces(x32, c32, f=fd, out7=od),
+                       "default": lambda: p32.forces(x32, c32, f=f32, out7=o32)},
+                      max(args.steps, 20), args.windows, torch)
+    det_repeats = bool(torch.equal(fd, fd0) and torch.equal(od, od0))
+    det_grid_fixed = pdet.params["grid_fixed"]
+    pdet.close()
+
     # ---- FP32 with ik-differentiated forces (momentum-conserving option) ------------
     pik = Plan(h, N, args.tol, precision="fp32", params=args.params, force="ik", tile=p32.params["tile"][0])
     dtik, fik, oik = run_plan(pik, x32, c32, args.steps, args.warmup, torch)
@@ -814,6 +826,11 @@ def main():
                          "ms_per_step": spread_stats(win_graph["graph"]),
                          "stream_ms_per_step": spread_stats(win_graph["stream"]),
                          "graph_over_stream": ratio_stats(win_graph["stream"], win_graph["graph"])},
+        "deterministic_fp32": {"what": "the headline plan with esp_opts.deterministic (int64 grid)",
+                               "grid_fixed": det_grid_fixed, "repeats_bit_for_bit": det_repeats,
+                               "ms_per_step": spread_stats(win_det["deterministic"]),
+                               "default_ms_per_step": spread_stats(win_det["default"]),
+                               "cost": ratio_stats(win_det["default"], win_det["deterministic"])},
         "fp64_baseline": {"value": round(v64, 3), "ms_per_step": dt64 / args.steps * 1e3, **brief(p64)},
         "speedup_vs_fp64": ratio_stats(win["fp64_analytic"], win["fp32_headline"]),
         "fp32_analytic": {"value": round(va, 3), "ms_per_step": dta / args.steps * 1e3, **brief(pa)},

@@ -130,8 +130,19 @@ typedef struct {
                           <= 2^59 (FP32) or < 2^62 (FP64), each term rounded once to
                           2^-e, exact integer sums (FP32 terms: the int32-rounded
                           factors q wx 2^eq and wy wz 2^ka multiplied exactly).
-                          Single plans only; batched launches spread FP32 batches
-                          in fixed point and FP64 batches with FP64 adds. */
+                          Tiles add their cells to the grid with floating-point
+                          atomics (see deterministic).  Single plans only;
+                          batched launches spread FP32 batches in fixed point and
+                          FP64 batches with FP64 adds. */
+  int deterministic;   /* nonzero, FP32 plans with fixed-point spreading: the grid is
+                          kept in fixed point too.  Tiles add their sums, rounded
+                          to one scale per call (2^gexp with 2^gexp wmax^3 sum|q|
+                          < 2^57 over all particles), into an int64 grid, so no
+                          sum depends on the order of the atomics and every output
+                          (energy, virial, forces) repeats bit for bit on the same
+                          input (esp_params.grid_fixed).  Costs ~2-3 % per step
+                          (64-bit grid atomics, 8-byte grid reads).  FP64 plans
+                          ignore it. */
 } esp_opts;
 
 enum { ESP_GATHER_AUTO = 0, ESP_GATHER_PARTICLE = 1, ESP_GATHER_TILE = 2, ESP_GATHER_LANE = 3 };
@@ -163,6 +174,8 @@ typedef struct {
   double hinv[9];                 /* h^-1 of the current cell, row major (the FP32 path uses it as
                                      the float pair hi = (float) hinv, lo = (float) (hinv - hi)) */
   int gather_lane;                /* 1: the tile-staged gather takes one particle per lane */
+  int grid_fixed;                 /* 1: deterministic FP32 plan (fixed-point tiles into an int64
+                                     grid): every output repeats bit for bit on the same input */
 } esp_params;
 
 void esp_opts_default(esp_opts *o);
@@ -285,8 +298,9 @@ void esp_destroy(esp_plan_t *p);
 
 /* ---- stage hooks (for testing each step of the path in isolation) ------
  * esp_stage_spread: cell sort + spreading only; copies the real grid
- *   (M1*M2*M3 reals, index (g3*M2 + g2)*M1 + g1, i.e. g1 fastest) to
- *   grid_out (device) and leaves the plan's grid cleared.
+ *   (M1*M2*M3 reals, index (g3*M2 + g2)*M1 + g1, i.e. g1 fastest; a
+ *   fixed-point grid converted to the plan's precision) to grid_out
+ *   (device) and leaves the plan's grid cleared.
  * esp_stage_fft: forward real-to-complex 3D FFT of grid_in (device, layout
  *   as above, unnormalised, sign exp(-2 pi i m.g/M)) into spec_out (device,
  *   (M1/2+1)*M2*M3 complex numbers as interleaved re,im; index

@@ -488,8 +488,8 @@ __device__ void finalize_sums(const DevPlan<R>& d, double* __restrict__ out, dou
   __syncthreads();
   double qv[2] = {0.0, 0.0};
   for (int b = threadIdx.x; b < d.nbin; b += blockDim.x) {
-    qv[0] += d.qpart[2 * b];
-    qv[1] += d.qpart[2 * b + 1];
+    qv[0] += d.qpart[3 * b];
+    qv[1] += d.qpart[3 * b + 1];
   }
   block_sum<2>(qv, red + kNumSums * 16 - 32);
   if (threadIdx.x == 0) {

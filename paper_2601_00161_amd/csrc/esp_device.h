@@ -30,6 +30,7 @@ constexpr int kBinContention = 64;   // target same-address atomics per tile cou
 constexpr int kMaxCounterCopies = 16;
 constexpr int kBinThreads = 256;     // threads of a binning workgroup
 constexpr int kBinMaxPpt = 4;        // particles per binning thread, at most
+constexpr int kGridExp = 56;        // FP32 fixed-point grid scale 2^gexp, gexp = kGridExp - ilogb(wmax^3 sum |q|)
 constexpr int kScanTpt = 4;          // rounds of tiles the counter-copy scan loads at once
 
 template <typename R>
@@ -109,11 +110,14 @@ struct DevPlan {
   int* perm;                       // n: sorted position -> particle
   Record<R>* tmp;                  // n: records in input order
   Record<R>* sorted;               // n
-  R* rho;                          // M1 M2 M3 real grid (kept zero between calls)
+  R* rho;                          // M1 M2 M3 real grid (kept zero between calls), unless grid_fixed
+  long long* rhofix;               // grid_fixed: the grid as int64 at scale 2^gexp (kept zero)
+  int* gexp;                       // grid_fixed: that exponent for the current call (set by the sort)
+  int grid_fixed;                  // FP32 with fixed-point spreading: tiles add integers into rhofix
   Cplx<R>* spec;                   // ncomp x H M2 M3 half spectra
   R* phi;                          // ncomp x M1 M2 M3 real grids (potential, ik field or Pi)
   double* zpart;                   // nzblk x 7 partial mode sums of the z-pass
-  double* qpart;                   // nbin x 2 partial sums (sum q, sum q^2)
+  double* qpart;                   // nbin x 3 partial sums (sum q, sum q^2, sum |q|)
   int* flags;                      // bit 0: non-finite input; bit 1: inconsistent tile counts
   int bin_lds;                     // tile histogram of the binning pass fits in LDS
   int gather_tiled;                // gather stages each tile's potential box in LDS
@@ -150,7 +154,7 @@ struct DevPlan {
   int* nr_perm;                    // n
   Record<R>* nr_tmp;               // n
   Record<R>* nr_sorted;            // n
-  double* nr_qpart;                // nbin x 2
+  double* nr_qpart;                // nbin x 3
   int64_t pofs;                    // batched launches: first particle of this plan in the
   int rep;                         // concatenated inputs, and its index (0 for single plans)
 };
@@ -190,6 +194,7 @@ struct BatchLaunch {
   size_t lds;
   int P, nw;
   int ppt;                         // binning stage: largest particles per thread of its plans
+  int grid_fixed;                  // xy stage: the plans keep int64 grids (deterministic FP32)
 };
 
 // Per-stage kernel timing.  While the host plan times a stage it sets the two
@@ -218,9 +223,13 @@ template <typename R>
 hipError_t launch_finalize(const DevPlan<R>& d, double* out7, hipStream_t s);
 template <typename R>
 hipError_t launch_spread(const DevPlan<R>& d, hipStream_t s);
+// grid: an R grid, or null for the plan's own grid (rhofix when grid_fixed).
 template <typename R>
 hipError_t launch_fft_xy(const DevPlan<R>& d, const R* grid, Cplx<R>* spec, bool clear_input,
                          hipStream_t s);
+// grid_fixed plans: the int64 grid as R values into out, and cleared.
+template <typename R>
+hipError_t launch_grid_out(const DevPlan<R>& d, R* out, hipStream_t s);
 // Z_POTENTIAL: G rho_hat, inverse z; Z_IK: the three components i k_a G rho_hat,
 // each inverse z into its own half spectrum (spec + a * H M2 M3); Z_LOCAL: the
 // six components of P_hat rho_hat / (2 V W_hat^2) (xx, yy, zz, xy, xz, yz).

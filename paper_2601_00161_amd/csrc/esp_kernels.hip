@@ -96,7 +96,8 @@ __device__ __forceinline__ void bin_reserve(int* hist, int* __restrict__ counts,
 // record), its tile key (tile of the stencil base g0) and its rank within the
 // tile.  Ranks come from an LDS histogram of the block's keys plus one global
 // atomic per occupied tile and block, so no global counter sees more than
-// one atomic per block.  Also accumulates sum q and sum q^2 per block in FP64.
+// one atomic per block.  Also accumulates sum q, sum q^2 and sum |q| per
+// block in FP64.
 // A thread takes binppt particles (i0 + u x 256, u < binppt): with many tiles
 // the per-block histogram work (clear, read, global atomics) is shared by up
 // to 1,024 particles.
@@ -105,7 +106,7 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(KArg<R, BATCH> ka, const R*
                                                      const R* __restrict__ q) {
   static_assert(PPT == 1 || PPT == kBinMaxPpt, "one particle per thread, or up to kBinMaxPpt");
   extern __shared__ int hist[];            // ntiles entries when d.bin_lds
-  __shared__ double red[2 * 16];
+  __shared__ double red[3 * 16];
   int blk;
   const DevPlan<R>& d = plan_of(ka, blk);
   xyz += 3 * d.pofs;
@@ -129,7 +130,7 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(KArg<R, BATCH> ka, const R*
   if (lh)
     for (int k = threadIdx.x; k < d.ntiles; k += nth) hist[k] = 0;
   __syncthreads();
-  double v[2] = {0.0, 0.0};
+  double v[3] = {0.0, 0.0, 0.0};
   int key[PPT], lr[PPT];
 #pragma unroll
   for (int u = 0; u < PPT; ++u) {
@@ -162,6 +163,7 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(KArg<R, BATCH> ka, const R*
                  : atomicAdd(d.counts + static_cast<size_t>(blk % d.nsub) * d.ntiles + k, 1);
       v[0] += static_cast<double>(qu);
       v[1] += static_cast<double>(qu) * static_cast<double>(qu);
+      v[2] += fabs(static_cast<double>(qu));
     }
   }
   __syncthreads();
@@ -185,10 +187,30 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(KArg<R, BATCH> ka, const R*
       d.ranks[i] = lh ? hist[key[u]] + lr[u] : lr[u];
     }
   }
-  block_sum<2>(v, red);
+  block_sum<3>(v, red);
   if (threadIdx.x == 0) {
-    d.qpart[2 * blk] = v[0];
-    d.qpart[2 * blk + 1] = v[1];
+    d.qpart[3 * blk] = v[0];
+    d.qpart[3 * blk + 1] = v[1];
+    d.qpart[3 * blk + 2] = v[2];
+  }
+}
+
+// FP32 plans with fixed-point spreading add each tile's integer sums into an
+// int64 grid at one scale 2^gexp for the call: with B = wmax^3 sum |q| no
+// cell exceeds B in magnitude, and gexp = kGridExp - ilogb(B) keeps every
+// cell below 2^57 while a tile's own scale (2^58 over its own, smaller bound)
+// is at least twice as fine, so a tile's sums reach the grid by a rounding
+// right shift.  Integer sums do not depend on the order of the atomics: the
+// grid, and everything computed from it, repeats bit for bit.  One block
+// (of the pass that ends the cell sort) reduces the binning partials.
+template <typename R>
+__device__ void publish_gexp(const DevPlan<R>& d, double* red) {
+  double v[1] = {0.0};
+  for (int b = threadIdx.x; b < d.nbin; b += blockDim.x) v[0] += d.qpart[3 * b + 2];
+  block_sum<1>(v, red);
+  if (threadIdx.x == 0) {
+    const double bound = v[0] * static_cast<double>(d.wmax3);
+    d.gexp[0] = max(-100, min(120, kGridExp - ilogb(fmax(bound, 1e-30))));
   }
 }
 
@@ -204,6 +226,7 @@ template <typename R, bool BATCH>
 __global__ void __launch_bounds__(1024) k_scan_sub(KArg<R, BATCH> ka) {
   static_assert(kScanTpt % 2 == 0, "consecutive rounds alternate the two slot sets");
   __shared__ int part[2][16];
+  __shared__ double red[16];
   int blk;
   const DevPlan<R>& d = plan_of(ka, blk);
   if (d.nsub <= 1) return;
@@ -252,6 +275,7 @@ __global__ void __launch_bounds__(1024) k_scan_sub(KArg<R, BATCH> ka) {
     }
   }
   if (tid == 0) d.offsets[nt] = carry;
+  if (d.grid_fixed) publish_gexp(d, red);
 }
 
 // Cell sort, pass 2.  With one counter per tile every block scans the tile
@@ -262,6 +286,7 @@ template <typename R, bool BATCH>
 __global__ void __launch_bounds__(1024) k_scatter(KArg<R, BATCH> ka) {
   extern __shared__ int offs[];             // ntiles + 1
   __shared__ int part[1024];
+  __shared__ double red[16];
   int blk;
   const DevPlan<R>& d = plan_of(ka, blk);
   const int64_t i = static_cast<int64_t>(blk) * blockDim.x + threadIdx.x;
@@ -293,8 +318,10 @@ __global__ void __launch_bounds__(1024) k_scatter(KArg<R, BATCH> ka) {
       atomicOr(d.flags, 2);                 // inconsistent tile counts
     }
   }
-  if (blk == 0)
+  if (blk == 0) {
     for (int k = threadIdx.x; k <= d.ntiles; k += blockDim.x) d.offsets[k] = offs[k];
+    if (d.grid_fixed) publish_gexp(d, red);
+  }
 }
 
 template <typename R, bool BATCH>
@@ -307,8 +334,9 @@ __global__ void __launch_bounds__(256) k_finalize(KArg<R, BATCH> ka, double* __r
 
 // ------------------------------------------------------------------ FFT xy
 // grid / spec: explicit operands of a single-plan launch, or null for the
-// plan's own rho / spec (batched launches).
-template <typename R, bool BATCH>
+// plan's own rho / spec (batched launches); GF: the plan's own grid is the
+// int64 fixed-point grid (grid_in null).
+template <typename R, bool BATCH, bool GF>
 __global__ void __launch_bounds__(1024) k_fft_xy(KArg<R, BATCH> ka, const R* __restrict__ grid_in,
                                                  Cplx<R>* __restrict__ spec_in, int clear) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -328,6 +356,17 @@ __global__ void __launch_bounds__(1024) k_fft_xy(KArg<R, BATCH> ka, const R* __r
   const size_t zoff = static_cast<size_t>(blk) * M2 * M1;
   const R* plane = grid + zoff;
   R* wplane = const_cast<R*>(grid) + zoff;
+  // the plan's own grid in fixed point: int64 at scale 2^gexp
+  constexpr bool fx = GF;
+  long long* fplane = d.rhofix + (fx ? zoff : 0);
+  const double finv = fx ? ldexp(1.0, -d.gexp[0]) : 0.0;
+  auto cell = [&](int k) { return fx ? static_cast<R>(static_cast<double>(fplane[k]) * finv) : plane[k]; };
+  auto zero = [&](int k) {
+    if (fx)
+      fplane[k] = 0;
+    else
+      wplane[k] = R(0);
+  };
   // The plane in rounds of U loads per thread, issued before their stores;
   // the first round is straight-line code together with the twiddle loads,
   // so that all of them are in flight at once (indices clamped: no branches).
@@ -340,8 +379,8 @@ __global__ void __launch_bounds__(1024) k_fft_xy(KArg<R, BATCH> ka, const R* __r
       int x;
       const int p = dM1.div(k, x);
       const int y0 = 2 * p;
-      re[u] = plane[y0 * M1 + x];
-      im[u] = plane[min(y0 + 1, M2 - 1) * M1 + x];
+      re[u] = cell(y0 * M1 + x);
+      im[u] = cell(min(y0 + 1, M2 - 1) * M1 + x);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -352,8 +391,8 @@ __global__ void __launch_bounds__(1024) k_fft_xy(KArg<R, BATCH> ka, const R* __r
         const int y0 = 2 * p;
         A[k] = {re[u], y0 + 1 < M2 ? im[u] : R(0)};
         if (clear) {
-          wplane[y0 * M1 + x] = R(0);
-          if (y0 + 1 < M2) wplane[(y0 + 1) * M1 + x] = R(0);
+          zero(y0 * M1 + x);
+          if (y0 + 1 < M2) zero((y0 + 1) * M1 + x);
         }
       }
     }
@@ -455,7 +494,7 @@ __global__ void __launch_bounds__(1024) k_fft_xy_inv(KArg<R, BATCH> ka) {
 // as separate passes: the x pass on groups of npb row pairs (two real rows as
 // one complex transform, as above), the y pass on groups of ncol adjacent
 // half-spectrum columns of one plane, transformed in place.
-template <typename R>
+template <typename R, bool GF>
 __global__ void __launch_bounds__(256) k_fft_x(DevPlan<R> d, const R* __restrict__ grid_in,
                                               Cplx<R>* __restrict__ spec_in, int clear, int npb) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -471,18 +510,27 @@ __global__ void __launch_bounds__(256) k_fft_x(DevPlan<R> d, const R* __restrict
   const int nth = blockDim.x, tid = threadIdx.x;
   for (int k = tid; k < M1; k += nth) tw1[k] = d.tw[d.f1.tw + k];
   R* wgrid = const_cast<R*>(grid);
+  constexpr bool fx = GF;                                 // the plan's int64 grid at scale 2^gexp
+  const double finv = fx ? ldexp(1.0, -d.gexp[0]) : 0.0;
+  auto cell = [&](size_t k) { return fx ? static_cast<R>(static_cast<double>(d.rhofix[k]) * finv) : grid[k]; };
+  auto zero = [&](size_t k) {
+    if (fx)
+      d.rhofix[k] = 0;
+    else
+      wgrid[k] = R(0);
+  };
   for (int k = tid; k < np * M1; k += nth) {
     int x;
     const int j = dM1.div(k, x);
     int zr;
     const int q = q0 + j, z = dnp.div(q, zr), y0 = 2 * zr;
     const size_t r0 = (static_cast<size_t>(z) * M2 + y0) * M1 + x;
-    const R re = grid[r0];
-    const R im = y0 + 1 < M2 ? grid[r0 + M1] : R(0);
+    const R re = cell(r0);
+    const R im = y0 + 1 < M2 ? cell(r0 + M1) : R(0);
     A[k] = {re, im};
     if (clear) {
-      wgrid[r0] = R(0);
-      if (y0 + 1 < M2) wgrid[r0 + M1] = R(0);
+      zero(r0);
+      if (y0 + 1 < M2) zero(r0 + M1);
     }
   }
   __syncthreads();
@@ -805,6 +853,16 @@ __global__ void __launch_bounds__(256) k_fft_z(KArg<R, BATCH> ka, int mode) {
   }
 }
 
+template <typename R>
+__global__ void k_grid_out(DevPlan<R> d, R* __restrict__ out, size_t count) {
+  const double inv = ldexp(1.0, -d.gexp[0]);
+  for (size_t k = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < count;
+       k += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    out[k] = static_cast<R>(static_cast<double>(d.rhofix[k]) * inv);
+    d.rhofix[k] = 0;
+  }
+}
+
 template <typename T>
 __global__ void k_fill(T* __restrict__ p, size_t count) {
   for (size_t k = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < count;
@@ -936,12 +994,18 @@ size_t lds_fft_y(const DevPlan<R>& d, int ncol) {
 template <typename R>
 hipError_t launch_fft_xy(const DevPlan<R>& d, const R* grid, Cplx<R>* spec, bool clear_input,
                          hipStream_t s) {
+  const bool gf = sizeof(R) == 4 && grid == nullptr && d.grid_fixed;
   if (d.xy_split) {
     const int total = (d.M2 + 1) / 2 * d.M3;
     size_t lds = lds_fft_x(d, d.xpairs);
-    allow_lds(reinterpret_cast<const void*>(&k_fft_x<R>), lds);
-    ESP_LAUNCH(k_fft_x<R>, dim3((total + d.xpairs - 1) / d.xpairs), dim3(256), lds, s, d, grid, spec,
-                       clear_input ? 1 : 0, d.xpairs);
+    const dim3 nb((total + d.xpairs - 1) / d.xpairs);
+    if (gf) {
+      allow_lds(reinterpret_cast<const void*>(&k_fft_x<R, true>), lds);
+      ESP_LAUNCH((k_fft_x<R, true>), nb, dim3(256), lds, s, d, grid, spec, clear_input ? 1 : 0, d.xpairs);
+    } else {
+      allow_lds(reinterpret_cast<const void*>(&k_fft_x<R, false>), lds);
+      ESP_LAUNCH((k_fft_x<R, false>), nb, dim3(256), lds, s, d, grid, spec, clear_input ? 1 : 0, d.xpairs);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     lds = lds_fft_y(d, d.ycols);
@@ -951,10 +1015,16 @@ hipError_t launch_fft_xy(const DevPlan<R>& d, const R* grid, Cplx<R>* spec, bool
     return hipGetLastError();
   }
   const size_t lds = lds_fft_xy(d);
-  allow_lds(reinterpret_cast<const void*>(&k_fft_xy<R, false>), lds);
   const int nth = fft_threads(d.M1 * d.M2);
-  ESP_LAUNCH((k_fft_xy<R, false>), dim3(d.M3), dim3(nth), lds, s, KArg<R, false>{d}, grid, spec,
-                     clear_input ? 1 : 0);
+  if (gf) {
+    allow_lds(reinterpret_cast<const void*>(&k_fft_xy<R, false, true>), lds);
+    ESP_LAUNCH((k_fft_xy<R, false, true>), dim3(d.M3), dim3(nth), lds, s, KArg<R, false>{d}, grid, spec,
+               clear_input ? 1 : 0);
+  } else {
+    allow_lds(reinterpret_cast<const void*>(&k_fft_xy<R, false, false>), lds);
+    ESP_LAUNCH((k_fft_xy<R, false, false>), dim3(d.M3), dim3(nth), lds, s, KArg<R, false>{d}, grid, spec,
+               clear_input ? 1 : 0);
+  }
   return hipGetLastError();
 }
 
@@ -1028,9 +1098,16 @@ hipError_t launch_gather_batch(const BatchLaunch<R>& b, R* f, double* out7, hipS
 
 template <typename R>
 hipError_t launch_fft_xy_batch(const BatchLaunch<R>& b, hipStream_t s) {
-  allow_lds(reinterpret_cast<const void*>(&k_fft_xy<R, true>), b.lds);
-  ESP_LAUNCH((k_fft_xy<R, true>), dim3(b.nblk), dim3(b.nth), b.lds, s, karg(b),
-                     static_cast<const R*>(nullptr), static_cast<Cplx<R>*>(nullptr), 1);
+  // deterministic FP32 batches read their replicas' int64 grids
+  if (sizeof(R) == 4 && b.grid_fixed) {
+    allow_lds(reinterpret_cast<const void*>(&k_fft_xy<R, true, true>), b.lds);
+    ESP_LAUNCH((k_fft_xy<R, true, true>), dim3(b.nblk), dim3(b.nth), b.lds, s, karg(b),
+               static_cast<const R*>(nullptr), static_cast<Cplx<R>*>(nullptr), 1);
+  } else {
+    allow_lds(reinterpret_cast<const void*>(&k_fft_xy<R, true, false>), b.lds);
+    ESP_LAUNCH((k_fft_xy<R, true, false>), dim3(b.nblk), dim3(b.nth), b.lds, s, karg(b),
+               static_cast<const R*>(nullptr), static_cast<Cplx<R>*>(nullptr), 1);
+  }
   return hipGetLastError();
 }
 
@@ -1062,6 +1139,14 @@ hipError_t launch_fill(T* p, size_t count, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <typename R>
+hipError_t launch_grid_out(const DevPlan<R>& d, R* out, hipStream_t s) {
+  const size_t count = static_cast<size_t>(d.M1) * d.M2 * d.M3;
+  const int nb = static_cast<int>(std::min<size_t>((count + 255) / 256, 4096));
+  ESP_LAUNCH(k_grid_out<R>, dim3(nb), dim3(256), 0, s, d, out, count);
+  return hipGetLastError();
+}
+
 #define ESP_INSTANTIATE(R)                                                                    \
   template hipError_t launch_bin<R>(const DevPlan<R>&, const R*, const R*, hipStream_t);      \
   template hipError_t launch_scatter<R>(const DevPlan<R>&, hipStream_t);                      \
@@ -1083,6 +1168,7 @@ hipError_t launch_fill(T* p, size_t count, hipStream_t s) {
   template hipError_t launch_gather_batch<R>(const BatchLaunch<R>&, R*, double*, hipStream_t); \
   template hipError_t launch_finalize_batch<R>(const BatchLaunch<R>&, double*, hipStream_t);  \
   template hipError_t launch_fill<R>(R*, size_t, hipStream_t);                                \
+  template hipError_t launch_grid_out<R>(const DevPlan<R>&, R*, hipStream_t);                 \
   template size_t lds_fft_xy<R>(const DevPlan<R>&);                                           \
   template size_t lds_fft_x<R>(const DevPlan<R>&, int);                                       \
   template size_t lds_fft_y<R>(const DevPlan<R>&, int);                                       \
@@ -1093,5 +1179,6 @@ hipError_t launch_fill(T* p, size_t count, hipStream_t s) {
 ESP_INSTANTIATE(float)
 ESP_INSTANTIATE(double)
 template hipError_t launch_fill<int>(int*, size_t, hipStream_t);
+template hipError_t launch_fill<long long>(long long*, size_t, hipStream_t);
 
 }  // namespace espx

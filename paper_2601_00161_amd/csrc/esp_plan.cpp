@@ -43,6 +43,7 @@ struct Resolved {
   int local = 0;
   int fft_split = 0;
   int spread_accum = ESP_SPREAD_AUTO;
+  int deterministic = 0;
   double pred[4] = {0, 0, 0, 0};
   double pred_cost = 0;
 };
@@ -296,6 +297,7 @@ esp_status resolve(const double* h, int64_t n, double tol, const esp_opts* o, Re
     return ESP_EINVAL;
   }
   r.spread_accum = o->spread_accum;
+  r.deterministic = o->deterministic ? 1 : 0;
   std::memcpy(r.h, h, 9 * sizeof(double));
   esp_status st = check_box(h, r.rc, r.hinv, &r.V, err);
   if (st != ESP_OK) return st;
@@ -785,6 +787,9 @@ esp_status build_device(esp_plan_t* p) {
                    (r.spread_accum == ESP_SPREAD_AUTO &&
                     (r.precision == ESP_FP32 || (r.ntiles >= kSpreadFixedMinTiles &&
                                                  r.n >= static_cast<int64_t>(kSpreadFixedMin) * r.ntiles)));
+  // deterministic FP32 plans: fixed-point tiles add their integers into an
+  // int64 grid (results that repeat bit for bit); other plans keep the R grid
+  d.grid_fixed = r.deterministic && r.precision == ESP_FP32 && d.spread_fixed ? 1 : 0;
   d.xpairs = d.ycols = 8;
   while (d.xpairs > 1 && lds_fft_x(d, d.xpairs) > static_cast<size_t>(maxlds)) d.xpairs /= 2;
   while (d.ycols > 1 && lds_fft_y(d, d.ycols) > static_cast<size_t>(maxlds)) d.ycols /= 2;
@@ -816,15 +821,16 @@ esp_status build_device(esp_plan_t* p) {
                 (st = dalloc(p, &d.nr_keys, r.n)) || (st = dalloc(p, &d.nr_ranks, r.n)) ||
                 (st = dalloc(p, &d.nr_perm, r.n)) || (st = dalloc(p, &d.nr_tmp, r.n)) ||
                 (st = dalloc(p, &d.nr_sorted, r.n)) ||
-                (st = dalloc(p, &d.nr_qpart, bin_blocks_max(r.n) * 2)) ||
+                (st = dalloc(p, &d.nr_qpart, bin_blocks_max(r.n) * 3)) ||
                 (st = dalloc(p, &d.rpart, static_cast<size_t>(std::max(kMaxCells, 2 * kRealBlocks)) * kNumSums)) ||
                 (st = dalloc(p, &d.fpart, static_cast<size_t>(kMaxRealSplit) * r.n * 3)) ||
                 (st = dalloc(p, &d.facc, static_cast<size_t>(r.n) * 3)))) ||
       (st = dalloc(p, &d.keys, r.n)) || (st = dalloc(p, &d.ranks, r.n)) || (st = dalloc(p, &d.perm, r.n)) ||
-      (st = dalloc(p, &d.tmp, r.n)) || (st = dalloc(p, &d.sorted, r.n)) || (st = dalloc(p, &d.rho, G)) ||
+      (st = dalloc(p, &d.tmp, r.n)) || (st = dalloc(p, &d.sorted, r.n)) || (st = dalloc(p, &d.rho, d.grid_fixed ? 1 : G)) ||
+      (st = dalloc(p, &d.rhofix, d.grid_fixed ? G : 1)) || (st = dalloc(p, &d.gexp, 1)) ||
       (st = dalloc(p, &d.spec, S * d.ncomp)) || (st = dalloc(p, &d.phi, G * d.ncomp)) ||
       (st = dalloc(p, &d.zpart, static_cast<size_t>(d.nzblk) * kNumSums)) ||
-      (st = dalloc(p, &d.qpart, bin_blocks_max(r.n) * 2)) || (st = dalloc(p, &d.flags, 4)))
+      (st = dalloc(p, &d.qpart, bin_blocks_max(r.n) * 3)) || (st = dalloc(p, &d.flags, 4)))
     return st;
   d.bin_lds = r.ntiles <= 8192 ? 1 : 0;
   // dense tiles: stage each tile's potential box in LDS for the gather
@@ -859,7 +865,7 @@ esp_status build_device(esp_plan_t* p) {
     // the region holds whatever its previous user left: clear, stream-ordered
     // with fill kernels, what the force path needs zero at its start
     e = launch_fill(d.counts, ncount, p->stream);
-    if (e == hipSuccess) e = launch_fill(d.rho, G, p->stream);
+    if (e == hipSuccess) e = d.grid_fixed ? launch_fill(d.rhofix, G, p->stream) : launch_fill(d.rho, G, p->stream);
     if (e == hipSuccess) e = launch_fill(d.flags, 4, p->stream);
     const hipError_t es = hipStreamSynchronize(p->stream);
     if (e == hipSuccess) e = es;
@@ -868,7 +874,8 @@ esp_status build_device(esp_plan_t* p) {
   }
   e = hipMemset(d.counts, 0, ncount * sizeof(int));
   if (e == hipSuccess) e = hipMemset(d.nr_counts, 0, kMaxCells * sizeof(int));
-  if (e == hipSuccess) e = hipMemset(d.rho, 0, G * sizeof(R));
+  if (e == hipSuccess)
+    e = d.grid_fixed ? hipMemset(d.rhofix, 0, G * sizeof(long long)) : hipMemset(d.rho, 0, G * sizeof(R));
   if (e == hipSuccess) e = hipMemset(d.facc, 0, static_cast<size_t>(r.n) * 3 * sizeof(double));
   if (e == hipSuccess) e = hipMemset(d.flags, 0, 4 * sizeof(int));
   const hipError_t es = hipDeviceSynchronize();
@@ -929,7 +936,7 @@ esp_status energy_virial(esp_plan_t* p, const R* xyz, const R* q, double* out7) 
   DevPlan<R>& d = dev<R>(p);
   esp_status st = run_sort_spread(p, xyz, q);
   if (st != ESP_OK) return st;
-  hipError_t e = stage(p, ST_FFT_XY, [&] { return launch_fft_xy(d, d.rho, d.spec, true, p->stream); });
+  hipError_t e = stage(p, ST_FFT_XY, [&] { return launch_fft_xy(d, static_cast<const R*>(nullptr), d.spec, true, p->stream); });
   if (e == hipSuccess) e = stage(p, ST_FFT_Z, [&] { return launch_fft_z(d, Z_ENERGY, p->stream); });
   if (e == hipSuccess) e = launch_finalize(d, out7, p->stream);
   return e == hipSuccess ? ESP_OK : hip_fail(p, e, "kernel launch");
@@ -943,7 +950,7 @@ esp_status potential(esp_plan_t* p, const R* xyz, const R* q, ZMode mode = Z_POT
   DevPlan<R>& d = dev<R>(p);
   esp_status st = run_sort_spread(p, xyz, q);
   if (st != ESP_OK) return st;
-  hipError_t e = stage(p, ST_FFT_XY, [&] { return launch_fft_xy(d, d.rho, d.spec, true, p->stream); });
+  hipError_t e = stage(p, ST_FFT_XY, [&] { return launch_fft_xy(d, static_cast<const R*>(nullptr), d.spec, true, p->stream); });
   if (e == hipSuccess) e = stage(p, ST_FFT_Z, [&] { return launch_fft_z(d, mode, p->stream); });
   const int ncomp = mode == Z_IK ? 3 : (mode == Z_LOCAL ? 6 : 1);
   if (e == hipSuccess) e = stage(p, ST_FFT_XY_INV, [&] { return launch_fft_xy_inv(d, ncomp, p->stream); });
@@ -986,6 +993,7 @@ template <typename R>
 DevPlan<R> near_plan(esp_plan_t* p) {
   DevPlan<R> c = dev<R>(p);
   c.cellsort = 1;
+  c.grid_fixed = 0;                   // the near part's sort publishes no grid scale
   c.ntiles = c.cn1 * c.cn2 * c.cn3;
   c.nsub = 1;
   c.bin_lds = c.ntiles <= 8192 ? 1 : 0;
@@ -1311,6 +1319,7 @@ esp_status esp_get_params(const esp_plan_t* p, esp_params* out) {
   out->predicted_cost = r.pred_cost;
   out->gather_tiled = r.precision == ESP_FP32 ? p->d32.gather_tiled : p->d64.gather_tiled;
   out->gather_lane = r.precision == ESP_FP32 ? p->d32.gather_lane : p->d64.gather_lane;
+  out->grid_fixed = r.precision == ESP_FP32 ? p->d32.grid_fixed : 0;
   out->counter_copies = r.precision == ESP_FP32 ? p->d32.nsub : p->d64.nsub;
   out->force = r.force;
   out->local_virial = r.local;
@@ -1372,8 +1381,12 @@ esp_status esp_stage_spread(esp_plan_t* p, const void* xyz, const void* q, void*
   if (p->r.precision == ESP_FP32) {
     st = run_sort_spread(p, static_cast<const float*>(xyz), static_cast<const float*>(q));
     if (st != ESP_OK) return st;
-    e = hipMemcpyAsync(grid_out, p->d32.rho, G * sizeof(float), hipMemcpyDeviceToDevice, p->stream);
-    if (e == hipSuccess) e = launch_fill(p->d32.rho, G, p->stream);
+    if (p->d32.grid_fixed) {
+      e = launch_grid_out(p->d32, static_cast<float*>(grid_out), p->stream);
+    } else {
+      e = hipMemcpyAsync(grid_out, p->d32.rho, G * sizeof(float), hipMemcpyDeviceToDevice, p->stream);
+      if (e == hipSuccess) e = launch_fill(p->d32.rho, G, p->stream);
+    }
   } else {
     st = run_sort_spread(p, static_cast<const double*>(xyz), static_cast<const double*>(q));
     if (st != ESP_OK) return st;
@@ -1570,6 +1583,7 @@ struct BatchStage {
   int first = 0, count = 0;
   int P = 0, nw = 0;
   int ppt = 1;            // binning stage: largest binppt of its replicas
+  int grid_fixed = 0;     // xy stage: the replicas keep int64 grids
 };
 
 struct esp_batch_s {
@@ -1632,6 +1646,13 @@ esp_status batch_build(esp_batch_t* b) {
       b->err = "a replica's grid plane exceeds one workgroup's LDS; batched launches need the one-pass xy transform";
       return ESP_EINVAL;
     }
+  // batched FP32 spreading is fixed point: a deterministic batch needs every
+  // replica's int64 grid (batch options are shared, so all or none have one)
+  for (int k = 0; k < nrep; ++k)
+    if (hp[k].grid_fixed != hp[0].grid_fixed || (hp[k].grid_fixed && sizeof(R) != 4)) {
+      b->err = "replicas differ in their grid accumulation (deterministic FP32 batches need fixed-point tiles)";
+      return ESP_EINVAL;
+    }
   std::vector<int> offs;
   auto make = [&](BatchStage& st, int first, int count, auto nblk_of, auto lds_of, int nth) {
     st.first = first;
@@ -1659,6 +1680,7 @@ esp_status batch_build(esp_batch_t* b) {
   for (const DevPlan<R>& d : hp) nth_xy = std::max(nth_xy, fft_threads(d.M1 * d.M2));
   make(b->fxy, 0, nrep, [](const DevPlan<R>& d) { return d.M3; }, [](const DevPlan<R>& d) { return lds_fft_xy(d); },
        nth_xy);
+  b->fxy.grid_fixed = hp[0].grid_fixed;
   make(b->fz, 0, nrep, [](const DevPlan<R>& d) { return d.nzblk; }, [](const DevPlan<R>& d) { return lds_fft_z(d); },
        256);
   make(b->fxyi, 0, nrep, [](const DevPlan<R>& d) { return d.M3; }, [](const DevPlan<R>& d) { return lds_fft_xy(d); },
@@ -1704,7 +1726,7 @@ esp_status batch_build(esp_batch_t* b) {
 template <typename R>
 BatchLaunch<R> batch_launch(const esp_batch_t* b, const BatchStage& st) {
   return BatchLaunch<R>{static_cast<const DevPlan<R>*>(b->dplans) + st.first, st.boff, st.count, st.nblk, st.nth,
-                        st.lds, st.P, st.nw, st.ppt};
+                        st.lds, st.P, st.nw, st.ppt, st.grid_fixed};
 }
 
 template <typename R>

@@ -294,9 +294,32 @@ __global__ void __launch_bounds__(256) k_spread(KArg<R, BATCH> ka) {
     wave_lds_sync();
   }
   __syncthreads();
-  // write-back: each thread owns one (x, y) column of the tile and walks z
+  // write-back: each thread owns one (x, y) column of the tile and walks z.
+  // Deterministic FP32 plans: the tile's integers, rescaled from 2^e to the
+  // grid's 2^gexp by a rounding shift, are added to the int64 grid (order-
+  // independent sums); otherwise the cells are added to the R grid.
   const int E12 = E1 * E2;
   const size_t planesz = static_cast<size_t>(d.M1) * d.M2;
+  if (IPROD && d.grid_fixed) {
+    const int sh = max(0, min(63, e - d.gexp[0]));    // >= 1 unless both scales are clamped
+    const long long half = sh > 0 ? (1ll << (sh - 1)) : 0ll;
+    for (int k0 = threadIdx.x; k0 < E12; k0 += blockDim.x) {
+      const int y = k0 / E1, x = k0 - y * E1;
+      int gx = o1 + x, gy = o2 + y;
+      gx -= gx >= d.M1 ? d.M1 : 0;
+      gy -= gy >= d.M2 ? d.M2 : 0;
+      unsigned long long* col =
+          reinterpret_cast<unsigned long long*>(d.rhofix) + static_cast<size_t>(gy) * d.M1 + gx;
+      for (int z = 0; z < E3; ++z) {
+        const long long v = static_cast<long long>(grid[z * S + k0]);
+        const long long g = sh == 63 ? 0ll : (v + half) >> sh;
+        int gz = o3 + z;
+        gz -= gz >= d.M3 ? d.M3 : 0;
+        if (g != 0) atomicAdd(col + gz * planesz, static_cast<unsigned long long>(g));
+      }
+    }
+    return;
+  }
   for (int k0 = threadIdx.x; k0 < E12; k0 += blockDim.x) {
     const int y = k0 / E1, x = k0 - y * E1;
     int gx = o1 + x, gy = o2 + y;

@@ -40,7 +40,8 @@ class Opts(ctypes.Structure):
                 ("P", ctypes.c_int), ("M", ctypes.c_int * 3), ("grid_sigma", ctypes.c_double),
                 ("coulomb_k", ctypes.c_double), ("tile", ctypes.c_int), ("stream", ctypes.c_void_p),
                 ("window_tol", ctypes.c_double), ("gather", ctypes.c_int), ("force", ctypes.c_int),
-                ("local_virial", ctypes.c_int), ("fft_split", ctypes.c_int), ("spread_accum", ctypes.c_int)]
+                ("local_virial", ctypes.c_int), ("fft_split", ctypes.c_int), ("spread_accum", ctypes.c_int),
+                ("deterministic", ctypes.c_int)]
 
 
 class Params(ctypes.Structure):
@@ -55,7 +56,8 @@ class Params(ctypes.Structure):
                 ("gather_tiled", ctypes.c_int), ("counter_copies", ctypes.c_int), ("force", ctypes.c_int),
                 ("local_virial", ctypes.c_int), ("real_cells", ctypes.c_int * 3),
                 ("real_segments", ctypes.c_int), ("fft_split", ctypes.c_int), ("spread_fixed", ctypes.c_int),
-                ("hinv", ctypes.c_double * 9), ("gather_lane", ctypes.c_int)]
+                ("hinv", ctypes.c_double * 9), ("gather_lane", ctypes.c_int),
+                ("grid_fixed", ctypes.c_int)]
 
     def as_dict(self):
         out = {}
@@ -164,7 +166,7 @@ def _cell(h):
 def make_opts(precision="fp32", params="analytic", coupling="iso", rc=0.9, c_split=None,
               c_spread=None, P=None, M=None, grid_sigma=1.07, coulomb_k=1.0, tile=0, stream=None,
               window_tol=0.0, gather="auto", force="ad", local_virial=False, fft_split=False,
-              spread_accum="auto"):
+              spread_accum="auto", deterministic=False):
     o = Opts()
     lib().esp_opts_default(ctypes.byref(o))
     o.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
@@ -195,6 +197,7 @@ def make_opts(precision="fp32", params="analytic", coupling="iso", rc=0.9, c_spl
     o.local_virial = 1 if local_virial else 0
     o.fft_split = 1 if fft_split else 0
     o.spread_accum = SPREAD_ACCUM[spread_accum] if isinstance(spread_accum, str) else int(spread_accum)
+    o.deterministic = 1 if deterministic else 0
     return o
 
 
