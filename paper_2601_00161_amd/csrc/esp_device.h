@@ -75,6 +75,7 @@ struct DevPlan {
   int64_t n;
   int M1, M2, M3, H;               // grid; H = M1 / 2 + 1 half-spectrum columns
   int P, nw, nker;                 // window support, padded window degree (8/12/16), kernel degree
+                                   // padded to a multiple of 4
   int T1, T2, T3, nt1, nt2, nt3, ntiles;
   int cz;                          // columns per block in the z-pass
   int nbin;                        // blocks of the binning kernel
@@ -95,8 +96,8 @@ struct DevPlan {
   int spread_fixed;                // spreading tile in 64-bit fixed point (else FP64)
   // tables (device)
   const R* win;                    // (nw + 1) x P monomial coefficients in tau, coefficient-major
-  const R* kerf;                   // Chebyshev coefficients of psi(sqrt(y)), z = 2y - 1
-  const R* kerg;                   // Chebyshev coefficients of x psi'(x), x = sqrt(y)
+  const Cplx<R>* kerfg;            // (nker + 1) pairs of Chebyshev coefficients in z = 2y - 1:
+                                   // (psi(sqrt y), x psi'(x) at x = sqrt y), zero past the fit
   const R* iw1;                    // 1 / w_hat(2 pi m / M1)^2, DFT index order
   const R* iw2;
   const R* iw3;

@@ -626,15 +626,29 @@ __global__ void __launch_bounds__(256) k_fft_x_inv(DevPlan<R> d, int npb) {
 }
 
 // ------------------------------------------------------------------- FFT z
+// Both kernel series at z by Clenshaw's recurrence: c holds (f_k, g_k)
+// pairs, zero-padded to degree n (a multiple of 4), so the loop takes four
+// degrees per trip and the two recurrences run as independent chains (one
+// series at a time, in a loop of one degree per trip, spent most of the z
+// pass's VALU issue).
 template <typename R>
-__device__ __forceinline__ R chebyshev(const R* __restrict__ c, int deg, R z) {
-  R b1 = R(0), b2 = R(0);
-  for (int k = deg; k >= 1; --k) {
-    const R b0 = R(2) * z * b1 - b2 + c[k];
-    b2 = b1;
-    b1 = b0;
+__device__ __forceinline__ void clenshaw2(const Cplx<R>* __restrict__ c, int n, R z, R& f, R& g) {
+  const R z2 = z + z;
+  R b1 = R(0), b2 = R(0), e1 = R(0), e2 = R(0);
+  for (int k = n; k > 0; k -= 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const Cplx<R> ck = c[k - u];
+      const R b0 = z2 * b1 - b2 + ck.x;
+      const R e0 = z2 * e1 - e2 + ck.y;
+      b2 = b1;
+      b1 = b0;
+      e2 = e1;
+      e1 = e0;
+    }
   }
-  return z * b1 - b2 + c[0];
+  f = z * b1 - b2 + c[0].x;
+  g = z * e1 - e2 + c[0].y;
 }
 
 // Compensated accumulator: FP32 Kahan sums for the production path, plain
@@ -669,9 +683,8 @@ __global__ void __launch_bounds__(256) k_fft_z(KArg<R, BATCH> ka, int mode) {
   Cplx<R>* B = A + cz * M3;
   Cplx<R>* C = B + cz * M3;                                        // component buffer (Z_IK, Z_LOCAL)
   Cplx<R>* tw3 = C + (mode >= Z_IK ? cz * M3 : 0);
-  R* kf = reinterpret_cast<R*>(tw3 + M3);
-  R* kg = kf + d.nker + 1;
-  R* fw = kg + d.nker + 1;                                         // Z_LOCAL: F_hat / (2 V W_hat^2)
+  Cplx<R>* kc = tw3 + M3;                                          // kernel coefficient pairs
+  R* fw = reinterpret_cast<R*>(kc + d.nker + 1);                   // Z_LOCAL: F_hat / (2 V W_hat^2)
   R* bw = fw + (mode == Z_LOCAL ? cz * M3 : 0);                    //          beta / (2 V W_hat^2)
   const int nth = blockDim.x, tid = threadIdx.x;
   const size_t colstride = static_cast<size_t>(M2) * H;
@@ -689,7 +702,7 @@ __global__ void __launch_bounds__(256) k_fft_z(KArg<R, BATCH> ka, int mode) {
     cv[u] = col[z * colstride + c];
   }
   const Cplx<R> twv = d.tw[d.f3.tw + min(tid, M3 - 1)];
-  const R kfv = d.kerf[min(tid, d.nker)], kgv = d.kerg[min(tid, d.nker)];
+  const Cplx<R> kcv = d.kerfg[min(tid, d.nker)];
   // the 1 / W_hat^2 factors of the scaling, fetched with the column
   R iw1p[U], iw3p[U];
   const R iwy = d.iw2[y];
@@ -705,15 +718,9 @@ __global__ void __launch_bounds__(256) k_fft_z(KArg<R, BATCH> ka, int mode) {
   for (int u = 0; u < U; ++u)
     if (tid + u * nth < nc * M3) A[tid + u * nth] = cv[u];
   if (tid < M3) tw3[tid] = twv;
-  if (tid <= d.nker) {
-    kf[tid] = kfv;
-    kg[tid] = kgv;
-  }
+  if (tid <= d.nker) kc[tid] = kcv;
   for (int k = tid + nth; k < M3; k += nth) tw3[k] = d.tw[d.f3.tw + k];
-  for (int k = tid + nth; k <= d.nker; k += nth) {
-    kf[k] = d.kerf[k];
-    kg[k] = d.kerg[k];
-  }
+  for (int k = tid + nth; k <= d.nker; k += nth) kc[k] = d.kerfg[k];
   for (int k = tid + U * nth; k < nc * M3; k += nth) {
     int c;
     const int z = dnc.div(k, c);
@@ -748,8 +755,8 @@ __global__ void __launch_bounds__(256) k_fft_z(KArg<R, BATCH> ka, int mode) {
     R g = R(0), fl = R(0), bl = R(0);
     if (inside) {
       const R zc = R(2) * kk * d.ysc - R(1);
-      const R f = chebyshev(kf, d.nker, zc);
-      const R xg = chebyshev(kg, d.nker, zc);
+      R f, xg;
+      clenshaw2(kc, d.nker, zc, f, xg);
       const R ik = R(1) / kk;
       const R Fh = d.A * f * ik;
       const R beta = (d.A * xg * ik - R(2) * Fh) * ik;

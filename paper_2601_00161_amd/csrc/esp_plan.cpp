@@ -578,8 +578,12 @@ int fit_window(esp_plan_t* p, double eps, std::vector<double>& coef, int* fitted
   return cls;
 }
 
+// Chebyshev fits of the two kernel functions in z = 2y - 1, to 1e-13 psi(0)
+// for FP64 plans and to 1e-9 psi(0) for FP32 plans (far below FP32 rounding;
+// two to four degrees fewer).
 int fit_kernel(esp_plan_t* p, std::vector<double>& cf, std::vector<double>& cg) {
   const Pswf& ps = *p->split;
+  const double rel = p->r.precision == ESP_FP32 ? 1e-9 : 1e-13;
   auto f = [&](double z) {
     const double y = 0.5 * (z + 1.0);
     return ps.psi(std::sqrt(y));
@@ -604,7 +608,7 @@ int fit_kernel(esp_plan_t* p, std::vector<double>& cf, std::vector<double>& cg) 
       err = std::max(err, std::fabs(z * b1 - b2 + cf[0] - f(z)));
       err = std::max(err, std::fabs(z * c1 - c2 + cg[0] - g(z)));
     }
-    if (err <= 1e-13 * ps.psi0()) return deg;
+    if (err <= rel * ps.psi0()) return deg;
   }
   return kMaxKerDeg;
 }
@@ -713,7 +717,7 @@ esp_status build_device(esp_plan_t* p) {
   std::vector<double> cf, cg;
   p->nker = fit_kernel(p, cf, cg);
   d.nw = p->nw;
-  d.nker = p->nker;
+  d.nker = (p->nker + 3) / 4 * 4;
   std::vector<double> iw[3];
   const Pswf& sp = *p->spread;
   const double omega = 0.5 * r.P;
@@ -751,7 +755,12 @@ esp_status build_device(esp_plan_t* p) {
   while (2 * max_seg * 2 * (kRealDeg<R> + 1) * static_cast<int>(sizeof(R)) <= 40 * 1024) max_seg *= 2;
   p->nseg = fit_near(p, kRealDeg<R>, r.precision == ESP_FP32 ? 2e-8 : 1e-14, max_seg, near);
   d.nrs = p->nseg;
-  const size_t o_win = push(win), o_kf = push(cf), o_kg = push(cg);
+  std::vector<double> kfg(2 * static_cast<size_t>(d.nker + 1), 0.0);   // (f_k, g_k) pairs, zero past the fit
+  for (int k = 0; k <= p->nker; ++k) {
+    kfg[2 * k] = cf[k];
+    kfg[2 * k + 1] = cg[k];
+  }
+  const size_t o_win = push(win), o_kfg = push(kfg);
   const size_t o_i1 = push(iw[0]), o_i2 = push(iw[1]), o_i3 = push(iw[2]), o_near = push(near);
   R* dtab;
   Cplx<R>* dtw;
@@ -760,8 +769,7 @@ esp_status build_device(esp_plan_t* p) {
   if ((st = dalloc(p, &dtw, tw.size())) != ESP_OK) return st;
   hipError_t e = hipSuccess;
   d.win = dtab + o_win;
-  d.kerf = dtab + o_kf;
-  d.kerg = dtab + o_kg;
+  d.kerfg = reinterpret_cast<const Cplx<R>*>(dtab + o_kfg);   // offsets are multiples of 4 reals
   d.iw1 = dtab + o_i1;
   d.iw2 = dtab + o_i2;
   d.iw3 = dtab + o_i3;
