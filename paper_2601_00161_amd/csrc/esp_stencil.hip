@@ -632,15 +632,24 @@ __global__ void __launch_bounds__(256) k_gather_tile(KArg<R, BATCH> ka, R* __res
   // the offsets, the window table and the potential box are fetched in rounds
   // of U loads per thread, the first together with the offsets (clamped
   // indices: no branches)
-  constexpr int U = 4;
+  // box loads in flight per thread: 16 for large boxes (10^6 slab, 15^3: the
+  // staging is latency-bound, 66.4 -> 64.2 us), 4 for small ones (30k water,
+  // 9^3: deeper rounds cost 2 us there)
   BoxWalk walk(tid, nth, E1, E2);
+  const bool deep = nbox > 4 * nth;
+  auto stage_round = [&] {
+    if (deep)
+      stage_box_round<R, 16>(d, box, walk, nbox, o1, o2, o3, nth);
+    else
+      stage_box_round<R, 4>(d, box, walk, nbox, o1, o2, o3, nth);
+  };
   const int start = d.offsets[tile], end = d.offsets[tile + 1];
   const R wv = d.win[min(tid, (NW + 1) * P - 1)];
-  stage_box_round<R, U>(d, box, walk, nbox, o1, o2, o3, nth);
+  stage_round();
   if (start == end) return;
   if (tid < (NW + 1) * P) win[tid] = wv;
   for (int k = tid + nth; k < (NW + 1) * P; k += nth) win[k] = d.win[k];
-  while (walk.k < nbox) stage_box_round<R, U>(d, box, walk, nbox, o1, o2, o3, nth);
+  while (walk.k < nbox) stage_round();
   const int grp = tid / L, lane = tid - grp * L;
   R* my = wt + grp * 6 * P;
   for (int base = start; base < end; base += G) {
@@ -744,11 +753,20 @@ __global__ void __launch_bounds__(256) k_gather_lane(KArg<R, BATCH> ka, R* __res
   const int E3 = min(d.T3, d.M3 - o3) + P - 1;
   const int E12 = E1 * E2;
   const int nbox = E12 * E3;
-  constexpr int U = 4;
+  // box loads in flight per thread: 16 for large boxes (10^6 slab, 15^3: the
+  // staging is latency-bound, 66.4 -> 64.2 us), 4 for small ones (30k water,
+  // 9^3: deeper rounds cost 2 us there)
   BoxWalk walk(tid, nth, E1, E2);
+  const bool deep = nbox > 4 * nth;
+  auto stage_round = [&] {
+    if (deep)
+      stage_box_round<R, 16>(d, box, walk, nbox, o1, o2, o3, nth);
+    else
+      stage_box_round<R, 4>(d, box, walk, nbox, o1, o2, o3, nth);
+  };
   const int start = d.offsets[tile], end = d.offsets[tile + 1];
   const R wv = d.win[min(tid, (NW + 1) * P - 1)];
-  stage_box_round<R, U>(d, box, walk, nbox, o1, o2, o3, nth);
+  stage_round();
   if (start == end) return;
   // this thread's first particle, fetched while the box is staged
   int i = start + tid;
@@ -756,7 +774,7 @@ __global__ void __launch_bounds__(256) k_gather_lane(KArg<R, BATCH> ka, R* __res
   int64_t j = i < end ? d.perm[i] : 0;
   if (tid < (NW + 1) * P) win[tid] = wv;
   for (int k = tid + nth; k < (NW + 1) * P; k += nth) win[k] = d.win[k];
-  while (walk.k < nbox) stage_box_round<R, U>(d, box, walk, nbox, o1, o2, o3, nth);
+  while (walk.k < nbox) stage_round();
   __syncthreads();
   const R qk0 = d.coulomb_k;
   for (; i < end; i += nth) {
