@@ -17,38 +17,96 @@
 
 namespace espx {
 
-// Values of the P window polynomials at tau.  Coefficient-major table:
-// win[j * P + p] multiplies tau^j in polynomial p (the window on the stencil
-// point g0 + p, whose offset from the particle is tau + (P - 1)/2 - p).
+// Window polynomials.  Coefficient-major table: win[j * P + p] multiplies
+// tau^j in polynomial p (the window on the stencil point g0 + p, whose offset
+// from the particle is tau + (P - 1)/2 - p).  psi is even and the P points
+// lie symmetric about the particle, so polynomial P - 1 - q at tau is
+// polynomial q at -tau: writing c_q(tau) = E(u) + tau O(u), u = tau^2 (even
+// and odd coefficients), one evaluation of E and O gives both members of a
+// mirror pair, E(u) +- tau O(u), in half the FMAs of evaluating each
+// polynomial.  Only the tables of q < P/2 (and the middle one for odd P)
+// are read.  NW is even: E has NW/2 + 1 coefficients, O has NW/2.
+template <typename R, int NW>
+__device__ __forceinline__ void even_odd(const R* __restrict__ c, int stride, R u, R& e, R& o) {
+  static_assert(NW % 2 == 0, "even padded degree");
+  e = c[NW * stride];
+  o = c[(NW - 1) * stride];
+#pragma unroll
+  for (int j = NW - 2; j >= 0; j -= 2) {
+    e = e * u + c[j * stride];
+    if (j >= 2) o = o * u + c[(j - 1) * stride];
+  }
+}
+
+// ... and with the derivatives E'(u), O'(u)
+template <typename R, int NW>
+__device__ __forceinline__ void even_odd_d(const R* __restrict__ c, int stride, R u, R& e, R& de, R& o, R& dO) {
+  static_assert(NW % 2 == 0, "even padded degree");
+  e = c[NW * stride];
+  o = c[(NW - 1) * stride];
+  de = R(0);
+  dO = R(0);
+#pragma unroll
+  for (int j = NW - 2; j >= 0; j -= 2) {
+    de = de * u + e;
+    e = e * u + c[j * stride];
+    if (j >= 2) {
+      dO = dO * u + o;
+      o = o * u + c[(j - 1) * stride];
+    }
+  }
+}
+
+// Values of the P window polynomials at tau.
 template <typename R, int P, int NW>
 __device__ __forceinline__ void eval_window(const R* __restrict__ win, R tau, R* w) {
+  const R u = tau * tau;
 #pragma unroll
-  for (int p = 0; p < P; ++p) w[p] = win[NW * P + p];
-#pragma unroll
-  for (int j = NW - 1; j >= 0; --j)
-#pragma unroll
-    for (int p = 0; p < P; ++p) w[p] = w[p] * tau + win[j * P + p];
+  for (int q = 0; q < (P + 1) / 2; ++q) {
+    R e, o;
+    even_odd<R, NW>(win + q, P, u, e, o);
+    const R to = tau * o;
+    w[q] = e + to;
+    if (P - 1 - q != q) w[P - 1 - q] = e - to;
+  }
+}
+
+// Values and tau-derivatives: d/dtau [E(u) +- tau O(u)] = 2 tau E'(u) +-
+// (O(u) + 2 u O'(u)).
+template <typename R, int P, int NW>
+__device__ __forceinline__ void window_pair_d(const R* __restrict__ win, int q, R tau, R& w, R& dw, R& wm, R& dwm) {
+  const R u = tau * tau;
+  R e, de, o, dO;
+  even_odd_d<R, NW>(win + q, P, u, e, de, o, dO);
+  const R to = tau * o;
+  const R a = R(2) * tau * de, b = o + R(2) * u * dO;
+  w = e + to;
+  dw = a + b;
+  wm = e - to;
+  dwm = a - b;
 }
 
 // The 3 P window values and derivatives of one particle, shared out over its
-// L lanes (polynomial k = lane, lane + L, ...: dimension k / P, point k % P),
-// stored as my[2 d P + p] (value) and my[(2 d + 1) P + p] (derivative).
+// L lanes (mirror pair k = lane, lane + L, ...: dimension k / H, pair k % H,
+// H = (P + 1) / 2), stored as my[2 d P + p] (value) and my[(2 d + 1) P + p]
+// (derivative).
 template <typename R, int P, int NW, int L>
 __device__ __forceinline__ void window_d_lanes(const R* __restrict__ win, R t1, R t2, R t3, int lane, R* my) {
+  constexpr int H = (P + 1) / 2;
 #pragma unroll
-  for (int r = 0; r < (3 * P + L - 1) / L; ++r) {
+  for (int r = 0; r < (3 * H + L - 1) / L; ++r) {
     const int k = lane + r * L;
-    if (k < 3 * P) {
-      const int dim = k / P, p = k - dim * P;
+    if (k < 3 * H) {
+      const int dim = k / H, q = k - dim * H;
       const R tau = dim == 0 ? t1 : (dim == 1 ? t2 : t3);
-      R v = win[NW * P + p], dv = R(0);
-#pragma unroll
-      for (int j = NW - 1; j >= 0; --j) {
-        dv = dv * tau + v;
-        v = v * tau + win[j * P + p];
+      R v, dv, vm, dvm;
+      window_pair_d<R, P, NW>(win, q, tau, v, dv, vm, dvm);
+      my[2 * dim * P + q] = v;
+      my[(2 * dim + 1) * P + q] = dv;
+      if (P - 1 - q != q) {
+        my[2 * dim * P + P - 1 - q] = vm;
+        my[(2 * dim + 1) * P + P - 1 - q] = dvm;
       }
-      my[2 * dim * P + p] = v;
-      my[(2 * dim + 1) * P + p] = dv;
     }
   }
 }
@@ -719,17 +777,16 @@ __global__ void __launch_bounds__(256) k_gather_tile(KArg<R, BATCH> ka, R* __res
 template <typename R, int P, int NW>
 __device__ __forceinline__ void eval_window_d(const R* __restrict__ win, R tau, R* w, R* dw) {
 #pragma unroll
-  for (int p = 0; p < P; ++p) {
-    w[p] = win[NW * P + p];
-    dw[p] = R(0);
-  }
-#pragma unroll
-  for (int j = NW - 1; j >= 0; --j)
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-      dw[p] = dw[p] * tau + w[p];
-      w[p] = w[p] * tau + win[j * P + p];
+  for (int q = 0; q < (P + 1) / 2; ++q) {
+    R v, dv, vm, dvm;
+    window_pair_d<R, P, NW>(win, q, tau, v, dv, vm, dvm);
+    w[q] = v;
+    dw[q] = dv;
+    if (P - 1 - q != q) {
+      w[P - 1 - q] = vm;
+      dw[P - 1 - q] = dvm;
     }
+  }
 }
 
 template <typename R, int P, int NW, bool BATCH>
