@@ -196,6 +196,7 @@ struct BatchLaunch {
   int P, nw;
   int ppt;                         // binning stage: largest particles per thread of its plans
   int grid_fixed;                  // xy stage: the plans keep int64 grids (deterministic FP32)
+  int lane;                        // gather stage: tile-staged, one particle per lane
 };
 
 // Per-stage kernel timing.  While the host plan times a stage it sets the two

@@ -1592,6 +1592,7 @@ struct BatchStage {
   int P = 0, nw = 0;
   int ppt = 1;            // binning stage: largest binppt of its replicas
   int grid_fixed = 0;     // xy stage: the replicas keep int64 grids
+  int lane = 0;           // gather stage: tile-staged, one particle per lane
 };
 
 struct esp_batch_s {
@@ -1698,14 +1699,29 @@ esp_status batch_build(esp_batch_t* b) {
   for (const DevPlan<R>& d : hp) b->any_sub = b->any_sub || d.nsub > 1;
   b->spread.clear();
   b->gather.clear();
+  int dev_id = 0, maxlds = 65536;
+  if (hipGetDevice(&dev_id) == hipSuccess)
+    (void)hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev_id);
   for (int k = 0; k < nrep;) {
     int e = k + 1;
     while (e < nrep && hp[e].P == hp[k].P && hp[e].nw == hp[k].nw) ++e;
     BatchStage sp, ga;
     make(sp, k, e - k, [](const DevPlan<R>& d) { return d.ntiles; },
          [](const DevPlan<R>& d) { return lds_spread(d); }, 256);
-    const int G = 256 / gather_lanes(hp[k].P);
-    make(ga, k, e - k, [G](const DevPlan<R>& d) { return static_cast<int>((d.n + G - 1) / G); }, zero, 256);
+    // gather: tile-staged with one particle per lane (one workgroup per tile)
+    // where every replica's potential box fits in LDS, else per particle
+    auto lane_lds = [](const DevPlan<R>& d) {
+      return static_cast<size_t>(((d.nw + 1) * d.P + 3) / 4 * 4) * sizeof(R) + lds_gather_box(d);
+    };
+    bool lane = true;
+    for (int j = k; j < e; ++j) lane = lane && lane_lds(hp[j]) <= static_cast<size_t>(maxlds);
+    if (lane) {
+      make(ga, k, e - k, [](const DevPlan<R>& d) { return d.ntiles; }, lane_lds, 256);
+      ga.lane = 1;
+    } else {
+      const int G = 256 / gather_lanes(hp[k].P);
+      make(ga, k, e - k, [G](const DevPlan<R>& d) { return static_cast<int>((d.n + G - 1) / G); }, zero, 256);
+    }
     b->spread.push_back(sp);
     b->gather.push_back(ga);
     k = e;
@@ -1734,7 +1750,7 @@ esp_status batch_build(esp_batch_t* b) {
 template <typename R>
 BatchLaunch<R> batch_launch(const esp_batch_t* b, const BatchStage& st) {
   return BatchLaunch<R>{static_cast<const DevPlan<R>*>(b->dplans) + st.first, st.boff, st.count, st.nblk, st.nth,
-                        st.lds, st.P, st.nw, st.ppt, st.grid_fixed};
+                        st.lds, st.P, st.nw, st.ppt, st.grid_fixed, st.lane};
 }
 
 template <typename R>

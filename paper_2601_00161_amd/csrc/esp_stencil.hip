@@ -944,6 +944,15 @@ static hipError_t spread_nw_batch(const BatchLaunch<R>& b, hipStream_t s) {
 
 template <typename R, int P, int NW>
 static hipError_t gather_nw_batch(const BatchLaunch<R>& b, R* f, double* out7, hipStream_t s) {
+  if (b.lane) {
+    // tile-staged, one particle per lane: one workgroup per tile of every replica
+    if (b.lds > 65536)
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather_lane<R, P, NW, true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(b.lds));
+    ESP_LAUNCH((k_gather_lane<R, P, NW, true>), dim3(b.nblk), dim3(256), b.lds, s,
+               KArg<R, true>{b.plans, b.boff, b.nrep}, f, out7);
+    return hipGetLastError();
+  }
   ESP_LAUNCH((k_gather<R, P, NW, true>), dim3(b.nblk), dim3(256), (gather_lds<R, P, NW>()), s,
                      KArg<R, true>{b.plans, b.boff, b.nrep}, f, out7);
   return hipGetLastError();
