@@ -171,6 +171,26 @@ __device__ __forceinline__ void stage_box_round(const DevPlan<R>& d, R* __restri
 }
 
 // ----------------------------------------------------------------- spread
+// Particles a spreading wave stages at a time, at most kWaveChunk (one weight
+// task per (particle, dimension) lane): the size whose (particle, z offset)
+// tasks fill the 64-lane accumulation passes best, i.e. the most particles per
+// pass, c / ceil(c P / 64), the larger c on a tie (P = 6: 21, two passes of
+// 63 tasks; P = 4: 16, one full pass, where 21 left a second pass of 20
+// lanes; P = 5: 12; P = 7: 18; P = 8: 16).
+constexpr int spread_chunk(int P) {
+  int best = 1, num = 1, den = 1;                  // best particles per pass as num / den
+  for (int c = 1; c <= kWaveChunk; ++c) {
+    const int passes = (c * P + 63) / 64;
+    if (c * den >= num * passes) {
+      best = c;
+      num = c;
+      den = passes;
+    }
+  }
+  return best;
+}
+static_assert(spread_chunk(6) == 21 && spread_chunk(4) == 16 && spread_chunk(7) == 18, "chunk sizes");
+
 // One workgroup per tile of T1 x T2 x T3 grid cells.  Its particles (those
 // whose stencil base lies in the tile, contiguous after the cell sort) are
 // spread into an LDS copy of the tile plus its (P - 1)-wide upper halo, which
@@ -237,7 +257,7 @@ __global__ void __launch_bounds__(256) k_spread(KArg<R, BATCH> ka) {
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
   const int lane = threadIdx.x & 63;
   const int n = end - start;
-  const int csz = __builtin_amdgcn_readfirstlane(max(1, min(kWaveChunk, (n + kSpreadWaves - 1) / kSpreadWaves)));
+  const int csz = __builtin_amdgcn_readfirstlane(max(1, min(spread_chunk(P), (n + kSpreadWaves - 1) / kSpreadWaves)));
   const int step = kSpreadWaves * csz;
   R* wts_w = wts + wave * kWaveChunk * 3 * P;
   int* base_w = base + wave * kWaveChunk * 3;
