@@ -32,6 +32,7 @@ def _same(a, b):
 @pytest.mark.parametrize("n_mol, L, tol, opts", [
     (3000, 4.5, 1e-5, dict()),                       # one counter per tile
     (3000, 4.5, 1e-5, dict(coupling="flex", gather="particle")),
+    (3000, 4.5, 1e-5, dict(fft_split=True)),         # split x / y passes read the int64 grid
     (100000, 10.0, 1e-3, dict(tile=4)),              # counter copies (nsub > 1)
 ])
 def test_repeated_calls_return_identical_bits(n_mol, L, tol, opts):
