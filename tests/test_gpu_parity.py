@@ -7,7 +7,7 @@ FP64) inputs converted exactly to FP64 and the same explicit parameters.
 import numpy as np
 import pytest
 
-from gpu_util import BARS, as_inputs, oracle, paper_params, parity_vs_oracle, rel_rms, ties_of
+from gpu_util import BARS, as_inputs, oracle, paper_params, parity, parity_vs_oracle, rel_rms, ties_of
 from paper_2601_00161_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -160,6 +160,43 @@ def test_sort_keys_bit_exact(case, precision, dev):
     got[perm] = tile_of_pos
     assert np.array_equal(got, key), f"{int(np.sum(got != key))} particles in a different tile than the host's"
     plan.close()
+
+
+@pytest.mark.parametrize("tile, lds", [(4, 1), (3, 0)], ids=["5832_tiles_lds_histogram", "13824_tiles_global_counters"])
+def test_sort_keys_bit_exact_many_tiles(tile, lds, dev):
+    """A1 with thousands of tiles: binning workgroups take 1,024 particles
+    (4 per thread) and reserve their tile ranges with one global atomic per
+    occupied tile (LDS histogram), or, beyond 8,192 tiles, count straight into
+    global counters; keys and offsets still match the host bit for bit, and
+    the forces match a plan with the default tiles."""
+    h, r, q = synth.water(60000, synth.cubic(12.2), config=1, seed=17)
+    r_, q_, r64, q64 = as_inputs(r, q, "fp32")
+    from paper_2601_00161_amd.esp import Plan
+    plan = Plan(h, len(q), 1e-5, tile=tile)
+    prm = plan.params
+    print(f"many-tiles sort: n={len(q)} M={prm['M']} tile={prm['tile']} ntiles={prm['ntiles']}", flush=True)
+    assert prm["ntiles"] >= 2048 and (prm["ntiles"] <= 8192) == bool(lds)
+    x, c = to_dev(r_, dev), to_dev(q_, dev)
+    perm, off = plan.stage_sort(x, c)
+    perm, off = perm.cpu().numpy(), off.cpu().numpy()
+    n = len(q)
+    assert np.array_equal(np.sort(perm), np.arange(n))
+    key = host_tile_keys(np.array(prm["hinv"]), r_, prm["M"], prm["P"], prm["tile"], "fp32")
+    counts = np.bincount(key, minlength=prm["ntiles"])
+    assert np.array_equal(off, np.concatenate([[0], np.cumsum(counts)]))
+    tile_of_pos = np.searchsorted(off, np.arange(n), side="right") - 1
+    got = np.empty(n, dtype=np.int64)
+    got[perm] = tile_of_pos
+    assert np.array_equal(got, key)
+    f1, o1 = plan.forces(x, c)
+    ref = Plan(h, n, 1e-5)
+    f0, o0 = ref.forces(x, c)
+    torch.cuda.synchronize()
+    plan.check()
+    parity(f"many_tiles_T{tile}", o1.cpu().numpy(), o0[0].item(), o0[1:].cpu().numpy(),
+           f1.double().cpu().numpy(), f0.double().cpu().numpy(), "fp32")
+    plan.close()
+    ref.close()
 
 
 def test_spread_accumulator_rule(dev):
