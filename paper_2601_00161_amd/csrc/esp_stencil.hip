@@ -150,8 +150,8 @@ struct BoxWalk {
 // stages only the first round, so that a kernel can put other loads behind
 // it; `w` keeps the position for the remaining rounds.
 template <typename R, int U>
-__device__ __forceinline__ void stage_box_round(const DevPlan<R>& d, R* __restrict__ box, BoxWalk& w, int nbox,
-                                                int o1, int o2, int o3, int nth) {
+__device__ __forceinline__ void stage_box_round(const DevPlan<R>& d, const R* __restrict__ src, R* __restrict__ box,
+                                                BoxWalk& w, int nbox, int o1, int o2, int o3, int nth) {
   R v[U];
   int kk[U];
 #pragma unroll
@@ -162,7 +162,7 @@ __device__ __forceinline__ void stage_box_round(const DevPlan<R>& d, R* __restri
     gy -= gy >= d.M2 ? d.M2 : 0;
     gz -= gz >= d.M3 ? d.M3 : 0;
     kk[u] = w.k;
-    v[u] = d.phi[(static_cast<size_t>(gz) * d.M2 + gy) * d.M1 + gx];
+    v[u] = src[(static_cast<size_t>(gz) * d.M2 + gy) * d.M1 + gx];
     w.step(nth);
   }
 #pragma unroll
@@ -679,6 +679,95 @@ __global__ void __launch_bounds__(256) k_gather_local(KArg<R, BATCH> ka, R* __re
   }
 }
 
+// Tile-staged gathers of NC plain-window components, one particle per lane:
+// NC = 3, the ik field (App. C, eq. rhodiagforce), f_j = -q_j sum_g W E_c(g);
+// NC = 6, the per-particle virial (Sec. 4.4, eq. PinsFind), w6_j = q_j sum_g
+// W Pi_c(g).  One workgroup per tile stages the tile's box of every component
+// grid (component c at phi + c M1 M2 M3) in LDS, then each lane evaluates its
+// particle's 3 P window values and sums the NC components over its P^3
+// stencil.  The per-particle kernels read the NC grids from L2 at random
+// (10^6 slab: 1.4 ms for the ik gather, 2.4 ms for the virial gather).
+template <typename R, int P, int NW, int NC, bool BATCH>
+__global__ void __launch_bounds__(256) k_gather_comp_lane(KArg<R, BATCH> ka, R* __restrict__ out,
+                                                          double* __restrict__ out7) {
+  static_assert(NC == 3 || NC == 6, "ik field or virial components");
+  int tile;
+  const DevPlan<R>& d = plan_of(ka, tile);
+  out += NC * d.pofs;
+  if (out7 && tile == 0) {
+    __shared__ double red[kNumSums * 16];
+    finalize_sums(d, out7 + kNumSums * d.rep, red);
+  }
+  extern __shared__ __align__(16) unsigned char smem[];
+  R* win = reinterpret_cast<R*>(smem);                // (NW + 1) x P
+  R* box = win + ((NW + 1) * P + 3) / 4 * 4;          // NC x E1 x E2 x E3 component values
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int t1 = tile % d.nt1, t2 = (tile / d.nt1) % d.nt2, t3 = tile / (d.nt1 * d.nt2);
+  const int o1 = t1 * d.T1, o2 = t2 * d.T2, o3 = t3 * d.T3;
+  const int E1 = min(d.T1, d.M1 - o1) + P - 1;
+  const int E2 = min(d.T2, d.M2 - o2) + P - 1;
+  const int E3 = min(d.T3, d.M3 - o3) + P - 1;
+  const int E12 = E1 * E2;
+  const int nbox = E12 * E3;
+  const int start = d.offsets[tile], end = d.offsets[tile + 1];
+  if (start == end) return;
+  const size_t G3 = static_cast<size_t>(d.M1) * d.M2 * d.M3;
+  const bool deep = nbox > 4 * nth;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    BoxWalk walk(tid, nth, E1, E2);
+    while (walk.k < nbox) {
+      if (deep)
+        stage_box_round<R, 16>(d, d.phi + c * G3, box + c * nbox, walk, nbox, o1, o2, o3, nth);
+      else
+        stage_box_round<R, 4>(d, d.phi + c * G3, box + c * nbox, walk, nbox, o1, o2, o3, nth);
+    }
+  }
+  for (int k = tid; k < (NW + 1) * P; k += nth) win[k] = d.win[k];
+  __syncthreads();
+  const R qk0 = NC == 3 ? -d.coulomb_k : d.coulomb_k;
+  for (int i = start + tid; i < end; i += nth) {
+    const Record<R> rec = d.sorted[i];
+    const int64_t j = d.perm[i];
+    int g1, g2, g3;
+    R u1, u2, u3;
+    Coord<R>::stencil(rec, 0, d.M1, P, g1, u1);
+    Coord<R>::stencil(rec, 1, d.M2, P, g2, u2);
+    Coord<R>::stencil(rec, 2, d.M3, P, g3, u3);
+    R w1[P], w2[P], w3[P];
+    eval_window<R, P, NW>(win, u1, w1);
+    eval_window<R, P, NW>(win, u2, w2);
+    eval_window<R, P, NW>(win, u3, w3);
+    // the base lies in this tile: box-local base = g0 - o (no wrap)
+    const R* p0 = box + (g3 - o3) * E12 + (g2 - o2) * E1 + (g1 - o1);
+    R acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = R(0);
+#pragma unroll
+    for (int cz = 0; cz < P; ++cz) {
+      R accz[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) accz[c] = R(0);
+#pragma unroll
+      for (int b = 0; b < P; ++b) {
+        const R* row = p0 + cz * E12 + b * E1;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          R s = R(0);
+#pragma unroll
+          for (int a = 0; a < P; ++a) s += row[c * nbox + a] * w1[a];
+          accz[c] += s * w2[b];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) acc[c] += accz[c] * w3[cz];
+    }
+    const R qk = rec.q * qk0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) out[NC * j + c] = qk * acc[c];
+  }
+}
+
 // Tile-staged gather, for dense tiles: one workgroup per tile.  The
 // potential on the tile's stencil box (its cells plus P - 1 more along each
 // cell vector, cyclically) is staged in LDS once, then the tile's particles
@@ -717,9 +806,9 @@ __global__ void __launch_bounds__(256) k_gather_tile(KArg<R, BATCH> ka, R* __res
   const bool deep = nbox > 4 * nth;
   auto stage_round = [&] {
     if (deep)
-      stage_box_round<R, 16>(d, box, walk, nbox, o1, o2, o3, nth);
+      stage_box_round<R, 16>(d, d.phi, box, walk, nbox, o1, o2, o3, nth);
     else
-      stage_box_round<R, 4>(d, box, walk, nbox, o1, o2, o3, nth);
+      stage_box_round<R, 4>(d, d.phi, box, walk, nbox, o1, o2, o3, nth);
   };
   const int start = d.offsets[tile], end = d.offsets[tile + 1];
   const R wv = d.win[min(tid, (NW + 1) * P - 1)];
@@ -837,9 +926,9 @@ __global__ void __launch_bounds__(256) k_gather_lane(KArg<R, BATCH> ka, R* __res
   const bool deep = nbox > 4 * nth;
   auto stage_round = [&] {
     if (deep)
-      stage_box_round<R, 16>(d, box, walk, nbox, o1, o2, o3, nth);
+      stage_box_round<R, 16>(d, d.phi, box, walk, nbox, o1, o2, o3, nth);
     else
-      stage_box_round<R, 4>(d, box, walk, nbox, o1, o2, o3, nth);
+      stage_box_round<R, 4>(d, d.phi, box, walk, nbox, o1, o2, o3, nth);
   };
   const int start = d.offsets[tile], end = d.offsets[tile + 1];
   const R wv = d.win[min(tid, (NW + 1) * P - 1)];
@@ -998,6 +1087,15 @@ hipError_t gather_launch(const DevPlan<R>& d, R* f, double* out7, hipStream_t s)
 
 template <typename R, int P, int NW>
 static hipError_t gather_ik_nw(const DevPlan<R>& d, R* f, double* out7, hipStream_t s) {
+  if (d.comp_lane & 1) {
+    const size_t lds = ((NW + 1) * P + 3) / 4 * 4 * sizeof(R) + 3 * lds_gather_box(d);
+    if (lds > 65536)
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather_comp_lane<R, P, NW, 3, false>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    ESP_LAUNCH((k_gather_comp_lane<R, P, NW, 3, false>), dim3(d.ntiles), dim3(256), lds, s, KArg<R, false>{d},
+               f, out7);
+    return hipGetLastError();
+  }
   constexpr int G = 256 / GatherLanes<P>::L;
   const int nb = static_cast<int>((d.n + G - 1) / G);
   const size_t lds = ((NW + 1) * P + G * 3 * P) * sizeof(R);
@@ -1012,6 +1110,15 @@ hipError_t gather_ik_launch(const DevPlan<R>& d, R* f, double* out7, hipStream_t
 
 template <typename R, int P, int NW>
 static hipError_t gather_local_nw(const DevPlan<R>& d, R* w6, double* out7, hipStream_t s) {
+  if (d.comp_lane & 2) {
+    const size_t lds = ((NW + 1) * P + 3) / 4 * 4 * sizeof(R) + 6 * lds_gather_box(d);
+    if (lds > 65536)
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather_comp_lane<R, P, NW, 6, false>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    ESP_LAUNCH((k_gather_comp_lane<R, P, NW, 6, false>), dim3(d.ntiles), dim3(256), lds, s, KArg<R, false>{d},
+               w6, out7);
+    return hipGetLastError();
+  }
   constexpr int G = 256 / GatherLanes<P>::L;
   const int nb = static_cast<int>((d.n + G - 1) / G);
   const size_t lds = ((NW + 1) * P + G * 3 * P) * sizeof(R);
