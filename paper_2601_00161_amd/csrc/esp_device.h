@@ -25,6 +25,7 @@ constexpr int kSpreadWaves = 4;   // waves of a spreading workgroup (256 threads
 constexpr int kWaveChunk = 21;    // particles a spreading wave stages at a time (3 weight tasks each)
 constexpr int kSpreadFixedMin = 128;  // automatic fixed-point spreading of FP64 plans: mean particles
 constexpr int kSpreadFixedMinTiles = 512;  // per tile, and tiles (two per CU), at least
+constexpr size_t kCompLaneOneLaunch = 48 * 1024;  // virial gather: six boxes in one launch up to this LDS
 constexpr int kCompLaneMin = 8;      // mean particles per tile from which the ik / virial gathers stage boxes
 constexpr int kTiledGatherMin = 96;  // mean particles per tile above which the gather is tile-staged
 constexpr int kBinContention = 64;   // target same-address atomics per tile counter in binning
@@ -124,7 +125,7 @@ struct DevPlan {
   int bin_lds;                     // tile histogram of the binning pass fits in LDS
   int gather_tiled;                // gather stages each tile's potential box in LDS
   int gather_lane;                 // tile-staged gather with one particle per lane
-  int comp_lane;                   // bit 0 / 1: the ik / virial gathers stage their 3 / 6 component
+  int comp_lane;                   // bit 0 / 1: the ik / virial gathers stage three component
                                    // boxes per tile (one particle per lane)
   int ik;                          // forces by ik-differentiation (3 field components)
   int local;                       // per-particle virial enabled (6 field components)

@@ -857,14 +857,14 @@ esp_status build_device(esp_plan_t* p) {
                           r.n >= static_cast<int64_t>(kTiledGatherMin) * r.ntiles;
   d.gather_lane = r.gather == ESP_GATHER_LANE || auto_tiled ? 1 : 0;
   d.gather_tiled = r.gather == ESP_GATHER_TILE || d.gather_lane ? 1 : 0;
-  // the ik and virial gathers stage their component boxes per tile once tiles
-  // hold kCompLaneMin+ particles on average and the boxes fit in LDS (their
-  // per-particle form reads 3 or 6 grids at random: 10^6 slab 1.4 / 2.4 ms)
+  // the ik and virial gathers stage three component boxes per tile once
+  // tiles hold kCompLaneMin+ particles on average and the boxes fit in LDS
+  // (their per-particle form reads 3 or 6 grids at random: 10^6 slab 1.4 /
+  // 2.4 ms); the virial takes two launches of three components
   d.comp_lane = 0;
-  if (r.gather != ESP_GATHER_PARTICLE && r.n >= static_cast<int64_t>(kCompLaneMin) * r.ntiles) {
-    if (lane_base + 3 * lds_gather_box(d) <= static_cast<size_t>(maxlds)) d.comp_lane |= 1;
-    if (lane_base + 6 * lds_gather_box(d) <= static_cast<size_t>(maxlds)) d.comp_lane |= 2;
-  }
+  if (r.gather != ESP_GATHER_PARTICLE && r.n >= static_cast<int64_t>(kCompLaneMin) * r.ntiles &&
+      lane_base + 3 * lds_gather_box(d) <= static_cast<size_t>(maxlds))
+    d.comp_lane = 3;
   // tables: uploaded once every buffer has its place, so that a plan that
   // does not fit its region fails before it writes any device memory; the
   // copies are ordered on the plan's stream after earlier work there (a

@@ -680,20 +680,23 @@ __global__ void __launch_bounds__(256) k_gather_local(KArg<R, BATCH> ka, R* __re
 }
 
 // Tile-staged gathers of NC plain-window components, one particle per lane:
-// NC = 3, the ik field (App. C, eq. rhodiagforce), f_j = -q_j sum_g W E_c(g);
-// NC = 6, the per-particle virial (Sec. 4.4, eq. PinsFind), w6_j = q_j sum_g
-// W Pi_c(g).  One workgroup per tile stages the tile's box of every component
-// grid (component c at phi + c M1 M2 M3) in LDS, then each lane evaluates its
-// particle's 3 P window values and sums the NC components over its P^3
-// stencil.  The per-particle kernels read the NC grids from L2 at random
+// components c0 .. c0 + NC - 1 of the field grids (component c at phi + c M1
+// M2 M3) go to out[stride j + c], scaled by sgn q_j.  The ik field (App. C,
+// eq. rhodiagforce) is one launch of three, f_j = -q_j sum_g W E_c(g); the
+// per-particle virial (Sec. 4.4, eq. PinsFind), w6_j = q_j sum_g W Pi_c(g), is
+// one launch of six for small boxes and two of three for large ones (three
+// boxes in LDS instead of six keep three workgroups per CU: 10^6 slab 694 ->
+// 342 us; at 30k the second launch costs more than it saves).  One workgroup
+// per tile stages the tile's component boxes, then each lane evaluates its
+// particle's 3 P window values and sums the components over its P^3 stencil.  The per-particle kernels read the grids from L2 at random
 // (10^6 slab: 1.4 ms for the ik gather, 2.4 ms for the virial gather).
 template <typename R, int P, int NW, int NC, bool BATCH>
 __global__ void __launch_bounds__(256) k_gather_comp_lane(KArg<R, BATCH> ka, R* __restrict__ out,
-                                                          double* __restrict__ out7) {
-  static_assert(NC == 3 || NC == 6, "ik field or virial components");
+                                                          double* __restrict__ out7, int c0, int stride, R sgn) {
+  static_assert(NC == 3 || NC == 6, "three or six components");
   int tile;
   const DevPlan<R>& d = plan_of(ka, tile);
-  out += NC * d.pofs;
+  out += static_cast<int64_t>(stride) * d.pofs;
   if (out7 && tile == 0) {
     __shared__ double red[kNumSums * 16];
     finalize_sums(d, out7 + kNumSums * d.rep, red);
@@ -715,17 +718,18 @@ __global__ void __launch_bounds__(256) k_gather_comp_lane(KArg<R, BATCH> ka, R* 
   const bool deep = nbox > 4 * nth;
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
+    const R* src = d.phi + (c0 + c) * G3;
     BoxWalk walk(tid, nth, E1, E2);
     while (walk.k < nbox) {
       if (deep)
-        stage_box_round<R, 16>(d, d.phi + c * G3, box + c * nbox, walk, nbox, o1, o2, o3, nth);
+        stage_box_round<R, 16>(d, src, box + c * nbox, walk, nbox, o1, o2, o3, nth);
       else
-        stage_box_round<R, 4>(d, d.phi + c * G3, box + c * nbox, walk, nbox, o1, o2, o3, nth);
+        stage_box_round<R, 4>(d, src, box + c * nbox, walk, nbox, o1, o2, o3, nth);
     }
   }
   for (int k = tid; k < (NW + 1) * P; k += nth) win[k] = d.win[k];
   __syncthreads();
-  const R qk0 = NC == 3 ? -d.coulomb_k : d.coulomb_k;
+  const R qk0 = sgn * d.coulomb_k;
   for (int i = start + tid; i < end; i += nth) {
     const Record<R> rec = d.sorted[i];
     const int64_t j = d.perm[i];
@@ -764,7 +768,7 @@ __global__ void __launch_bounds__(256) k_gather_comp_lane(KArg<R, BATCH> ka, R* 
     }
     const R qk = rec.q * qk0;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) out[NC * j + c] = qk * acc[c];
+    for (int c = 0; c < NC; ++c) out[static_cast<int64_t>(stride) * j + c0 + c] = qk * acc[c];
   }
 }
 
@@ -1093,7 +1097,7 @@ static hipError_t gather_ik_nw(const DevPlan<R>& d, R* f, double* out7, hipStrea
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather_comp_lane<R, P, NW, 3, false>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     ESP_LAUNCH((k_gather_comp_lane<R, P, NW, 3, false>), dim3(d.ntiles), dim3(256), lds, s, KArg<R, false>{d},
-               f, out7);
+               f, out7, 0, 3, R(-1));
     return hipGetLastError();
   }
   constexpr int G = 256 / GatherLanes<P>::L;
@@ -1111,12 +1115,22 @@ hipError_t gather_ik_launch(const DevPlan<R>& d, R* f, double* out7, hipStream_t
 template <typename R, int P, int NW>
 static hipError_t gather_local_nw(const DevPlan<R>& d, R* w6, double* out7, hipStream_t s) {
   if (d.comp_lane & 2) {
-    const size_t lds = ((NW + 1) * P + 3) / 4 * 4 * sizeof(R) + 6 * lds_gather_box(d);
-    if (lds > 65536)
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather_comp_lane<R, P, NW, 6, false>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-    ESP_LAUNCH((k_gather_comp_lane<R, P, NW, 6, false>), dim3(d.ntiles), dim3(256), lds, s, KArg<R, false>{d},
-               w6, out7);
+    const size_t base = ((NW + 1) * P + 3) / 4 * 4 * sizeof(R);
+    const size_t lds6 = base + 6 * lds_gather_box(d), lds3 = base + 3 * lds_gather_box(d);
+    if (lds6 <= kCompLaneOneLaunch) {
+      ESP_LAUNCH((k_gather_comp_lane<R, P, NW, 6, false>), dim3(d.ntiles), dim3(256), lds6, s,
+                 KArg<R, false>{d}, w6, out7, 0, 6, R(1));
+      return hipGetLastError();
+    }
+    if (lds3 > 65536)
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather_comp_lane<R, P, NW, 3, false>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds3));
+    ESP_LAUNCH((k_gather_comp_lane<R, P, NW, 3, false>), dim3(d.ntiles), dim3(256), lds3, s, KArg<R, false>{d},
+               w6, out7, 0, 6, R(1));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    ESP_LAUNCH((k_gather_comp_lane<R, P, NW, 3, false>), dim3(d.ntiles), dim3(256), lds3, s, KArg<R, false>{d},
+               w6, static_cast<double*>(nullptr), 3, 6, R(1));
     return hipGetLastError();
   }
   constexpr int G = 256 / GatherLanes<P>::L;
