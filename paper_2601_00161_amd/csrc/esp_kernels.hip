@@ -131,6 +131,7 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(KArg<R, BATCH> ka, const R*
     for (int k = threadIdx.x; k < d.ntiles; k += nth) hist[k] = 0;
   __syncthreads();
   double v[3] = {0.0, 0.0, 0.0};
+  const Divisor dT1(d.T1), dT2(d.T2), dT3(d.T3);   // exact for the grid indices (< 2^24)
   int key[PPT], lr[PPT];
 #pragma unroll
   for (int u = 0; u < PPT; ++u) {
@@ -156,7 +157,8 @@ __global__ void __launch_bounds__(kBinThreads) k_bin(KArg<R, BATCH> ka, const R*
         Coord<R>::stencil(rec, 0, d.M1, d.P, g1, t);
         Coord<R>::stencil(rec, 1, d.M2, d.P, g2, t);
         Coord<R>::stencil(rec, 2, d.M3, d.P, g3, t);
-        k = ((g3 / d.T3) * d.nt2 + g2 / d.T2) * d.nt1 + g1 / d.T1;
+        int rm;
+        k = (dT3.div(g3, rm) * d.nt2 + dT2.div(g2, rm)) * d.nt1 + dT1.div(g1, rm);
       }
       key[u] = k;
       lr[u] = lh ? atomicAdd(hist + k, 1)
