@@ -214,8 +214,8 @@ __device__ void fft_stage(const Cplx<R>* __restrict__ in, Cplx<R>* __restrict__ 
 
 // All stages; ping-pongs between a and b and returns the buffer holding the result.
 template <typename R>
-__device__ Cplx<R>* fft_lines(Cplx<R>* a, Cplx<R>* b, const FftLen& f, int nlines, int lstride,
-                              int estride, const Cplx<R>* tw, bool inverse, int nth) {
+__device__ __forceinline__ Cplx<R>* fft_lines(Cplx<R>* a, Cplx<R>* b, const FftLen& f, int nlines, int lstride,
+                                              int estride, const Cplx<R>* tw, bool inverse, int nth) {
   const R sgn = inverse ? R(1) : R(-1);
   int Ns = 1;
   Cplx<R>* in = a;
@@ -526,6 +526,17 @@ __device__ __forceinline__ int xcd_block(int i, int n) {
   return round * X * C + (k % X) * C + k / X;
 }
 
+// Batched launches read their plans from a device array that is written only
+// between kernels, so a kernel may read it through the constant address
+// space: uniform field reads then become scalar loads hoisted past the
+// kernel's stores, as for kernel arguments.  (The integer round trip keeps
+// the compiler from folding the two address-space casts away.)
+template <typename R>
+__device__ __forceinline__ const DevPlan<R>& plan_at(const DevPlan<R>* p) {
+  using CP = const __attribute__((address_space(4))) DevPlan<R>*;
+  return *(const DevPlan<R>*)(CP)reinterpret_cast<uintptr_t>(p);
+}
+
 template <typename R>
 __device__ __forceinline__ const DevPlan<R>& plan_of(const KArg<R, false>& a, int& blk) {
   blk = xcd_block(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
@@ -540,7 +551,7 @@ __device__ __forceinline__ const DevPlan<R>& plan_of(const KArg<R, true>& a, int
     if (a.boff[mid] <= b) lo = mid; else hi = mid;
   }
   blk = b - a.boff[lo];
-  return a.plans[lo];
+  return plan_at(a.plans + lo);
 }
 
 // Spreading and gather launchers for one window support P (one translation
