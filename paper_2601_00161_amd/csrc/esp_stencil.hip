@@ -119,7 +119,14 @@ __device__ __forceinline__ void window_d_lanes(const R* __restrict__ win, R t1, 
 struct BoxWalk {
   int k, x, y, z;
   int dx, dy, dz, E1, E2;
-  __device__ BoxWalk(int k0, int nth, int e1, int e2) : k(k0), E1(e1), E2(e2) {
+  // offset of (x, y, z) from the box origin in the grid, for boxes that do
+  // not wrap around the periodic grid: advanced with the walk, so that such
+  // a box is staged without per-element wrap tests or index products
+  int off, doff, rowfix, planefix;
+  bool wrap;                     // the box crosses the grid's upper edge in some dimension
+  size_t base;                   // grid index of the box origin
+  __device__ BoxWalk(int k0, int nth, int e1, int e2, int e3, int o1, int o2, int o3, int m1, int m2, int m3)
+      : k(k0), E1(e1), E2(e2) {
     const int e12 = e1 * e2;
     z = k0 / e12;
     y = (k0 - z * e12) / e1;
@@ -127,19 +134,29 @@ struct BoxWalk {
     dz = nth / e12;
     dy = (nth - dz * e12) / e1;
     dx = nth - dz * e12 - dy * e1;
+    const int m12 = m1 * m2;
+    off = z * m12 + y * m1 + x;
+    doff = dz * m12 + dy * m1 + dx;
+    rowfix = m1 - e1;
+    planefix = m12 - e2 * m1;
+    wrap = o1 + e1 > m1 || o2 + e2 > m2 || o3 + e3 > m3;
+    base = (static_cast<size_t>(o3) * m2 + o2) * m1 + o1;
   }
   __device__ __forceinline__ void step(int nth) {
     k += nth;
     x += dx;
     y += dy;
     z += dz;
+    off += doff;
     if (x >= E1) {
       x -= E1;
       ++y;
+      off += rowfix;
     }
     if (y >= E2) {
       y -= E2;
       ++z;
+      off += planefix;
     }
   }
 };
@@ -154,16 +171,26 @@ __device__ __forceinline__ void stage_box_round(const DevPlan<R>& d, const R* __
                                                 BoxWalk& w, int nbox, int o1, int o2, int o3, int nth) {
   R v[U];
   int kk[U];
+  if (!w.wrap) {
+    const R* s0 = src + w.base;
 #pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const bool in = w.k < nbox;
-    int gx = o1 + (in ? w.x : 0), gy = o2 + (in ? w.y : 0), gz = o3 + (in ? w.z : 0);
-    gx -= gx >= d.M1 ? d.M1 : 0;
-    gy -= gy >= d.M2 ? d.M2 : 0;
-    gz -= gz >= d.M3 ? d.M3 : 0;
-    kk[u] = w.k;
-    v[u] = src[(static_cast<size_t>(gz) * d.M2 + gy) * d.M1 + gx];
-    w.step(nth);
+    for (int u = 0; u < U; ++u) {
+      kk[u] = w.k;
+      v[u] = s0[w.k < nbox ? w.off : 0];
+      w.step(nth);
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool in = w.k < nbox;
+      int gx = o1 + (in ? w.x : 0), gy = o2 + (in ? w.y : 0), gz = o3 + (in ? w.z : 0);
+      gx -= gx >= d.M1 ? d.M1 : 0;
+      gy -= gy >= d.M2 ? d.M2 : 0;
+      gz -= gz >= d.M3 ? d.M3 : 0;
+      kk[u] = w.k;
+      v[u] = src[(static_cast<size_t>(gz) * d.M2 + gy) * d.M1 + gx];
+      w.step(nth);
+    }
   }
 #pragma unroll
   for (int u = 0; u < U; ++u)
@@ -719,7 +746,7 @@ __global__ void __launch_bounds__(256) k_gather_comp_lane(KArg<R, BATCH> ka, R* 
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     const R* src = d.phi + (c0 + c) * G3;
-    BoxWalk walk(tid, nth, E1, E2);
+    BoxWalk walk(tid, nth, E1, E2, E3, o1, o2, o3, d.M1, d.M2, d.M3);
     while (walk.k < nbox) {
       if (deep)
         stage_box_round<R, 16>(d, src, box + c * nbox, walk, nbox, o1, o2, o3, nth);
@@ -806,7 +833,7 @@ __global__ void __launch_bounds__(256) k_gather_tile(KArg<R, BATCH> ka, R* __res
   // box loads in flight per thread: 16 for large boxes (10^6 slab, 15^3: the
   // staging is latency-bound, 66.4 -> 64.2 us), 4 for small ones (30k water,
   // 9^3: deeper rounds cost 2 us there)
-  BoxWalk walk(tid, nth, E1, E2);
+  BoxWalk walk(tid, nth, E1, E2, E3, o1, o2, o3, d.M1, d.M2, d.M3);
   const bool deep = nbox > 4 * nth;
   auto stage_round = [&] {
     if (deep)
@@ -926,7 +953,7 @@ __global__ void __launch_bounds__(256) k_gather_lane(KArg<R, BATCH> ka, R* __res
   // box loads in flight per thread: 16 for large boxes (10^6 slab, 15^3: the
   // staging is latency-bound, 66.4 -> 64.2 us), 4 for small ones (30k water,
   // 9^3: deeper rounds cost 2 us there)
-  BoxWalk walk(tid, nth, E1, E2);
+  BoxWalk walk(tid, nth, E1, E2, E3, o1, o2, o3, d.M1, d.M2, d.M3);
   const bool deep = nbox > 4 * nth;
   auto stage_round = [&] {
     if (deep)
