@@ -1650,6 +1650,10 @@ DevPlan<R> batch_entry(const esp_batch_t* b, int r) {
   DevPlan<R> d = dev<R>(b->reps[r]);
   d.pofs = b->pofs[r];
   d.rep = r;
+  // the batch's binning launch has blocks enough for the chip from all its
+  // replicas together: every replica takes kBinMaxPpt particles per thread
+  d.binppt = kBinMaxPpt;
+  d.nbin = static_cast<int>((d.n + kBinThreads * kBinMaxPpt - 1) / (kBinThreads * kBinMaxPpt));
   return d;
 }
 
