@@ -624,7 +624,7 @@ def main():
                     help="gather variant when the launch shape is given (--tile or --no-tune)")
     ap.add_argument("--counters-only", action="store_true",
                     help="run only the headline plan (at --tile / --gather) and the near part, for counter passes")
-    ap.add_argument("--workload", default="water30k", choices=["water30k", "membrane1m"],
+    ap.add_argument("--workload", default="water30k", choices=["water30k", "membrane1m", "batch64"],
                     help="workload of the --counters-only run")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-replica batch measurement")
     ap.add_argument("--no-extra", action="store_true", help="skip the ionic and membrane workloads")
@@ -673,6 +673,25 @@ def main():
     if args.counters_only:
         # one plan at a fixed launch shape, so that per-kernel counters are not
         # mixed with the autotuner's trial shapes
+        if args.workload == "batch64":
+            # the 64-replica batch (learned parameters, default tiles), replayed
+            # from its graph
+            from paper_2601_00161_amd.esp import Batch
+            reps = synth.replicas()
+            xb = torch.tensor(np.concatenate([x[1] for x in reps]), dtype=torch.float32, device=dev)
+            qb = torch.tensor(np.concatenate([x[2] for x in reps]), dtype=torch.float32, device=dev)
+            b = Batch([x[0] for x in reps], [len(x[2]) for x in reps], [x[3] for x in reps], graph=True,
+                      params=args.params)
+            f, o = b.forces(xb, qb)
+            for _ in range(args.warmup + args.steps):
+                b.forces(xb, qb, f=f, out7=o)
+            torch.cuda.synchronize()
+            b.check()
+            print(json.dumps({"counters_run": True, "workload": args.workload, "replicas": len(reps),
+                              "particles": int(xb.shape[0]), "launches_per_step": b.num_launches(True),
+                              "steps": args.warmup + args.steps + 1}))
+            b.close()
+            return
         if args.workload == "membrane1m":
             h, r, q = synth.config4(args.seed)
             N = len(q)
